@@ -1,0 +1,92 @@
+/*
+ * lco.h -- plain FP64 CPU oracle of the hybrid lattice-Boltzmann /
+ * finite-difference step for one colloid in a liquid crystal
+ * (Lintuvuori, Marenduzzo, Stratford, Cates, "Colloids in liquid crystals:
+ * a lattice Boltzmann study", Soft Matter 2011).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the definition of "correct"
+ * against which the HIP library is checked.  It shares no code, header,
+ * table or helper with the HIP path.  Only the tests, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.
+ *
+ * Conventions (all FP64, lattice units dx = dt = 1):
+ *   - site index  s = x + nx*(y + ny*z), periodic in all three axes;
+ *   - arrays are structure-of-arrays [component][z][y][x];
+ *   - Q is stored as five components (xx, xy, xz, yy, yz), Qzz = -Qxx-Qyy
+ *     (traceless symmetric, Sec. 2.1);
+ *   - D3Q19 order: 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 = (+1,+1,0),
+ *     (-1,-1,0), (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1), (+1,0,-1),
+ *     (-1,0,+1), (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1): opposite
+ *     directions are adjacent pairs.
+ *   - colloid force layout (12 doubles): F_bbl[3], F_stress[3], T_bbl[3],
+ *     T_stress[3]; momentum exchanged by moving-boundary events is added to
+ *     F_bbl / T_bbl.
+ */
+#ifndef LCO_H
+#define LCO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { LCO_OK = 0, LCO_EINVAL = 1, LCO_ENOMEM = 2, LCO_ESTATE = 5 };
+enum { LCO_ANCHOR_NONE = 0, LCO_ANCHOR_NORMAL = 1, LCO_ANCHOR_PLANAR = 2 };
+enum { LCO_FIXED = 0, LCO_PRESCRIBED = 1 };
+
+typedef struct lco_params {
+  int nx, ny, nz;
+  int hydro;              /* 1: full coupled step; 0: u = 0, dQ/dt = Gamma H */
+  double tau;             /* BGK relaxation time, viscosity (tau - 1/2)/3 */
+  double rho0;            /* reference density (initial fluid, BBL, new fluid) */
+  double A0, gamma, K, q0, xi, Gamma;   /* Eq. (1), Eq. (2), Eq. (4) */
+  double body_force[3];   /* uniform force density on fluid nodes */
+} lco_params;
+
+typedef struct lco_colloid {
+  int present;            /* 0: no colloid in the box */
+  int motion;             /* LCO_FIXED or LCO_PRESCRIBED (R += v every step) */
+  int anchoring;          /* LCO_ANCHOR_NONE / NORMAL / PLANAR (Sec. 2.2) */
+  int pad_;
+  double pos[3];          /* centre R */
+  double a0;              /* nominal radius (Sec. 2.2) */
+  double vel[3];          /* v */
+  double omega[3];        /* angular velocity */
+  double S0;              /* surface order of Eq. for Q^0 (Sec. 2.2) */
+  double W;               /* anchoring strength; +inf = fixed Q^0 */
+} lco_colloid;
+
+typedef struct lco_sim lco_sim;
+
+int  lco_create(const lco_params* p, lco_sim** out);
+void lco_destroy(lco_sim* s);
+int  lco_set_colloid(lco_sim* s, const lco_colloid* c);
+int  lco_get_colloid(const lco_sim* s, lco_colloid* c);
+int  lco_set_Q(lco_sim* s, const double* Q5);      /* 5*N */
+int  lco_set_f(lco_sim* s, const double* f19);     /* 19*N, pre-collision */
+int  lco_set_u(lco_sim* s, const double* u3);      /* 3*N lagged velocity */
+int  lco_get_Q(const lco_sim* s, double* Q5);
+int  lco_get_f(const lco_sim* s, double* f19);
+int  lco_get_u(const lco_sim* s, double* u3);
+int  lco_get_solid(const lco_sim* s, unsigned char* solid);
+int  lco_step(lco_sim* s, int nsteps);
+int  lco_get_force(const lco_sim* s, double out[12]);
+long lco_get_nstep(const lco_sim* s);
+/* F_d, mass, momentum[3], max|u|  (Q ghost values refreshed first) */
+int  lco_get_diag(lco_sim* s, double out[6]);
+
+/* Pieces exposed for the pins (all refresh ghost Q from the current Q). */
+int  lco_fields(lco_sim* s, double* H5, double* P9, double* F3);
+int  lco_ghost(lco_sim* s, double* Q5_out);        /* Q with ghost values */
+void lco_bulk_field(const lco_params* p, const double Q5[5], double H5[5]);
+void lco_corotation(double xi, const double W9[9], const double Q5[5], double S5[5]);
+void lco_feq(double rho, const double u[3], double feq[19]);
+void lco_lattice(int c[19][3], double w[19]);
+int  lco_principal_axis(const double A9[9], double n[3], double* lam);
+/* single-site Beris-Edwards integration under a fixed velocity gradient
+ * W9 (row-major W_ab = d_b u_a), bulk field only; Q5 is updated in place */
+void lco_single_site(const lco_params* p, const double W9[9], long nsteps, double Q5[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
