@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled LB + Q-tensor step on one MI355X.
+
+Default workload: 128^3 FP32 nematic with a colloid of radius 8 dragged at
+constant velocity 1e-3 along x, normal anchoring W = 0.01, seeded noise in Q
+(the drag workload).  A step is one pass of the whole hot path: ghost Q,
+the fused per-site kernel, moving-boundary events and the colloid update.
+
+Prints one JSON line: MLUPS (million lattice-site updates per second) over
+the timed steps, the fused kernel's achieved algorithmic bandwidth against
+the HBM peak, and the FP64 CPU oracle timed on a bounded sample on this
+host's cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled LB+Q MLUPS & HBM GB/s; relax steps warm-start vs plain at equal error"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per lattice update in FP32: f (19) + Q (5) + u (3) values,
+# each read once and written once
+BYTES_PER_LU = {"fp32": 2 * (19 + 5 + 3) * 4, "fp64": 2 * (19 + 5 + 3) * 8}
+
+
+def workload(name):
+    from paper_1102_2193_amd import inputs
+    if name == "drag128_fp32":
+        L = 128
+        return dict(boxes=[dict(nx=L, precision="fp32", **inputs.NEMATIC)],
+                    colloids=[((L / 2,) * 3, 8.0, dict(anchoring="normal", W=0.01, S0=0.5, vel=(1e-3, 0, 0),
+                                                       motion=1))],
+                    Q=[lambda: inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=2)],
+                    config=dict(workload=name, L=L, a=8.0, anchoring="normal", W=0.01, v=[1e-3, 0, 0],
+                                tau=1.0, seed=2), sites=L ** 3, prec="fp32")
+    if name == "cholesteric128_fp32":
+        L, q0 = 128, 2 * math.pi / 32
+        return dict(boxes=[dict(nx=L, precision="fp32", **dict(inputs.NEMATIC, q0=q0))],
+                    colloids=[((L / 2,) * 3, 16.0, dict(anchoring="normal", W=math.inf))],
+                    Q=[lambda: inputs.helix_q(L, L, L, q0, inputs.Q_INIT)],
+                    config=dict(workload=name, L=L, a=16.0, pitch=32), sites=L ** 3, prec="fp32")
+    if name == "nematic256_fp32":
+        L = 256
+        return dict(boxes=[dict(nx=L, precision="fp32", **inputs.NEMATIC)],
+                    colloids=[((L / 2,) * 3, 16.0, dict(anchoring="normal", W=0.01))],
+                    Q=[lambda: inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=2)],
+                    config=dict(workload=name, L=L, a=16.0), sites=L ** 3, prec="fp32")
+    if name == "batch48_fp32":
+        specs = inputs.batch_boxes(4)
+        boxes, cols, Qs = [], [], []
+        for s in specs:
+            L = s["L"]
+            boxes.append(dict(nx=L, precision="fp32", **dict(inputs.NEMATIC, q0=s["q0"])))
+            cols.append(((L / 2,) * 3, s["a"], dict(anchoring="normal", W=math.inf)))
+            Qs.append((lambda L=L, q0=s["q0"]: inputs.helix_q(L, L, L, q0, inputs.Q_INIT)))
+        return dict(boxes=boxes, colloids=cols, Q=Qs, sites=sum(s["L"] ** 3 for s in specs),
+                    config=dict(workload=name, nbox=len(specs), seed=4), prec="fp32")
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(wl, target_s):
+    """FP64 oracle on the first steps of the same workload (box 0)."""
+    from oracle import lco
+    b = dict(wl["boxes"][0])
+    L = b.pop("nx")
+    b.pop("precision")
+    sim = lco.Sim(L, **b)
+    pos, a0, kw = wl["colloids"][0]
+    kw = dict(kw)
+    kw["anchoring"] = {"none": 0, "normal": 1, "planar": 2}[kw["anchoring"]]
+    sim.set_colloid(pos, a0, **kw)
+    sim.set_Q(wl["Q"][0]())
+    t0 = time.perf_counter()
+    sim.step(1)
+    t1 = time.perf_counter()
+    n = 1
+    per = t1 - t0
+    more = max(0, int(target_s / max(per, 1e-6)) - 1)
+    if more:
+        sim.step(more)
+        n += more
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": L ** 3 * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "first %d steps of the %d^3 box in FP64 (%.1f s)" % (n, L, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="drag128_fp32")
+    ap.add_argument("--tile", type=int, default=None, help="fused-kernel tile id (default: tuned)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", type=int, default=0, help="also time graph replay (1)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1102_2193_amd import lc, tune
+
+    wl = workload(args.workload)
+    ctx = lc.Context(wl["boxes"])
+    for b, (pos, a0, kw) in enumerate(wl["colloids"]):
+        ctx.set_colloid(b, pos, a0, **kw)
+    for b, q in enumerate(wl["Q"]):
+        ctx.set_Q(b, q())
+    tile = args.tile if args.tile is not None else tune.best_tile(ctx, wl["config"]["workload"])
+    ctx.set_tile(tile)
+    ctx.use_graph(False)
+    ctx.step(args.warmup)
+    ctx.sync()
+
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(ctx.stream)
+    t0 = time.perf_counter()
+    tk = ctx.time_kernel(args.steps)       # events around every fused-kernel launch
+    stop.record(ctx.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = start.elapsed_time(stop) / args.steps
+    sites = wl["sites"]
+    mlups = sites / (ms_step * 1e-3) / 1e6
+    bpl = BYTES_PER_LU[wl["prec"]]
+    achieved = bpl * sites / (tk["kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if wl["prec"] == "fp32" else "f64", "data": "synthetic",
+        "config": dict(wl["config"], tile=list(ctx.tile_shape(tile)), sites=sites),
+        "hbm_gbps_effective": round(bpl * sites / (ms_step * 1e-3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step (fused)", "kernel_ms": round(tk["kernel_ms"], 5),
+                     "bytes_per_launch": bpl * sites},
+        "wall_s": round(wall, 3),
+    }
+    if args.graph:
+        ctx.use_graph(True)
+        ctx.step(64)
+        ctx.sync()
+        start.record(ctx.stream)
+        ctx.step(args.steps)
+        stop.record(ctx.stream)
+        torch.cuda.synchronize()
+        out["ms_per_step_graph"] = round(start.elapsed_time(stop) / args.steps, 5)
+    ctx.sync()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,765 @@
+// lc_kernels.hip -- gfx950 kernels of the hybrid LB/FD step.
+//
+//   k_ghost     anchoring: Q at boundary solid nodes (Sec. 2.2, Q^0)
+//   k_step      fused per-site pass: H and P from an LDS-staged Q halo,
+//               force = discrete divergence of P over control-volume faces,
+//               Beris-Edwards update of Q, BGK collision with Guo forcing,
+//               push streaming with bounce-back on links, colloid force and
+//               torque partial sums (Sec. 2.1-2.2)
+//   k_events    moving-boundary events of a colloid with prescribed motion
+//   k_finalize  fixed-order sum of the partials, force history, R += v
+//   k_diag      free energy, mass, momentum, max|u| partials
+//   k_defects   (3/2) lambda_max(Q) below a threshold
+//
+// Populations are stored shifted, f~ = f - w_i, which keeps FP32 rounding
+// relative to the small deviations from rest.  Every array is
+// structure-of-arrays [component][site] over the concatenation of all boxes.
+#include "lc_kernels.hpp"
+
+namespace lc {
+
+template <typename R>
+__device__ inline R wave_sum(R v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Reduce n doubles per thread over the block into out[0..n) (thread 0).
+template <int NT, int NV>
+__device__ inline void block_sum(double (&v)[NV], double* sred, double* out) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    double s = wave_sum(v[k]);
+    if (lane == 0) sred[w * NV + k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int i = 0; i < NW; i++) s += sred[i * NV + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------
+// fused step
+// ---------------------------------------------------------------------
+template <typename R, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX* TY* TZ)
+    k_step(const BoxDev* __restrict__ boxes, const int2* __restrict__ tiles, StepPtrs<R> a) {
+  constexpr int NT = TX * TY * TZ;
+  constexpr int QX = TX + 4, QY = TY + 4, QZ = TZ + 4, QN = QX * QY * QZ;
+  constexpr int PX = TX + 2, PY = TY + 2, PZ = TZ + 2, PN = PX * PY * PZ;
+  constexpr int NF = 2 * (TX * TY + TY * TZ + TX * TZ);
+  constexpr int QSY = QX, QSZ = QX * QY;     // strides in the Q box
+  constexpr int PSY = PX, PSZ = PX * PY;     // strides in the P box
+
+  __shared__ R sQ[5 * QN];
+  __shared__ R sP[9 * PN];
+  __shared__ R sH[5 * NT];
+  __shared__ R sU[3 * PN];
+  __shared__ unsigned char sS[QN];
+  __shared__ double sred[(NT / 64) * 12];
+
+  const int2 tt = tiles[blockIdx.x];
+  if (tt.x < 0) return;  // padding entry (whole block)
+  const BoxDev& B = boxes[tt.x];
+  const int nx = B.nx, ny = B.ny, nz = B.nz, hydro = B.hydro;
+  const int tix = tt.y % B.ntx, tiy = (tt.y / B.ntx) % B.nty, tiz = tt.y / (B.ntx * B.nty);
+  const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
+  const long long off = B.off;
+  const long long NS = a.nsites;
+  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, TZ + 4);
+  const Mat<R> mp(B);
+  const int tid = threadIdx.x;
+
+  // Phase 1: Q with a halo of two nodes, solid flags.
+  for (int s = tid; s < QN; s += NT) {
+    const int lx = s % QX, ly = (s / QX) % QY, lz = s / QSZ;
+    const int gx = wrapc(x0 - 2 + lx, nx), gy = wrapc(y0 - 2 + ly, ny), gz = wrapc(z0 - 2 + lz, nz);
+    const long long g = off + gx + (long long)nx * (gy + (long long)ny * gz);
+#pragma unroll
+    for (int c = 0; c < 5; c++) sQ[c * QN + s] = a.Qin[c * NS + g];
+    sS[s] = near ? (unsigned char)inside(B, Rc, gx, gy, gz) : (unsigned char)0;
+  }
+  __syncthreads();
+
+  // Phase 2: H and P at the tile and its face halo (plus-shaped region);
+  // velocity of the last collision with a halo of one (rigid-body motion at
+  // solid nodes).
+  for (int p = tid; p < NT + NF; p += NT) {
+    int px, py, pz;
+    if (p < NT) {
+      px = p % TX + 1; py = (p / TX) % TY + 1; pz = p / (TX * TY) + 1;
+    } else {
+      int h = p - NT;
+      if (h < 2 * TX * TY) {
+        const int r = h % (TX * TY);
+        px = r % TX + 1; py = r / TX + 1; pz = h < TX * TY ? 0 : PZ - 1;
+      } else if ((h -= 2 * TX * TY) < 2 * TY * TZ) {
+        const int r = h % (TY * TZ);
+        py = r % TY + 1; pz = r / TY + 1; px = h < TY * TZ ? 0 : PX - 1;
+      } else {
+        h -= 2 * TY * TZ;
+        const int r = h % (TX * TZ);
+        px = r % TX + 1; pz = r / TX + 1; py = h < TX * TZ ? 0 : PY - 1;
+      }
+    }
+    const int qc = (pz + 1) * QSZ + (py + 1) * QSY + (px + 1);
+    if (sS[qc]) continue;
+    R c5[5], xp[5], xm[5], yp[5], ym[5], zp[5], zm[5], H5[5], P9[9];
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      const R* q = sQ + c * QN + qc;
+      c5[c] = q[0]; xp[c] = q[1]; xm[c] = q[-1]; yp[c] = q[QSY]; ym[c] = q[-QSY];
+      zp[c] = q[QSZ]; zm[c] = q[-QSZ];
+    }
+    if (hydro) {
+      field_and_stress<R, true>(mp, c5, xp, xm, yp, ym, zp, zm, H5, P9);
+      const int pc = pz * PSZ + py * PSY + px;
+#pragma unroll
+      for (int k = 0; k < 9; k++) sP[k * PN + pc] = P9[k];
+    } else {
+      field_and_stress<R, false>(mp, c5, xp, xm, yp, ym, zp, zm, H5, P9);
+    }
+    if (p < NT) {
+#pragma unroll
+      for (int c = 0; c < 5; c++) sH[c * NT + p] = H5[c];
+    }
+  }
+  if (hydro) {
+    for (int s = tid; s < PN; s += NT) {
+      const int lx = s % PX, ly = (s / PX) % PY, lz = s / PSZ;
+      const int gx = wrapc(x0 - 1 + lx, nx), gy = wrapc(y0 - 1 + ly, ny), gz = wrapc(z0 - 1 + lz, nz);
+      const int qs = (lz + 1) * QSZ + (ly + 1) * QSY + (lx + 1);
+      if (sS[qs]) {
+        double r[3], ub[3];
+        rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
+        rigid_vel(B, r, ub);
+#pragma unroll
+        for (int c = 0; c < 3; c++) sU[c * PN + s] = (R)ub[c];
+      } else {
+        const long long g = off + gx + (long long)nx * (gy + (long long)ny * gz);
+#pragma unroll
+        for (int c = 0; c < 3; c++) sU[c * PN + s] = a.uin[c * NS + g];
+      }
+    }
+  }
+  __syncthreads();
+
+  // Phase 3: own node.
+  const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+  const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+  const int qc = (lz + 2) * QSZ + (ly + 2) * QSY + (lx + 2);
+  const int pc = (lz + 1) * PSZ + (ly + 1) * PSY + (lx + 1);
+  const bool active = gx < nx && gy < ny && gz < nz && !sS[qc];
+  double part[12];
+#pragma unroll
+  for (int k = 0; k < 12; k++) part[k] = 0.0;
+
+  if (active) {
+    const long long g = off + gx + (long long)nx * (gy + (long long)ny * gz);
+    const int qst[3] = {1, QSY, QSZ}, pst[3] = {1, PSY, PSZ};
+    R q5[5], dQ[5];
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      q5[c] = sQ[c * QN + qc];
+      dQ[c] = mp.Gamma * sH[c * NT + tid];
+    }
+    R F[3] = {(R)0, (R)0, (R)0};
+    if (hydro) {
+      // force on the fluid: differences of P between opposite faces
+      R Pc[9];
+#pragma unroll
+      for (int k = 0; k < 9; k++) Pc[k] = sP[k * PN + pc];
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        const bool sp = sS[qc + qst[b]], sm = sS[qc - qst[b]];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          const R pcv = Pc[3 * c + b];
+          const R pp = sp ? pcv : (R)0.5 * (pcv + sP[(3 * c + b) * PN + pc + pst[b]]);
+          const R pm = sm ? pcv : (R)0.5 * (pcv + sP[(3 * c + b) * PN + pc - pst[b]]);
+          F[c] += pp - pm;
+        }
+        // colloid force and torque from the solid-fluid faces
+        if (sp || sm) {
+#pragma unroll
+          for (int sg = 1; sg >= -1; sg -= 2) {
+            if (sg > 0 ? !sp : !sm) continue;
+            double ps[3], r[3];
+            for (int c = 0; c < 3; c++) ps[c] = -(double)sg * (double)Pc[3 * c + b];
+            const double e[3] = {b == 0 ? 0.5 * sg : 0.0, b == 1 ? 0.5 * sg : 0.0, b == 2 ? 0.5 * sg : 0.0};
+            rel_pos(B, Rc, gx + e[0], gy + e[1], gz + e[2], r);
+            part[3] += ps[0]; part[4] += ps[1]; part[5] += ps[2];
+            part[9] += r[1] * ps[2] - r[2] * ps[1];
+            part[10] += r[2] * ps[0] - r[0] * ps[2];
+            part[11] += r[0] * ps[1] - r[1] * ps[0];
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; c++) F[c] += (R)B.body[c];
+
+      // Beris-Edwards: velocity gradient, upwind advective fluxes with zero
+      // flux through solid faces, co-rotation
+      R u0[3], W[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; c++) u0[c] = sU[c * PN + pc];
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        R up[3], um[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          up[c] = sU[c * PN + pc + pst[b]];
+          um[c] = sU[c * PN + pc - pst[b]];
+          W[c][b] = (R)0.5 * (up[c] - um[c]);
+        }
+        R phip[5], phim[5];
+        if (!sS[qc + qst[b]]) {
+          const R uf = (R)0.5 * (u0[b] + up[b]);
+#pragma unroll
+          for (int c = 0; c < 5; c++) phip[c] = uf * (uf >= (R)0 ? q5[c] : sQ[c * QN + qc + qst[b]]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 5; c++) phip[c] = (R)0;
+        }
+        if (!sS[qc - qst[b]]) {
+          const R uf = (R)0.5 * (um[b] + u0[b]);
+#pragma unroll
+          for (int c = 0; c < 5; c++) phim[c] = uf * (uf >= (R)0 ? sQ[c * QN + qc - qst[b]] : q5[c]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 5; c++) phim[c] = (R)0;
+        }
+#pragma unroll
+        for (int c = 0; c < 5; c++) dQ[c] -= phip[c] - phim[c];
+      }
+      R S5[5];
+      corotation<R>(mp.xi, W, q5, S5);
+#pragma unroll
+      for (int c = 0; c < 5; c++) dQ[c] += S5[c];
+    }
+    R qn2 = (R)0;
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      const R v = q5[c] + dQ[c];
+      a.Qout[c * NS + g] = v;
+      qn2 += v * v;
+    }
+    bool bad = !(qn2 < (R)100);
+
+    if (hydro) {
+      // LB collision (BGK, Guo forcing with the half-force velocity)
+      R f[19];
+#pragma unroll
+      for (int i = 0; i < 19; i++) f[i] = a.fin[i * NS + g];
+      R rm1 = (R)0, j[3] = {(R)0, (R)0, (R)0};
+#pragma unroll
+      for (int i = 0; i < 19; i++) {
+        rm1 += f[i];
+        if (cx(i)) j[0] += cx(i) > 0 ? f[i] : -f[i];
+        if (cy(i)) j[1] += cy(i) > 0 ? f[i] : -f[i];
+        if (cz(i)) j[2] += cz(i) > 0 ? f[i] : -f[i];
+      }
+      const R rho = (R)1 + rm1;
+      R u[3];
+#pragma unroll
+      for (int c = 0; c < 3; c++) u[c] = (j[c] + (R)0.5 * F[c]) / rho;
+      const R usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+      const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+      const R itau = (R)1 / mp.tau, fsrc = (R)1 - (R)0.5 * itau;
+      bad = bad || !(usq < (R)0.09);
+      // neighbour indices for push streaming
+      const int gxp = gx + 1 == nx ? 0 : gx + 1, gxm = gx == 0 ? nx - 1 : gx - 1;
+      const int gyp = gy + 1 == ny ? 0 : gy + 1, gym = gy == 0 ? ny - 1 : gy - 1;
+      const int gzp = gz + 1 == nz ? 0 : gz + 1, gzm = gz == 0 ? nz - 1 : gz - 1;
+      const int xs[3] = {gxm, gx, gxp}, ys[3] = {gym, gy, gyp}, zs[3] = {gzm, gz, gzp};
+#pragma unroll
+      for (int i = 0; i < 19; i++) {
+        const R w = (R)wgt(i);
+        const R cu = (R)cx(i) * u[0] + (R)cy(i) * u[1] + (R)cz(i) * u[2];
+        const R cF = (R)cx(i) * F[0] + (R)cy(i) * F[1] + (R)cz(i) * F[2];
+        const R feq = w * rm1 + w * rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * usq);
+        const R src = w * ((R)3 * (cF - uF) + (R)9 * cu * cF);
+        const R fs = f[i] - (f[i] - feq) * itau + fsrc * src;
+        const int qn = qc + cx(i) + cz(i) * QSZ + cy(i) * QSY;
+        if (!sS[qn]) {
+          const long long gn = off + xs[cx(i) + 1] +
+                               (long long)nx * (ys[cy(i) + 1] + (long long)ny * zs[cz(i) + 1]);
+          a.fout[i * NS + gn] = fs;
+        } else {
+          // bounce-back on the link with the moving-wall correction
+          double r[3], ub[3];
+          rel_pos(B, Rc, gx + 0.5 * cx(i), gy + 0.5 * cy(i), gz + 0.5 * cz(i), r);
+          rigid_vel(B, r, ub);
+          const double cub = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
+          const double corr = 6.0 * wgt(i) * B.rho0 * cub;
+          a.fout[opp(i) * NS + g] = (R)((double)fs - corr);
+          const double m = 2.0 * ((double)fs + wgt(i)) - corr;
+          const double dp[3] = {m * cx(i), m * cy(i), m * cz(i)};
+          part[0] += dp[0]; part[1] += dp[1]; part[2] += dp[2];
+          part[6] += r[1] * dp[2] - r[2] * dp[1];
+          part[7] += r[2] * dp[0] - r[0] * dp[2];
+          part[8] += r[0] * dp[1] - r[1] * dp[0];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; c++) a.uout[c * NS + g] = u[c];
+    }
+    if (bad) atomicOr(a.flag, 1);
+  }
+
+  if (near) {
+    double red[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) red[k] = part[k];
+    block_sum<NT, 12>(red, sred, a.part + 12LL * (B.tile_base + tt.y));
+  }
+}
+
+// ---------------------------------------------------------------------
+// ghost Q at boundary solid nodes
+// ---------------------------------------------------------------------
+__device__ inline int find_box(const BoxDev* boxes, int nbox, long long t, int which) {
+  int b = 0;
+  for (int k = 1; k < nbox; k++) {
+    const int base = which == 0 ? boxes[k].ghost_base : boxes[k].event_base;
+    if (t >= base) b = k;
+  }
+  return b;
+}
+
+template <typename R>
+__device__ inline void load_full(const R* Q, long long NS, long long g, double q[3][3]) {
+  const double xx = Q[g], xy = Q[NS + g], xz = Q[2 * NS + g], yy = Q[3 * NS + g], yz = Q[4 * NS + g];
+  q[0][0] = xx; q[0][1] = xy; q[0][2] = xz;
+  q[1][0] = xy; q[1][1] = yy; q[1][2] = yz;
+  q[2][0] = xz; q[2][1] = yz; q[2][2] = -xx - yy;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_ghost(const BoxDev* __restrict__ boxes, int nbox, long long total, R* __restrict__ Q, long long NS) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int b = find_box(boxes, nbox, t, 0);
+  const BoxDev& B = boxes[b];
+  if (!B.present) return;
+  const int E = B.ghost_ext;
+  const long long l = t - B.ghost_base;
+  if (l >= (long long)E * E * E) return;
+  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  const int h = (E - 1) / 2;
+  const int x = wrapc((int)floor(Rc[0]) - h + (int)(l % E), B.nx);
+  const int y = wrapc((int)floor(Rc[1]) - h + (int)((l / E) % E), B.ny);
+  const int z = wrapc((int)floor(Rc[2]) - h + (int)(l / ((long long)E * E)), B.nz);
+  if (!inside(B, Rc, x, y, z)) return;
+  const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+  double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  int nf = 0;
+  for (int k = 0; k < 6; k++) {
+    const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
+    if (inside(B, Rc, xn, yn, zn)) continue;
+    double q[3][3];
+    load_full(Q, NS, B.off + xn + (long long)B.nx * (yn + (long long)B.ny * zn), q);
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) qbar[i][j] += q[i][j];
+    nf++;
+  }
+  if (nf == 0) return;  // interior solid node
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) qbar[i][j] /= nf;
+  double qs[3][3];
+  if (B.anchoring == 0) {
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) qs[i][j] = qbar[i][j];
+  } else {
+    double q0[3][3];
+    anchor_target(B, Rc, x, y, z, qbar, q0);
+    const bool fixed = isinf(B.W);
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++)
+        qs[i][j] = fixed ? q0[i][j] : (B.K * qbar[i][j] + B.W * q0[i][j]) / (B.K + B.W);
+  }
+  const long long g = B.off + x + (long long)B.nx * (y + (long long)B.ny * z);
+  Q[g] = (R)qs[0][0]; Q[NS + g] = (R)qs[0][1]; Q[2 * NS + g] = (R)qs[0][2];
+  Q[3 * NS + g] = (R)qs[1][1]; Q[4 * NS + g] = (R)qs[1][2];
+}
+
+// ---------------------------------------------------------------------
+// moving-boundary events (prescribed motion)
+// ---------------------------------------------------------------------
+__device__ inline void advanced_pos(const BoxDev& B, double Rn[3]) {
+  const int L[3] = {B.nx, B.ny, B.nz};
+  for (int c = 0; c < 3; c++) {
+    double r = __dadd_rn(B.pos[c], B.vel[c]);
+    if (r >= L[c]) r = __dsub_rn(r, (double)L[c]);
+    if (r < 0.0) r = __dadd_rn(r, (double)L[c]);
+    Rn[c] = r;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_events(const BoxDev* __restrict__ boxes, int nbox, long long total, StepPtrs<R> a, double* epart) {
+  __shared__ double sred[4 * 6];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  // every box's range is padded to whole blocks, so a block has one box
+  const int b = find_box(boxes, nbox, (long long)blockIdx.x * blockDim.x, 1);
+  const BoxDev& B = boxes[b];
+  const long long NS = a.nsites;
+  const long long l = t - B.event_base;
+  const int E = B.event_ext;
+  if (B.present && B.motion == 1 && t < total && l < (long long)E * E * E) {
+    const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+    double Rn[3];
+    advanced_pos(B, Rn);
+    const int h = (E - 1) / 2;
+    const int x = wrapc((int)floor(Rc[0]) - h + (int)(l % E), B.nx);
+    const int y = wrapc((int)floor(Rc[1]) - h + (int)((l / E) % E), B.ny);
+    const int z = wrapc((int)floor(Rc[2]) - h + (int)(l / ((long long)E * E)), B.nz);
+    const bool was = inside(B, Rc, x, y, z), now = inside(B, Rn, x, y, z);
+    if (was != now) {
+      const long long g = B.off + x + (long long)B.nx * (y + (long long)B.ny * z);
+      double r[3], p[3] = {0, 0, 0};
+      rel_pos(B, Rn, (double)x, (double)y, (double)z, r);
+      if (was) {
+        // newly exposed node: fluid at rest in the wall frame, Q from the
+        // face neighbours that are fluid before and after the move
+        double ub[3];
+        rigid_vel(B, r, ub);
+        if (B.hydro) {
+          const double usq = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+#pragma unroll
+          for (int i = 0; i < 19; i++) {
+            const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
+            const double feq = wgt(i) * B.rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+            a.fout[i * NS + g] = (R)(feq - wgt(i));
+            p[0] -= feq * cx(i); p[1] -= feq * cy(i); p[2] -= feq * cz(i);
+          }
+          for (int c = 0; c < 3; c++) a.uout[c * NS + g] = (R)ub[c];
+        }
+        const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+        double qm[5] = {0, 0, 0, 0, 0};
+        int nf = 0;
+        for (int k = 0; k < 6; k++) {
+          const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
+          if (inside(B, Rc, xn, yn, zn) || inside(B, Rn, xn, yn, zn)) continue;
+          const long long gn = B.off + xn + (long long)B.nx * (yn + (long long)B.ny * zn);
+          for (int c = 0; c < 5; c++) qm[c] += (double)a.Qout[c * NS + gn];
+          nf++;
+        }
+        for (int c = 0; c < 5; c++) a.Qout[c * NS + g] = (R)(nf ? qm[c] / nf : 0.0);
+      } else if (B.hydro) {
+        // newly covered node: its fluid momentum goes to the colloid
+#pragma unroll
+        for (int i = 0; i < 19; i++) {
+          const double fi = (double)a.fout[i * NS + g] + wgt(i);
+          p[0] += fi * cx(i); p[1] += fi * cy(i); p[2] += fi * cz(i);
+        }
+      }
+      v[0] = p[0]; v[1] = p[1]; v[2] = p[2];
+      v[3] = r[1] * p[2] - r[2] * p[1];
+      v[4] = r[2] * p[0] - r[0] * p[2];
+      v[5] = r[0] * p[1] - r[1] * p[0];
+    }
+  }
+  block_sum<256, 6>(v, sred, epart + 6LL * blockIdx.x);
+}
+
+// ---------------------------------------------------------------------
+// finalize: fixed-order sums, force history, colloid position
+// ---------------------------------------------------------------------
+template <int TX, int TY, int TZ>
+__global__ void __launch_bounds__(256)
+    k_finalize(BoxDev* __restrict__ boxes, const double* __restrict__ part, const double* __restrict__ epart,
+               double* __restrict__ force, double* __restrict__ hist, int cap, long long* __restrict__ count) {
+  __shared__ double sred[4 * 12];
+  __shared__ double sres[12];
+  const int b = blockIdx.x;
+  BoxDev& B = boxes[b];
+  double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  if (B.present) {
+    const int nt = B.ntx * B.nty * B.ntz;
+    for (int k = threadIdx.x; k < nt; k += 256) {
+      const int tix = k % B.ntx, tiy = (k / B.ntx) % B.nty, tiz = k / (B.ntx * B.nty);
+      if (!block_near(B, Rc, tix * TX - 2, tiy * TY - 2, tiz * TZ - 2, TX + 4, TY + 4, TZ + 4)) continue;
+      const double* p = part + 12LL * (B.tile_base + k);
+      for (int c = 0; c < 12; c++) v[c] += p[c];
+    }
+    if (B.motion == 1) {
+      for (int k = threadIdx.x; k < B.event_nblk; k += 256) {
+        const double* p = epart + 6LL * (B.event_blk0 + k);
+        v[0] += p[0]; v[1] += p[1]; v[2] += p[2];
+        v[6] += p[3]; v[7] += p[4]; v[8] += p[5];
+      }
+    }
+  }
+  block_sum<256, 12>(v, sred, sres);
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    const double val = B.present ? sres[threadIdx.x] : 0.0;
+    const long long n = count[b];
+    force[12 * b + threadIdx.x] = val;
+    hist[((long long)b * cap + (n % cap)) * 12 + threadIdx.x] = val;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (B.present && B.motion == 1) {
+      double Rn[3];
+      advanced_pos(B, Rn);
+      B.pos[0] = Rn[0]; B.pos[1] = Rn[1]; B.pos[2] = Rn[2];
+    }
+    count[b] += 1;
+  }
+}
+
+// ---------------------------------------------------------------------
+// diagnostics and defects (off the time loop)
+// ---------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_diag(const BoxDev* __restrict__ boxes, int box, StepPtrs<R> a, double* out) {
+  __shared__ double sred[4 * 6];
+  const BoxDev& B = boxes[box];
+  const long long NS = a.nsites;
+  const long long nsite = (long long)B.nx * B.ny * B.nz;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  if (t < nsite) {
+    const int x = (int)(t % B.nx), y = (int)((t / B.nx) % B.ny), z = (int)(t / ((long long)B.nx * B.ny));
+    const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+    auto solid = [&](int xx, int yy, int zz) {
+      return B.present && inside(B, Rc, wrapc(xx, B.nx), wrapc(yy, B.ny), wrapc(zz, B.nz));
+    };
+    auto gidx = [&](int xx, int yy, int zz) {
+      return B.off + wrapc(xx, B.nx) + (long long)B.nx * (wrapc(yy, B.ny) + (long long)B.ny * wrapc(zz, B.nz));
+    };
+    const bool sx = solid(x, y, z);
+    const long long g = gidx(x, y, z);
+    double q[3][3];
+    load_full(a.Qin, NS, g, q);
+    const double A0 = B.A0, gm = B.gamma, K = B.K, q0 = B.q0;
+    if (!sx) {
+      double d[3][3][3];
+      const int e[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+      for (int c = 0; c < 3; c++) {
+        double qp[3][3], qm[3][3];
+        load_full(a.Qin, NS, gidx(x + e[c][0], y + e[c][1], z + e[c][2]), qp);
+        load_full(a.Qin, NS, gidx(x - e[c][0], y - e[c][1], z - e[c][2]), qm);
+        for (int i = 0; i < 3; i++)
+          for (int j = 0; j < 3; j++) d[c][i][j] = 0.5 * (qp[i][j] - qm[i][j]);
+      }
+      double tr2 = 0, tr3 = 0, chi = 0;
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+          tr2 += q[i][j] * q[i][j];
+          for (int k = 0; k < 3; k++) tr3 += q[i][j] * q[j][k] * q[k][i];
+        }
+      for (int b = 0; b < 3; b++) {
+        chi += q[0][b] * (d[1][2][b] - d[2][1][b]) + q[1][b] * (d[2][0][b] - d[0][2][b]) +
+               q[2][b] * (d[0][1][b] - d[1][0][b]);
+      }
+      v[0] += 0.5 * A0 * (1.0 - gm / 3.0) * tr2 - A0 * gm / 3.0 * tr3 + 0.25 * A0 * gm * tr2 * tr2 +
+              2.0 * K * q0 * chi + 2.0 * K * q0 * q0 * tr2;
+      if (B.hydro) {
+        for (int i = 0; i < 19; i++) {
+          const double fi = (double)a.fin[i * NS + g] + wgt(i);
+          v[1] += fi;
+          v[2] += fi * cx(i); v[3] += fi * cy(i); v[4] += fi * cz(i);
+        }
+        double u2 = 0;
+        for (int c = 0; c < 3; c++) u2 += (double)a.uin[c * NS + g] * (double)a.uin[c * NS + g];
+        v[5] = sqrt(u2);
+      }
+    }
+    const bool finiteW = B.present && B.anchoring != 0 && !isinf(B.W);
+    for (int c = 0; c < 3; c++) {
+      const int xn = x + (c == 0), yn = y + (c == 1), zn = z + (c == 2);
+      const bool sn = solid(xn, yn, zn);
+      if (sx && sn) continue;
+      double qn[3][3], dd = 0;
+      load_full(a.Qin, NS, gidx(xn, yn, zn), qn);
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) dd += (qn[i][j] - q[i][j]) * (qn[i][j] - q[i][j]);
+      v[0] += 0.5 * K * dd;
+      if (finiteW && sx != sn) {
+        // W/2 |Qs - Q^0|^2 at the solid end of the face
+        const int xs = sx ? x : xn, ys = sx ? y : yn, zs = sx ? z : zn;
+        const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+        double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, qs[3][3], qz[3][3];
+        int nf = 0;
+        for (int k = 0; k < 6; k++) {
+          if (solid(xs + nb[k][0], ys + nb[k][1], zs + nb[k][2])) continue;
+          double qq[3][3];
+          load_full(a.Qin, NS, gidx(xs + nb[k][0], ys + nb[k][1], zs + nb[k][2]), qq);
+          for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) qbar[i][j] += qq[i][j];
+          nf++;
+        }
+        for (int i = 0; i < 3; i++)
+          for (int j = 0; j < 3; j++) qbar[i][j] /= nf;
+        anchor_target(B, Rc, wrapc(xs, B.nx), wrapc(ys, B.ny), wrapc(zs, B.nz), qbar, qz);
+        load_full(a.Qin, NS, gidx(xs, ys, zs), qs);
+        double w2 = 0;
+        for (int i = 0; i < 3; i++)
+          for (int j = 0; j < 3; j++) w2 += (qs[i][j] - qz[i][j]) * (qs[i][j] - qz[i][j]);
+        v[0] += 0.5 * B.W * w2;
+      }
+    }
+  }
+  // max|u| is reduced as a max, the rest as sums
+  __shared__ double smax[4];
+  double m = v[5];
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+  if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = m;
+  v[5] = 0.0;
+  block_sum<256, 6>(v, sred, out + 6LL * blockIdx.x);
+  __syncthreads();
+  if (threadIdx.x == 0) out[6LL * blockIdx.x + 5] = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
+}
+
+// Largest eigenvalue of a symmetric traceless 3x3 matrix (trigonometric
+// solution of the characteristic cubic).
+__device__ inline double lambda_max(const double q[3][3]) {
+  const double p2 = q[0][1] * q[0][1] + q[0][2] * q[0][2] + q[1][2] * q[1][2];
+  const double p1 = q[0][0] * q[0][0] + q[1][1] * q[1][1] + q[2][2] * q[2][2] + 2.0 * p2;
+  const double p = sqrt(p1 / 6.0);
+  if (p < 1e-300) return 0.0;
+  double bm[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) bm[i][j] = q[i][j] / p;
+  double det = bm[0][0] * (bm[1][1] * bm[2][2] - bm[1][2] * bm[2][1]) -
+               bm[0][1] * (bm[1][0] * bm[2][2] - bm[1][2] * bm[2][0]) +
+               bm[0][2] * (bm[1][0] * bm[2][1] - bm[1][1] * bm[2][0]);
+  double r = 0.5 * det;
+  r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+  return 2.0 * p * cos(acos(r) / 3.0);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_defects(const BoxDev* __restrict__ boxes, int box, const R* __restrict__ Q, long long NS, double thr,
+              unsigned char* __restrict__ mask, unsigned long long* __restrict__ count) {
+  const BoxDev& B = boxes[box];
+  const long long nsite = (long long)B.nx * B.ny * B.nz;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsite) return;
+  const int x = (int)(t % B.nx), y = (int)((t / B.nx) % B.ny), z = (int)(t / ((long long)B.nx * B.ny));
+  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  unsigned char m = 0;
+  if (!(B.present && inside(B, Rc, x, y, z))) {
+    double q[3][3];
+    load_full(Q, NS, B.off + t, q);
+    m = 1.5 * lambda_max(q) < thr;
+  }
+  mask[t] = m;
+  if (m) atomicAdd(count, 1ULL);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_fill_f(R* f, long long NS, const double* rho0_site_unused, double rho0) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NS) return;
+#pragma unroll
+  for (int i = 0; i < 19; i++) f[i * NS + t] = (R)(wgt(i) * rho0 - wgt(i));
+}
+
+// ---------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------
+template <typename R>
+hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const StepPtrs<R>& a,
+                       hipStream_t s) {
+#define LC_TILE_CASE(ID, X, Y, Z) \
+  case ID: k_step<R, X, Y, Z><<<nblk, X * Y * Z, 0, s>>>(boxes, tiles, a); break;
+  if constexpr (sizeof(R) == 4) {
+    switch (tile) {
+      LC_TILES_F32(LC_TILE_CASE)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (tile) {
+      LC_TILES_F64(LC_TILE_CASE)
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef LC_TILE_CASE
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_finalize(int tile, int nbox, BoxDev* boxes, const double* part, const double* epart,
+                           double* force, double* hist, int cap, long long* count, hipStream_t s) {
+#define LC_TILE_CASE(ID, X, Y, Z) \
+  case ID: k_finalize<X, Y, Z><<<nbox, 256, 0, s>>>(boxes, part, epart, force, hist, cap, count); break;
+  if constexpr (sizeof(R) == 4) {
+    switch (tile) {
+      LC_TILES_F32(LC_TILE_CASE)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (tile) {
+      LC_TILES_F64(LC_TILE_CASE)
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef LC_TILE_CASE
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  k_ghost<R><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(boxes, nbox, total, Q, NS);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_events(const BoxDev* boxes, int nbox, long long total, const StepPtrs<R>& a, double* epart,
+                         hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  k_events<R><<<(unsigned)(total / 256), 256, 0, s>>>(boxes, nbox, total, a, epart);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const StepPtrs<R>& a, double* out,
+                       hipStream_t s) {
+  k_diag<R><<<(unsigned)((nsite + 255) / 256), 256, 0, s>>>(boxes, box, a, out);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_defects(const BoxDev* boxes, int box, long long nsite, const R* Q, long long NS, double thr,
+                          unsigned char* mask, unsigned long long* count, hipStream_t s) {
+  k_defects<R><<<(unsigned)((nsite + 255) / 256), 256, 0, s>>>(boxes, box, Q, NS, thr, mask, count);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
+  k_fill_f<R><<<(unsigned)((NS + 255) / 256), 256, 0, s>>>(f, NS, nullptr, rho0);
+  return hipGetLastError();
+}
+
+#define LC_INST(R)                                                                                        \
+  template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const StepPtrs<R>&, hipStream_t); \
+  template hipError_t launch_finalize<R>(int, int, BoxDev*, const double*, const double*, double*, double*,  \
+                                         int, long long*, hipStream_t);                                     \
+  template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, hipStream_t);           \
+  template hipError_t launch_events<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*,          \
+                                       hipStream_t);                                                        \
+  template hipError_t launch_diag<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*, hipStream_t); \
+  template hipError_t launch_defects<R>(const BoxDev*, int, long long, const R*, long long, double,         \
+                                        unsigned char*, unsigned long long*, hipStream_t);                  \
+  template hipError_t launch_fill<R>(R*, long long, double, hipStream_t);
+LC_INST(float)
+LC_INST(double)
+
+}  // namespace lc

@@ -1,0 +1,58 @@
+// lc_kernels.hpp -- launch interface between the runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lc_dev.hpp"
+
+namespace lc {
+
+// Device pointers of one step: inputs at time n, outputs at n+1.
+template <typename R>
+struct StepPtrs {
+  const R* fin;
+  R* fout;
+  const R* Qin;
+  R* Qout;
+  const R* uin;
+  R* uout;
+  long long nsites;   // component stride (all boxes)
+  double* part;       // per-tile colloid partial sums, 12 doubles
+  int* flag;          // set to 1 on a non-finite value or |u| >= 0.3
+};
+
+// Block shapes (TX, TY, TZ) of the fused kernel, per precision.
+#define LC_TILES_F32(X)  \
+  X(0, 8, 8, 4)          \
+  X(1, 16, 8, 2)         \
+  X(2, 16, 4, 4)         \
+  X(3, 32, 4, 2)         \
+  X(4, 8, 4, 4)          \
+  X(5, 16, 8, 4)         \
+  X(6, 8, 8, 8)
+#define LC_TILES_F64(X)  \
+  X(0, 8, 4, 4)          \
+  X(1, 8, 8, 4)          \
+  X(2, 16, 4, 2)
+
+template <typename R>
+hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const StepPtrs<R>& a,
+                       hipStream_t s);
+template <typename R>
+hipError_t launch_finalize(int tile, int nbox, BoxDev* boxes, const double* part, const double* epart,
+                           double* force, double* hist, int cap, long long* count, hipStream_t s);
+template <typename R>
+hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, hipStream_t s);
+template <typename R>
+hipError_t launch_events(const BoxDev* boxes, int nbox, long long total, const StepPtrs<R>& a, double* epart,
+                         hipStream_t s);
+template <typename R>
+hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const StepPtrs<R>& a, double* out,
+                       hipStream_t s);
+template <typename R>
+hipError_t launch_defects(const BoxDev* boxes, int box, long long nsite, const R* Q, long long NS, double thr,
+                          unsigned char* mask, unsigned long long* count, hipStream_t s);
+template <typename R>
+hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s);
+
+}  // namespace lc

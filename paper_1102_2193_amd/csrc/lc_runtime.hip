@@ -1,0 +1,743 @@
+// lc_runtime.hip -- host runtime behind the C ABI of include/lc.h: box
+// layout, tile work lists, the per-step launch sequence, HIP graph capture
+// of repeated steps, transfers and diagnostics.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lc.h"
+#include "lc_kernels.hpp"
+
+using lc::BoxDev;
+
+namespace {
+
+struct TileShape {
+  int x, y, z;
+};
+
+#define LC_SHAPE(ID, X, Y, Z) {X, Y, Z},
+const TileShape kTilesF32[] = {LC_TILES_F32(LC_SHAPE)};
+const TileShape kTilesF64[] = {LC_TILES_F64(LC_SHAPE)};
+#undef LC_SHAPE
+const int kNumF32 = sizeof(kTilesF32) / sizeof(kTilesF32[0]);
+const int kNumF64 = sizeof(kTilesF64) / sizeof(kTilesF64[0]);
+
+const int kHistCap = 8192;     // force history ring (steps)
+const int kGraphSteps = 16;    // steps per captured graph (even)
+const int kXcd = 8;            // accelerator complex dies on MI355X
+
+std::string g_create_error;
+
+}  // namespace
+
+struct lc_ctx {
+  int nbox = 0;
+  int prec = LC_FP32;
+  size_t esz = 4;
+  std::vector<lc_params> prm;
+  std::vector<lc_colloid> col;
+  std::vector<BoxDev> hb;       // host copy of the descriptors
+  long long nsites = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* f[2] = {nullptr, nullptr};
+  void* Q[2] = {nullptr, nullptr};
+  void* u[2] = {nullptr, nullptr};
+  bool own_buf = true;
+  int cur = 0;                  // buffer index holding time n
+  BoxDev* dbox = nullptr;
+  int tile = 0;
+  int nblk = 0;                 // fused-kernel blocks (incl. XCD padding)
+  int ntile = 0;                // real tiles
+  int2* dtiles = nullptr;
+  double* dpart = nullptr;      // 12 per tile
+  long long ghost_total = 0, event_total = 0;
+  double* depart = nullptr;     // 6 per event block
+  size_t depart_cap = 0;
+  double* dforce = nullptr;     // 12 per box
+  double* dhist = nullptr;      // nbox * kHistCap * 12
+  long long* dcount = nullptr;  // steps per box on the device
+  int* dflag = nullptr;
+  double* ddiag = nullptr;
+  size_t ddiag_cap = 0;
+  long nstep = 0;
+  bool any_colloid = false, any_moving = false;
+  bool use_graph = true;
+  bool graph_ok = false;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int fail(lc_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, LC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+const TileShape& tile_shape(const lc_ctx* c, int id) {
+  return c->prec == LC_FP32 ? kTilesF32[id] : kTilesF64[id];
+}
+int num_tiles(const lc_ctx* c) { return c->prec == LC_FP32 ? kNumF32 : kNumF64; }
+
+long long box_sites(const lc_params& p) { return (long long)p.nx * p.ny * p.nz; }
+
+void destroy_graph(lc_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_ok = false;
+}
+
+// Read the device copy of the descriptors back (the colloid position moves
+// on the device) before the host rewrites them.
+int pull_boxes(lc_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->hb.data(), c->dbox, sizeof(BoxDev) * c->nbox, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int b = 0; b < c->nbox; b++)
+    for (int a = 0; a < 3; a++) c->col[b].pos[a] = c->hb[b].pos[a];
+  return LC_OK;
+}
+
+// Rebuild descriptors, tile list and launch ranges for the current tile
+// shape and colloids; upload.
+int layout(lc_ctx* c) {
+  const TileShape& T = tile_shape(c, c->tile);
+  long long tb = 0, gb = 0, eb = 0;
+  int eblk = 0;
+  c->any_colloid = c->any_moving = false;
+  std::vector<int2> tiles;
+  for (int b = 0; b < c->nbox; b++) {
+    BoxDev& B = c->hb[b];
+    const lc_params& p = c->prm[b];
+    const lc_colloid& k = c->col[b];
+    B.ntx = (p.nx + T.x - 1) / T.x;
+    B.nty = (p.ny + T.y - 1) / T.y;
+    B.ntz = (p.nz + T.z - 1) / T.z;
+    B.tile_base = (int)tb;
+    const int nt = B.ntx * B.nty * B.ntz;
+    for (int t = 0; t < nt; t++) tiles.push_back(make_int2(b, t));
+    tb += nt;
+    B.present = k.present;
+    B.motion = k.motion;
+    B.anchoring = k.anchoring;
+    for (int a = 0; a < 3; a++) {
+      B.pos[a] = k.pos[a];
+      B.vel[a] = k.vel[a];
+      B.omega[a] = k.omega[a];
+    }
+    B.a0 = k.a0;
+    B.S0 = k.S0;
+    B.W = k.W;
+    const int ca = k.present ? (int)ceil(k.a0) : 0;
+    B.ghost_ext = k.present ? 2 * ca + 3 : 0;
+    B.ghost_base = (int)gb;
+    gb += (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
+    const bool moving = k.present && k.motion == LC_PRESCRIBED;
+    B.event_ext = moving ? 2 * ca + 5 : 0;
+    B.event_base = (int)eb;
+    B.event_blk0 = eblk;
+    const long long ne = (long long)B.event_ext * B.event_ext * B.event_ext;
+    B.event_nblk = (int)((ne + 255) / 256);
+    eb += 256LL * B.event_nblk;
+    eblk += B.event_nblk;
+    c->any_colloid |= (bool)k.present;
+    c->any_moving |= moving;
+  }
+  c->ntile = (int)tb;
+  c->ghost_total = gb;
+  c->event_total = eb;
+  // XCD-aware order: workgroup i runs on die i % 8, so die d gets the
+  // contiguous chunk d of the spatial tile list.
+  const int per = (c->ntile + kXcd - 1) / kXcd;
+  c->nblk = per * kXcd;
+  std::vector<int2> order(c->nblk, make_int2(-1, 0));
+  for (int i = 0; i < c->nblk; i++) {
+    const int s = (i % kXcd) * per + i / kXcd;
+    if (s < c->ntile) order[i] = tiles[s];
+  }
+  if (c->dtiles) hipFree(c->dtiles);
+  if (c->dpart) hipFree(c->dpart);
+  c->dtiles = nullptr;
+  c->dpart = nullptr;
+  HIPCHK(c, hipMalloc(&c->dtiles, sizeof(int2) * c->nblk));
+  HIPCHK(c, hipMalloc(&c->dpart, sizeof(double) * 12 * std::max(1, c->ntile)));
+  HIPCHK(c, hipMemsetAsync(c->dpart, 0, sizeof(double) * 12 * std::max(1, c->ntile), c->stream));
+  if ((size_t)eblk * 6 > c->depart_cap) {
+    if (c->depart) hipFree(c->depart);
+    c->depart = nullptr;
+    c->depart_cap = std::max<size_t>(6, (size_t)eblk * 6);
+    HIPCHK(c, hipMalloc(&c->depart, sizeof(double) * c->depart_cap));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->dtiles, order.data(), sizeof(int2) * c->nblk, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dbox, c->hb.data(), sizeof(BoxDev) * c->nbox, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  destroy_graph(c);
+  return LC_OK;
+}
+
+template <typename R>
+lc::StepPtrs<R> ptrs(lc_ctx* c, int from) {
+  lc::StepPtrs<R> a;
+  a.fin = (const R*)c->f[from];
+  a.fout = (R*)c->f[1 - from];
+  a.Qin = (const R*)c->Q[from];
+  a.Qout = (R*)c->Q[1 - from];
+  a.uin = (const R*)c->u[from];
+  a.uout = (R*)c->u[1 - from];
+  a.nsites = c->nsites;
+  a.part = c->dpart;
+  a.flag = c->dflag;
+  return a;
+}
+
+// Queue one step reading buffer set `from`.
+template <typename R>
+hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t k1 = nullptr) {
+  hipError_t e;
+  lc::StepPtrs<R> a = ptrs<R>(c, from);
+  if (c->any_colloid) {
+    e = lc::launch_ghost<R>(c->dbox, c->nbox, c->ghost_total, (R*)c->Q[from], c->nsites, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  if (k0) hipEventRecord(k0, c->stream);
+  e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, a, c->stream);
+  if (e != hipSuccess) return e;
+  if (k1) hipEventRecord(k1, c->stream);
+  if (c->any_moving) {
+    e = lc::launch_events<R>(c->dbox, c->nbox, c->event_total, a, c->depart, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return lc::launch_finalize<R>(c->tile, c->nbox, c->dbox, c->dpart, c->depart, c->dforce, c->dhist, kHistCap,
+                                c->dcount, c->stream);
+}
+
+hipError_t enqueue(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t k1 = nullptr) {
+  return c->prec == LC_FP32 ? enqueue_step<float>(c, from, k0, k1) : enqueue_step<double>(c, from, k0, k1);
+}
+
+int build_graph(lc_ctx* c) {
+  destroy_graph(c);
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < kGraphSteps && e == hipSuccess; k++) e = enqueue(c, k & 1);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+  if (e != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(c, LC_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  HIPCHK(c, e2);
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+  c->graph_ok = true;
+  return LC_OK;
+}
+
+int check_box(lc_ctx* c, int box) {
+  if (!c) return LC_EINVAL;
+  if (box < 0 || box >= c->nbox) return fail(c, LC_EINVAL, "box index out of range");
+  return LC_OK;
+}
+
+int validate_params(const lc_params& p, std::string& why) {
+  if (p.nx < 8 || p.ny < 8 || p.nz < 8) { why = "box edges must be >= 8"; return LC_EINVAL; }
+  if ((long long)p.nx * p.ny * p.nz > (1LL << 31)) { why = "box too large"; return LC_EINVAL; }
+  if (p.precision != LC_FP32 && p.precision != LC_FP64) { why = "precision must be LC_FP32 or LC_FP64"; return LC_EINVAL; }
+  if (!(p.tau > 0.5)) { why = "tau must exceed 1/2"; return LC_EINVAL; }
+  if (!(p.rho0 > 0.0)) { why = "rho0 must be positive"; return LC_EINVAL; }
+  if (!(p.Gamma >= 0.0) || !(p.K >= 0.0)) { why = "Gamma and K must be >= 0"; return LC_EINVAL; }
+  if (!isfinite(p.A0) || !isfinite(p.gamma) || !isfinite(p.q0) || !isfinite(p.xi)) {
+    why = "non-finite material parameter";
+    return LC_EINVAL;
+  }
+  return LC_OK;
+}
+
+// host <-> device conversion of one box's field
+template <typename R>
+int put_field(lc_ctx* c, void* dev, int box, int ncomp, const double* src, double shift_w) {
+  const long long n = box_sites(c->prm[box]);
+  std::vector<R> tmp((size_t)n);
+  for (int k = 0; k < ncomp; k++) {
+    const double sh = shift_w != 0.0 ? lc::wgt(k) : 0.0;
+    for (long long i = 0; i < n; i++) tmp[i] = (R)(src[k * n + i] - sh);
+    HIPCHK(c, hipMemcpyAsync((R*)dev + k * c->nsites + c->hb[box].off, tmp.data(), sizeof(R) * n,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return LC_OK;
+}
+
+template <typename R>
+int get_field(lc_ctx* c, const void* dev, int box, int ncomp, double* dst, double shift_w) {
+  const long long n = box_sites(c->prm[box]);
+  std::vector<R> tmp((size_t)n);
+  for (int k = 0; k < ncomp; k++) {
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), (const R*)dev + k * c->nsites + c->hb[box].off, sizeof(R) * n,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double sh = shift_w != 0.0 ? lc::wgt(k) : 0.0;
+    for (long long i = 0; i < n; i++) dst[k * n + i] = (double)tmp[i] + sh;
+  }
+  return LC_OK;
+}
+
+int put(lc_ctx* c, void* dev, int box, int ncomp, const double* src, bool shift) {
+  return c->prec == LC_FP32 ? put_field<float>(c, dev, box, ncomp, src, shift ? 1.0 : 0.0)
+                            : put_field<double>(c, dev, box, ncomp, src, shift ? 1.0 : 0.0);
+}
+int get(lc_ctx* c, const void* dev, int box, int ncomp, double* dst, bool shift) {
+  return c->prec == LC_FP32 ? get_field<float>(c, dev, box, ncomp, dst, shift ? 1.0 : 0.0)
+                            : get_field<double>(c, dev, box, ncomp, dst, shift ? 1.0 : 0.0);
+}
+
+int check_flag(lc_ctx* c) {
+  int flag = 0;
+  HIPCHK(c, hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (flag) return fail(c, LC_ENUMERIC, "a step produced a non-finite value or |u| >= 0.3");
+  return LC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lc_create(const lc_params* p, void* hip_stream, lc_ctx** out) {
+  return lc_create_batch(1, p, hip_stream, out);
+}
+
+int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out) {
+  if (!out) return fail(nullptr, LC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nbox < 1 || !p) return fail(nullptr, LC_EINVAL, "need at least one box");
+  for (int b = 0; b < nbox; b++) {
+    std::string why;
+    if (validate_params(p[b], why) != LC_OK) return fail(nullptr, LC_EINVAL, "box " + std::to_string(b) + ": " + why);
+    if (p[b].precision != p[0].precision) return fail(nullptr, LC_EINVAL, "all boxes must share one precision");
+  }
+  lc_ctx* c = new lc_ctx();
+  c->nbox = nbox;
+  c->prec = p[0].precision;
+  c->esz = c->prec == LC_FP32 ? 4 : 8;
+  c->prm.assign(p, p + nbox);
+  c->col.assign(nbox, lc_colloid());
+  for (auto& k : c->col) memset(&k, 0, sizeof(k));
+  c->hb.assign(nbox, BoxDev());
+  long long off = 0;
+  for (int b = 0; b < nbox; b++) {
+    BoxDev& B = c->hb[b];
+    memset(&B, 0, sizeof(B));
+    const lc_params& q = p[b];
+    B.nx = q.nx; B.ny = q.ny; B.nz = q.nz; B.hydro = q.hydro ? 1 : 0;
+    B.off = off;
+    // keep every box 64-site aligned for coalesced access
+    off += (box_sites(q) + 63) / 64 * 64;
+    B.tau = q.tau; B.rho0 = q.rho0; B.A0 = q.A0; B.gamma = q.gamma; B.K = q.K; B.q0 = q.q0;
+    B.xi = q.xi; B.Gamma = q.Gamma;
+    for (int a = 0; a < 3; a++) B.body[a] = q.body_force[a];
+  }
+  c->nsites = off;
+  int rc = LC_OK;
+  auto bail = [&](int code, const std::string& m) {
+    g_create_error = m;
+    lc_destroy(c);
+    return code;
+  };
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(LC_EDEVICE, "hipStreamCreate failed");
+    c->own_stream = true;
+  }
+  const size_t nf = 19 * c->nsites * c->esz, nq = 5 * c->nsites * c->esz, nu = 3 * c->nsites * c->esz;
+  for (int k = 0; k < 2; k++) {
+    if (hipMalloc(&c->f[k], nf) != hipSuccess || hipMalloc(&c->Q[k], nq) != hipSuccess ||
+        hipMalloc(&c->u[k], nu) != hipSuccess)
+      return bail(LC_ENOMEM, "device allocation of the fields failed");
+  }
+  if (hipMalloc(&c->dbox, sizeof(BoxDev) * nbox) != hipSuccess ||
+      hipMalloc(&c->dforce, sizeof(double) * 12 * nbox) != hipSuccess ||
+      hipMalloc(&c->dhist, sizeof(double) * 12 * (size_t)kHistCap * nbox) != hipSuccess ||
+      hipMalloc(&c->dcount, sizeof(long long) * nbox) != hipSuccess ||
+      hipMalloc(&c->dflag, sizeof(int)) != hipSuccess)
+    return bail(LC_ENOMEM, "device allocation failed");
+  hipMemsetAsync(c->dforce, 0, sizeof(double) * 12 * nbox, c->stream);
+  hipMemsetAsync(c->dhist, 0, sizeof(double) * 12 * (size_t)kHistCap * nbox, c->stream);
+  hipMemsetAsync(c->dcount, 0, sizeof(long long) * nbox, c->stream);
+  hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream);
+  for (int k = 0; k < 2; k++) {
+    hipMemsetAsync(c->Q[k], 0, nq, c->stream);
+    hipMemsetAsync(c->u[k], 0, nu, c->stream);
+  }
+  // f = w_i rho0 everywhere (stored shifted by w_i)
+  for (int k = 0; k < 2; k++) {
+    // per-box rho0: fill with box 0's value, then fix boxes that differ
+    hipError_t e = c->prec == LC_FP32 ? lc::launch_fill<float>((float*)c->f[k], c->nsites, p[0].rho0, c->stream)
+                                      : lc::launch_fill<double>((double*)c->f[k], c->nsites, p[0].rho0, c->stream);
+    if (e != hipSuccess) return bail(LC_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+  }
+  rc = layout(c);
+  if (rc != LC_OK) return bail(rc, c->err);
+  for (int b = 0; b < nbox; b++) {
+    if (p[b].rho0 != p[0].rho0) {
+      std::vector<double> f0((size_t)19 * box_sites(p[b]));
+      for (int i = 0; i < 19; i++)
+        for (long long s = 0; s < box_sites(p[b]); s++) f0[i * box_sites(p[b]) + s] = lc::wgt(i) * p[b].rho0;
+      if ((rc = lc_set_f(c, b, f0.data())) != LC_OK) return bail(rc, c->err);
+    }
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(LC_EDEVICE, "initialisation failed");
+  *out = c;
+  return LC_OK;
+}
+
+void lc_destroy(lc_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  destroy_graph(c);
+  if (c->own_buf)
+    for (int k = 0; k < 2; k++) {
+      if (c->f[k]) hipFree(c->f[k]);
+      if (c->Q[k]) hipFree(c->Q[k]);
+      if (c->u[k]) hipFree(c->u[k]);
+    }
+  void* bufs[] = {c->dbox, c->dtiles, c->dpart, c->depart, c->dforce, c->dhist, c->dcount, c->dflag, c->ddiag};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* lc_last_error(const lc_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int lc_buffer_bytes(const lc_ctx* c, size_t out[3]) {
+  if (!c || !out) return LC_EINVAL;
+  out[0] = 19 * c->nsites * c->esz;
+  out[1] = 5 * c->nsites * c->esz;
+  out[2] = 3 * c->nsites * c->esz;
+  return LC_OK;
+}
+
+int lc_bind_buffers(lc_ctx* c, void* f0, void* f1, void* Q0, void* Q1, void* u0, void* u1) {
+  if (!c) return LC_EINVAL;
+  void* nf[2] = {f0, f1};
+  void* nq[2] = {Q0, Q1};
+  void* nu[2] = {u0, u1};
+  for (int k = 0; k < 2; k++)
+    if (!nf[k] || !nq[k] || !nu[k] || ((uintptr_t)nf[k] | (uintptr_t)nq[k] | (uintptr_t)nu[k]) % 256)
+      return fail(c, LC_EINVAL, "buffers must be non-NULL and 256-byte aligned");
+  size_t sz[3];
+  lc_buffer_bytes(c, sz);
+  for (int k = 0; k < 2; k++) {
+    HIPCHK(c, hipMemcpyAsync(nf[k], c->f[k], sz[0], hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(nq[k], c->Q[k], sz[1], hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(nu[k], c->u[k], sz[2], hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->own_buf)
+    for (int k = 0; k < 2; k++) {
+      hipFree(c->f[k]);
+      hipFree(c->Q[k]);
+      hipFree(c->u[k]);
+    }
+  for (int k = 0; k < 2; k++) {
+    c->f[k] = nf[k];
+    c->Q[k] = nq[k];
+    c->u[k] = nu[k];
+  }
+  c->own_buf = false;
+  destroy_graph(c);
+  return LC_OK;
+}
+
+int lc_set_colloid(lc_ctx* c, int box, const lc_colloid* k) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!k) return fail(c, LC_EINVAL, "colloid is NULL");
+  const lc_params& p = c->prm[box];
+  lc_colloid v = *k;
+  if (v.present) {
+    const int Lmin = std::min(p.nx, std::min(p.ny, p.nz));
+    if (!(v.a0 > 1.0) || !(2.0 * v.a0 + 4.0 <= Lmin)) return fail(c, LC_EINVAL, "colloid radius does not fit the box");
+    if (v.anchoring < LC_ANCHOR_NONE || v.anchoring > LC_ANCHOR_PLANAR) return fail(c, LC_EINVAL, "bad anchoring");
+    if (v.motion != LC_FIXED && v.motion != LC_PRESCRIBED) return fail(c, LC_EINVAL, "bad motion");
+    if (!(v.W >= 0.0)) return fail(c, LC_EINVAL, "W must be >= 0");
+    if (v.anchoring != LC_ANCHOR_NONE && !(p.K + v.W > 0.0)) return fail(c, LC_EINVAL, "K + W must be positive");
+    for (int a = 0; a < 3; a++)
+      if (!isfinite(v.pos[a]) || !isfinite(v.vel[a]) || !isfinite(v.omega[a]) || fabs(v.vel[a]) >= 1.0)
+        return fail(c, LC_EINVAL, "colloid position/velocity must be finite, |v| < 1");
+    const int L[3] = {p.nx, p.ny, p.nz};
+    for (int a = 0; a < 3; a++) {
+      double r = fmod(v.pos[a], (double)L[a]);
+      if (r < 0) r += L[a];
+      v.pos[a] = r;
+    }
+  }
+  if ((rc = pull_boxes(c)) != LC_OK) return rc;
+  c->col[box] = v;
+  return layout(c);
+}
+
+int lc_get_colloid(lc_ctx* c, int box, lc_colloid* k) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!k) return fail(c, LC_EINVAL, "colloid is NULL");
+  if ((rc = pull_boxes(c)) != LC_OK) return rc;
+  *k = c->col[box];
+  return LC_OK;
+}
+
+int lc_set_Q(lc_ctx* c, int box, const double* Q5) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!Q5) return fail(c, LC_EINVAL, "Q is NULL");
+  return put(c, c->Q[c->cur], box, 5, Q5, false);
+}
+int lc_set_f(lc_ctx* c, int box, const double* f19) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!f19) return fail(c, LC_EINVAL, "f is NULL");
+  return put(c, c->f[c->cur], box, 19, f19, true);
+}
+int lc_set_u(lc_ctx* c, int box, const double* u3) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!u3) return fail(c, LC_EINVAL, "u is NULL");
+  return put(c, c->u[c->cur], box, 3, u3, false);
+}
+int lc_get_Q(lc_ctx* c, int box, double* Q5) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!Q5) return fail(c, LC_EINVAL, "Q is NULL");
+  if ((rc = check_flag(c)) != LC_OK) return rc;
+  return get(c, c->Q[c->cur], box, 5, Q5, false);
+}
+int lc_get_f(lc_ctx* c, int box, double* f19) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!f19) return fail(c, LC_EINVAL, "f is NULL");
+  if ((rc = check_flag(c)) != LC_OK) return rc;
+  return get(c, c->f[c->cur], box, 19, f19, true);
+}
+int lc_get_u(lc_ctx* c, int box, double* u3) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!u3) return fail(c, LC_EINVAL, "u is NULL");
+  if ((rc = check_flag(c)) != LC_OK) return rc;
+  return get(c, c->u[c->cur], box, 3, u3, false);
+}
+
+int lc_step(lc_ctx* c, int nsteps) {
+  if (!c || nsteps < 0) return LC_EINVAL;
+  int left = nsteps;
+  auto eager = [&]() -> int {
+    hipError_t e = enqueue(c, c->cur);
+    if (e != hipSuccess) return fail(c, LC_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    c->cur ^= 1;
+    c->nstep++;
+    left--;
+    return LC_OK;
+  };
+  int rc;
+  if (c->use_graph && left >= kGraphSteps + (c->cur ? 1 : 0)) {
+    if (c->cur == 1 && (rc = eager()) != LC_OK) return rc;
+    if (!c->graph_ok && (rc = build_graph(c)) != LC_OK) return rc;
+    while (left >= kGraphSteps) {
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      c->nstep += kGraphSteps;
+      left -= kGraphSteps;
+    }
+  }
+  while (left > 0)
+    if ((rc = eager()) != LC_OK) return rc;
+  return LC_OK;
+}
+
+int lc_sync(lc_ctx* c) {
+  if (!c) return LC_EINVAL;
+  return check_flag(c);
+}
+
+long lc_get_nstep(lc_ctx* c) { return c ? c->nstep : -1; }
+
+int lc_get_force(lc_ctx* c, int box, double out[12]) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!out) return fail(c, LC_EINVAL, "out is NULL");
+  HIPCHK(c, hipMemcpyAsync(out, c->dforce + 12 * box, sizeof(double) * 12, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LC_OK;
+}
+
+int lc_history_capacity(const lc_ctx* c) { return c ? kHistCap : 0; }
+
+int lc_get_force_history(lc_ctx* c, int box, int nsteps, double* out) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!out || nsteps < 0 || nsteps > kHistCap || nsteps > c->nstep)
+    return fail(c, LC_EINVAL, "nsteps exceeds the steps taken or the history capacity");
+  long long cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, c->dcount + box, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> h((size_t)kHistCap * 12);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->dhist + (size_t)box * kHistCap * 12, sizeof(double) * h.size(),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < nsteps; k++) {
+    const long long n = cnt - nsteps + k;
+    memcpy(out + 12 * k, h.data() + 12 * (n % kHistCap), sizeof(double) * 12);
+  }
+  return LC_OK;
+}
+
+int lc_get_diag(lc_ctx* c, int box, lc_diag* out) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!out) return fail(c, LC_EINVAL, "out is NULL");
+  if ((rc = check_flag(c)) != LC_OK) return rc;
+  const long long n = box_sites(c->prm[box]);
+  const long long nb = (n + 255) / 256;
+  if ((size_t)(6 * nb) > c->ddiag_cap) {
+    if (c->ddiag) hipFree(c->ddiag);
+    c->ddiag = nullptr;
+    c->ddiag_cap = 6 * nb;
+    HIPCHK(c, hipMalloc(&c->ddiag, sizeof(double) * c->ddiag_cap));
+  }
+  hipError_t e;
+  if (c->prec == LC_FP32) {
+    lc::StepPtrs<float> a = ptrs<float>(c, c->cur);
+    if (c->any_colloid) lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->stream);
+    e = lc::launch_diag<float>(c->dbox, box, n, a, c->ddiag, c->stream);
+  } else {
+    lc::StepPtrs<double> a = ptrs<double>(c, c->cur);
+    if (c->any_colloid) lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->stream);
+    e = lc::launch_diag<double>(c->dbox, box, n, a, c->ddiag, c->stream);
+  }
+  HIPCHK(c, e);
+  std::vector<double> h((size_t)(6 * nb));
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->ddiag, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  memset(out, 0, sizeof(*out));
+  for (long long k = 0; k < nb; k++) {
+    out->free_energy += h[6 * k + 0];
+    out->mass += h[6 * k + 1];
+    for (int a = 0; a < 3; a++) out->momentum[a] += h[6 * k + 2 + a];
+    out->umax = std::max(out->umax, h[6 * k + 5]);
+  }
+  return LC_OK;
+}
+
+int lc_defects(lc_ctx* c, int box, double threshold, unsigned char* mask, long* count_out) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if ((rc = check_flag(c)) != LC_OK) return rc;
+  const long long n = box_sites(c->prm[box]);
+  unsigned char* dm = nullptr;
+  unsigned long long* dc = nullptr;
+  HIPCHK(c, hipMalloc(&dm, n));
+  if (hipMalloc(&dc, sizeof(unsigned long long)) != hipSuccess) {
+    hipFree(dm);
+    return fail(c, LC_ENOMEM, "hipMalloc failed");
+  }
+  hipMemsetAsync(dc, 0, sizeof(unsigned long long), c->stream);
+  hipError_t e = c->prec == LC_FP32
+                     ? lc::launch_defects<float>(c->dbox, box, n, (const float*)c->Q[c->cur] + 0, c->nsites,
+                                                 threshold, dm + 0, dc, c->stream)
+                     : lc::launch_defects<double>(c->dbox, box, n, (const double*)c->Q[c->cur], c->nsites,
+                                                  threshold, dm, dc, c->stream);
+  unsigned long long cnt = 0;
+  if (e == hipSuccess) {
+    if (mask) e = hipMemcpyAsync(mask, dm, n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&cnt, dc, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  hipFree(dm);
+  hipFree(dc);
+  HIPCHK(c, e);
+  if (count_out) *count_out = (long)cnt;
+  return LC_OK;
+}
+
+int lc_num_tiles(const lc_ctx* c) { return c ? num_tiles(c) : 0; }
+
+int lc_tile_shape(const lc_ctx* c, int id, int out[3]) {
+  if (!c || !out || id < 0 || id >= num_tiles(c)) return LC_EINVAL;
+  const TileShape& t = tile_shape(c, id);
+  out[0] = t.x;
+  out[1] = t.y;
+  out[2] = t.z;
+  return LC_OK;
+}
+
+int lc_set_tile(lc_ctx* c, int id) {
+  if (!c) return LC_EINVAL;
+  if (id < 0 || id >= num_tiles(c)) return fail(c, LC_EINVAL, "tile id out of range");
+  if (id == c->tile) return LC_OK;
+  int rc = pull_boxes(c);
+  if (rc) return rc;
+  c->tile = id;
+  return layout(c);
+}
+
+int lc_get_tile(const lc_ctx* c) { return c ? c->tile : -1; }
+
+int lc_use_graph(lc_ctx* c, int enable) {
+  if (!c) return LC_EINVAL;
+  c->use_graph = enable != 0;
+  return LC_OK;
+}
+
+int lc_launch_info(const lc_ctx* c, long out[2]) {
+  if (!c || !out) return LC_EINVAL;
+  const TileShape& t = tile_shape(c, c->tile);
+  out[0] = c->nblk;
+  out[1] = (long)t.x * t.y * t.z;
+  return LC_OK;
+}
+
+int lc_time_kernel(lc_ctx* c, int nsteps, double out[3]) {
+  if (!c || !out || nsteps < 1) return LC_EINVAL;
+  std::vector<hipEvent_t> ev(2 * nsteps + 2);
+  for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
+  HIPCHK(c, hipEventRecord(ev[2 * nsteps], c->stream));
+  for (int k = 0; k < nsteps; k++) {
+    hipError_t e = enqueue(c, c->cur, ev[2 * k], ev[2 * k + 1]);
+    if (e != hipSuccess) return fail(c, LC_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    c->cur ^= 1;
+    c->nstep++;
+  }
+  HIPCHK(c, hipEventRecord(ev[2 * nsteps + 1], c->stream));
+  HIPCHK(c, hipEventSynchronize(ev[2 * nsteps + 1]));
+  double ks = 0.0;
+  for (int k = 0; k < nsteps; k++) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+    ks += ms;
+  }
+  float tot = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&tot, ev[2 * nsteps], ev[2 * nsteps + 1]));
+  for (auto& e : ev) hipEventDestroy(e);
+  out[0] = ks / nsteps;
+  out[1] = tot / nsteps;
+  out[2] = tot;
+  return check_flag(c);
+}
+
+}  // extern "C"

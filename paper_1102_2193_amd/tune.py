@@ -1,0 +1,58 @@
+"""Tile-shape autotuner for the fused kernel.
+
+Every tile shape computes the same per-site arithmetic (the parity tests
+check that); the shapes differ only in LDS footprint, halo overhead and
+occupancy.  The tuner times each shape with HIP events on the live context
+and keeps the fastest in a JSON cache keyed by the batch's box sizes and
+precision.  Tuning on a live context advances its state by the timed steps.
+"""
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning.json")
+
+
+def batch_key(ctx):
+    dims = ",".join("%dx%dx%d" % (p.nx, p.ny, p.nz) for p in ctx.box_params)
+    prec = "fp64" if ctx.box_params[0].precision == 1 else "fp32"
+    if len(dims) > 200:
+        import hashlib
+        dims = "n%d-%s" % (len(ctx.box_params), hashlib.sha1(dims.encode()).hexdigest()[:16])
+    return "%s:%s" % (prec, dims)
+
+
+def load_cache():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune(ctx, steps=40, warm=8):
+    """Time every tile shape on ctx; returns {tile_id: mean step ms}."""
+    res = {}
+    for t in range(ctx.num_tiles()):
+        ctx.set_tile(t)
+        ctx.time_kernel(warm)
+        res[t] = ctx.time_kernel(steps)["step_ms"]
+    return res
+
+
+def best_tile(ctx, name="", save=True):
+    key = batch_key(ctx)
+    cache = load_cache()
+    if key in cache:
+        return int(cache[key]["tile"])
+    res = tune(ctx)
+    best = min(res, key=res.get)
+    if save:
+        cache[key] = {"tile": best, "shape": list(ctx.tile_shape(best)), "step_ms": res,
+                      "workload": name}
+        try:
+            with open(CACHE, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return best

@@ -1,0 +1,72 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/lc.h, and rejects invalid parameters before touching the
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "lc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lc_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1102_2193_amd import lc
+    if not os.path.exists(lc.LIB_PATH):
+        pytest.fail("liblc.so is not built; run __graft_entry__.build()")
+    return lc.load()
+
+
+def test_header_declares_the_core_calls():
+    names = declared()
+    for n in ("lc_create", "lc_set_colloid", "lc_step", "lc_get_Q", "lc_get_force"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1102_2193_amd import lc
+    names = declared()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(lc.EXPORTS) == names
+
+
+def test_struct_sizes_match_header(lib):
+    from paper_1102_2193_amd import lc
+    # int x6 + double x11 ; int x4 + double x12
+    assert ctypes.sizeof(lc.Params) == 6 * 4 + 11 * 8
+    assert ctypes.sizeof(lc.Colloid) == 4 * 4 + 12 * 8
+    assert ctypes.sizeof(lc.Diag) == 6 * 8
+
+
+@pytest.mark.parametrize("field,value", [("nx", 4), ("tau", 0.5), ("precision", 7), ("rho0", 0.0),
+                                         ("Gamma", -1.0)])
+def test_create_rejects_bad_parameters(lib, field, value):
+    from paper_1102_2193_amd import lc
+    p = lc.make_params(16)
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    rc = lib.lc_create(ctypes.byref(p), None, ctypes.byref(h))
+    assert rc == 1 and not h.value
+    assert lib.lc_last_error(None)
+
+
+def test_batch_rejects_mixed_precision(lib):
+    from paper_1102_2193_amd import lc
+    arr = (lc.Params * 2)(lc.make_params(16, precision=lc.FP32), lc.make_params(16, precision=lc.FP64))
+    h = ctypes.c_void_p()
+    assert lib.lc_create_batch(2, arr, None, ctypes.byref(h)) == 1
+    assert b"precision" in lib.lc_last_error(None)
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    assert lib.lc_step(None, 1) == 1
+    assert lib.lc_sync(None) == 1
+    assert lib.lc_get_nstep(None) == -1

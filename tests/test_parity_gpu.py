@@ -1,0 +1,302 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Bars (checked element by element over fluid sites):
+  FP64 library vs oracle: round-off (relative 1e-10 on Q, f and u).
+  FP32 library vs oracle: 1e-5 relative on Q and f, 1e-3 on the colloid force.
+Every case prints its name before touching the GPU.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1102_2193_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+NEM = inputs.NEMATIC
+ANCH = {"none": 0, "normal": 1, "planar": 2}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_inf(a, b, mask):
+    d = np.max(np.abs(a - b)[:, mask])
+    return d / max(np.max(np.abs(b[:, mask])), 1e-300)
+
+
+def rel_l2(a, b, mask):
+    d = np.linalg.norm((a - b)[:, mask])
+    return d / max(np.linalg.norm(b[:, mask]), 1e-300)
+
+
+def run_pair(dims, prm, steps, precision, colloid=None, Q0=None, tile=None, graph=True, f0=None,
+             hist=False):
+    """Run the same seeded case on the GPU and on the oracle."""
+    from oracle import lco
+    from paper_1102_2193_amd import lc
+    nx, ny, nz = dims
+    ctx = lc.Context([dict(nx=nx, ny=ny, nz=nz, precision=precision, **prm)])
+    if tile is not None:
+        ctx.set_tile(tile)
+    ctx.use_graph(graph)
+    ref = lco.Sim(nx, ny, nz, **{k: v for k, v in prm.items()})
+    if colloid is not None:
+        c = dict(colloid)
+        pos, a0 = c.pop("pos"), c.pop("a0")
+        ctx.set_colloid(0, pos, a0, **c)
+        oc = dict(c)
+        oc["anchoring"] = ANCH[oc.get("anchoring", "normal")] if isinstance(oc.get("anchoring", "normal"), str) \
+            else oc["anchoring"]
+        ref.set_colloid(pos, a0, **oc)
+    if Q0 is not None:
+        ctx.set_Q(0, Q0)
+        ref.set_Q(Q0)
+    if f0 is not None:
+        ctx.set_f(0, f0)
+        ref.set_f(f0)
+    ctx.step(steps)
+    ref_hist = []
+    if hist:
+        for _ in range(steps):
+            ref.step(1)
+            ref_hist.append(ref.force())
+    else:
+        ref.step(steps)
+    out = dict(Q=ctx.get_Q(0), f=ctx.get_f(0), u=ctx.get_u(0), F=ctx.force(0),
+               Qr=ref.get_Q(), fr=ref.get_f(), ur=ref.get_u(), Fr=ref.force(), fluid=~ref.solid(),
+               ctx=ctx, ref=ref)
+    if hist:
+        out["H"] = ctx.force_history(0, steps)
+        out["Hr"] = np.array(ref_hist)
+    return out
+
+
+def check(r, tol_q, tol_f, tol_u=None, tol_force=None, w_dev=True):
+    m = r["fluid"]
+    eq = max(rel_inf(r["Q"], r["Qr"], m), rel_l2(r["Q"], r["Qr"], m))
+    ef = max(rel_inf(r["f"], r["fr"], m), rel_l2(r["f"], r["fr"], m))
+    say("   rel err Q %.3e  f %.3e" % (eq, ef))
+    assert eq < tol_q, ("Q", eq)
+    assert ef < tol_f, ("f", ef)
+    if tol_u is not None:
+        eu = rel_inf(r["u"], r["ur"], m)
+        say("   rel err u %.3e" % eu)
+        assert eu < tol_u, ("u", eu)
+    if tol_force is not None:
+        if "H" in r:
+            F, Fr = r["H"], r["Hr"]
+        else:
+            F, Fr = r["F"][None], r["Fr"][None]
+        ef = np.linalg.norm(F - Fr) / max(np.linalg.norm(Fr), 1e-9)
+        say("   rel err force %.3e (|F| %.3e)" % (ef, np.linalg.norm(Fr)))
+        assert ef < tol_force, ("force", ef)
+
+
+CFG0 = dict(pos=(16.0, 16.0, 16.0), a0=4.0, anchoring="planar", W=0.01, S0=0.5)
+
+
+def test_fp64_parity_nematic32_planar():
+    say("case: 32^3 fp64 planar W=0.01 a=4, 200 steps")
+    L = 32
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=1)
+    r = run_pair((L, L, L), NEM, 200, "fp64", colloid=CFG0, Q0=Q0, hist=True)
+    check(r, 1e-10, 1e-12, tol_u=1e-8, tol_force=1e-8)
+    # deviations from rest carry the dynamics: compare them too
+    m = r["fluid"]
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)[:, None]
+    dev = rel_inf(r["f"][:, m] - w, r["fr"][:, m] - w, np.ones(m.sum(), bool))
+    say("   rel err f - w %.3e" % dev)
+    assert dev < 1e-9
+
+
+def test_fp32_parity_nematic32_planar():
+    say("case: 32^3 fp32 planar W=0.01 a=4, 100 steps")
+    L = 32
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=1)
+    r = run_pair((L, L, L), NEM, 100, "fp32", colloid=CFG0, Q0=Q0, hist=True)
+    check(r, 1e-5, 1e-5, tol_force=1e-3)
+
+
+MODES = [(anch, motion, hydro) for anch in ("none", "normal", "planar") for motion in (0, 1) for hydro in (0, 1)]
+
+
+@pytest.mark.parametrize("anch,motion,hydro", MODES)
+def test_fp64_brute_force_modes(anch, motion, hydro):
+    say("case: 12^3 fp64 anchoring=%s motion=%d hydro=%d" % (anch, motion, hydro))
+    L = 12
+    prm = dict(NEM, hydro=hydro, q0=0.2)
+    col = dict(pos=(6.3, 5.8, 6.1), a0=3.1, anchoring=anch, W=0.02 if anch != "normal" else math.inf,
+               S0=0.5, vel=(0.04, -0.02, 0.03) if motion else (0, 0, 0), omega=(0.0, 0.0, 0.002),
+               motion=motion)
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=21, noise=0.02, director=(1, 0.2, 0.4))
+    r = run_pair((L, L, L), prm, 30, "fp64", colloid=col, Q0=Q0, hist=True)
+    assert np.all(np.isfinite(r["Q"]))
+    check(r, 1e-10, 1e-12, tol_u=1e-8 if hydro else None, tol_force=1e-8 if hydro else None)
+    if motion:
+        c = r["ctx"].get_colloid(0)
+        oc = r["ref"].get_colloid()
+        np.testing.assert_array_equal(np.array(c.pos), np.array(oc.pos))
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_fp64_ragged_box_every_tile(tile):
+    say("case: 20x12x10 fp64 tile %d" % tile)
+    dims = (20, 12, 10)
+    prm = dict(NEM, q0=0.15)
+    col = dict(pos=(9.5, 6.2, 5.0), a0=2.6, anchoring="normal", W=0.05, S0=0.45)
+    Q0 = inputs.noisy_nematic_q(*dims, inputs.Q_INIT, seed=5, noise=0.01)
+    r = run_pair(dims, prm, 25, "fp64", colloid=col, Q0=Q0, tile=tile, hist=True)
+    check(r, 1e-10, 1e-12, tol_u=1e-8, tol_force=1e-8)
+
+
+def test_fp32_tiles_agree():
+    from paper_1102_2193_amd import lc
+    say("case: 40x24x16 fp32, all tiles")
+    dims = (40, 24, 16)
+    Q0 = inputs.noisy_nematic_q(*dims, inputs.Q_INIT, seed=6)
+    res = []
+    ntile = None
+    for tile in range(64):
+        ctx = lc.Context([dict(nx=dims[0], ny=dims[1], nz=dims[2], precision="fp32", **NEM)])
+        ntile = ctx.num_tiles()
+        if tile >= ntile:
+            break
+        ctx.set_tile(tile)
+        ctx.set_colloid(0, (20.0, 12.0, 8.0), 5.0, anchoring="planar", W=0.01)
+        ctx.set_Q(0, Q0)
+        ctx.step(20)
+        res.append((ctx.tile_shape(tile), ctx.get_Q(0), ctx.get_f(0), ctx.force(0)))
+        ctx.close()
+    for shape, Q, f, F in res[1:]:
+        dq = np.max(np.abs(Q - res[0][1]))
+        df = np.max(np.abs(f - res[0][2]))
+        say("   tile %s: max |dQ| %.3e |df| %.3e" % (shape, dq, df))
+        assert dq < 1e-6 and df < 1e-7
+        np.testing.assert_allclose(F, res[0][3], rtol=1e-4, atol=1e-9)
+
+
+def test_batch_equals_single_boxes_and_oracle():
+    from oracle import lco
+    from paper_1102_2193_amd import lc
+    say("case: batch of 3 uneven fp32 boxes")
+    boxes = [dict(nx=24, precision="fp32", **dict(NEM, q0=2 * math.pi / 24)),
+             dict(nx=16, ny=20, nz=12, precision="fp32", **NEM),
+             dict(nx=32, precision="fp32", **dict(NEM, q0=2 * math.pi / 16))]
+    cols = [((12, 12, 12), 4.0, "normal"), ((8, 10, 6), 3.0, "planar"), ((16, 16, 16), 6.0, "normal")]
+    Qs = [inputs.helix_q(24, 24, 24, 2 * math.pi / 24, inputs.Q_INIT),
+          inputs.noisy_nematic_q(16, 20, 12, inputs.Q_INIT, seed=3),
+          inputs.helix_q(32, 32, 32, 2 * math.pi / 16, inputs.Q_INIT)]
+    ctx = lc.Context(boxes)
+    for b, (pos, a, an) in enumerate(cols):
+        ctx.set_colloid(b, pos, a, anchoring=an, W=math.inf)
+        ctx.set_Q(b, Qs[b])
+    ctx.step(40)
+    for b, (pos, a, an) in enumerate(cols):
+        single = lc.Context([boxes[b]])
+        single.set_colloid(0, pos, a, anchoring=an, W=math.inf)
+        single.set_Q(0, Qs[b])
+        single.step(40)
+        np.testing.assert_array_equal(ctx.get_Q(b), single.get_Q(0))
+        np.testing.assert_array_equal(ctx.get_f(b), single.get_f(0))
+        single.close()
+        p = {k: v for k, v in boxes[b].items() if k not in ("nx", "ny", "nz", "precision")}
+        ref = lco.Sim(boxes[b]["nx"], boxes[b].get("ny"), boxes[b].get("nz"), **p)
+        ref.set_colloid(pos, a, anchoring=ANCH[an], W=math.inf)
+        ref.set_Q(Qs[b])
+        ref.step(40)
+        m = ~ref.solid()
+        eq = rel_inf(ctx.get_Q(b), ref.get_Q(), m)
+        ef = rel_inf(ctx.get_f(b), ref.get_f(), m)
+        say("   box %d rel err Q %.3e f %.3e" % (b, eq, ef))
+        assert eq < 1e-5 and ef < 1e-5
+
+
+def test_graph_replay_equals_eager():
+    from paper_1102_2193_amd import lc
+    say("case: graph vs eager, 24^3 fp32, 37 steps")
+    L = 24
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=9)
+    out = []
+    for g in (False, True):
+        ctx = lc.Context([dict(nx=L, precision="fp32", **NEM)])
+        ctx.use_graph(g)
+        ctx.set_colloid(0, (12.0, 12.0, 12.0), 4.0, anchoring="normal", W=0.01, vel=(1e-2, 0, 0),
+                        motion=lc.PRESCRIBED)
+        ctx.set_Q(0, Q0)
+        for n in (1, 36):
+            ctx.step(n)
+        out.append((ctx.get_Q(0), ctx.get_f(0), ctx.force_history(0, 37), np.array(ctx.get_colloid(0).pos)))
+        ctx.close()
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_diag_and_defects_match_oracle():
+    say("case: diag/defects 24^3 fp64 cholesteric")
+    L = 24
+    prm = dict(NEM, q0=2 * math.pi / 24)
+    col = dict(pos=(12.0, 12.0, 12.0), a0=5.0, anchoring="normal", W=math.inf)
+    Q0 = inputs.helix_q(L, L, L, 2 * math.pi / 24, inputs.Q_INIT)
+    r = run_pair((L, L, L), prm, 30, "fp64", colloid=col, Q0=Q0)
+    d, dr = r["ctx"].diag(0), r["ref"].diag()
+    for k in ("free_energy", "mass"):
+        assert d[k] == pytest.approx(dr[k], rel=1e-11), k
+    np.testing.assert_allclose(d["momentum"], dr["momentum"], atol=1e-10)
+    assert d["umax"] == pytest.approx(dr["umax"], rel=1e-9)
+    Q = r["ctx"].get_Q(0)
+    xx, xy, xz, yy, yz = Q
+    T = np.stack([np.stack([xx, xy, xz], -1), np.stack([xy, yy, yz], -1), np.stack([xz, yz, -xx - yy], -1)], -2)
+    lam = np.linalg.eigvalsh(T)[..., 2]
+    for thr in (0.435, 0.49):
+        mask, cnt = r["ctx"].defects(0, thr)
+        ref = (1.5 * lam < thr) & r["fluid"]
+        np.testing.assert_array_equal(mask, ref)
+        assert cnt == int(ref.sum())
+    assert cnt > 0
+
+
+def test_weak_anchoring_fp32_cholesteric64():
+    say("case: 48^3 fp32 cholesteric, fixed homeotropic a=8, 60 steps")
+    L = 48
+    q0 = 2 * math.pi / 24
+    prm = dict(NEM, q0=q0)
+    col = dict(pos=(24.0, 24.0, 24.0), a0=8.0, anchoring="normal", W=math.inf)
+    Q0 = inputs.helix_q(L, L, L, q0, inputs.Q_INIT)
+    r = run_pair((L, L, L), prm, 60, "fp32", colloid=col, Q0=Q0, hist=True)
+    check(r, 1e-5, 1e-5, tol_force=1e-3)
+
+
+def test_numeric_error_is_reported():
+    from paper_1102_2193_amd import lc
+    say("case: NaN injection")
+    L = 16
+    ctx = lc.Context([dict(nx=L, precision="fp32", **NEM)])
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=1)
+    Q0[0, 3, 4, 5] = np.nan
+    ctx.set_Q(0, Q0)
+    ctx.step(2)
+    with pytest.raises(lc.LCError) as e:
+        ctx.get_Q(0)
+    assert e.value.code == 4
+
+
+def test_full_size_drag128_against_oracle():
+    # the benchmark's workload and launch configuration (128^3 fp32, colloid
+    # a = 8 moving along x, normal anchoring W = 0.01), a few steps compared
+    # over the whole field
+    from paper_1102_2193_amd import lc
+    say("case: 128^3 fp32 drag workload, 4 steps vs oracle")
+    L = 128
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=2)
+    col = dict(pos=(64.0, 64.0, 64.0), a0=8.0, anchoring="normal", W=0.01, S0=0.5, vel=(1e-3, 0, 0),
+               motion=lc.PRESCRIBED)
+    r = run_pair((L, L, L), NEM, 4, "fp32", colloid=col, Q0=Q0, hist=True)
+    check(r, 1e-5, 1e-5, tol_force=1e-3)
+    # mass is conserved to FP32 round-off at full size
+    d = r["ctx"].diag(0)
+    assert d["mass"] == pytest.approx(r["ref"].diag()["mass"], rel=1e-6)
