@@ -76,13 +76,16 @@ def run_pair(dims, prm, steps, precision, colloid=None, Q0=None, tile=None, grap
     return out
 
 
-def check(r, tol_q, tol_f, tol_u=None, tol_force=None, w_dev=True):
+def check(r, tol_q, tol_f, tol_u=None, tol_force=None):
+    """tol_f None: the fluid is off (hydro = 0) and f is not part of the state."""
     m = r["fluid"]
     eq = max(rel_inf(r["Q"], r["Qr"], m), rel_l2(r["Q"], r["Qr"], m))
-    ef = max(rel_inf(r["f"], r["fr"], m), rel_l2(r["f"], r["fr"], m))
-    say("   rel err Q %.3e  f %.3e" % (eq, ef))
+    say("   rel err Q %.3e" % eq)
     assert eq < tol_q, ("Q", eq)
-    assert ef < tol_f, ("f", ef)
+    if tol_f is not None:
+        ef = max(rel_inf(r["f"], r["fr"], m), rel_l2(r["f"], r["fr"], m))
+        say("   rel err f %.3e" % ef)
+        assert ef < tol_f, ("f", ef)
     if tol_u is not None:
         eu = rel_inf(r["u"], r["ur"], m)
         say("   rel err u %.3e" % eu)
@@ -92,9 +95,13 @@ def check(r, tol_q, tol_f, tol_u=None, tol_force=None, w_dev=True):
             F, Fr = r["H"], r["Hr"]
         else:
             F, Fr = r["F"][None], r["Fr"][None]
-        ef = np.linalg.norm(F - Fr) / max(np.linalg.norm(Fr), 1e-9)
-        say("   rel err force %.3e (|F| %.3e)" % (ef, np.linalg.norm(Fr)))
-        assert ef < tol_force, ("force", ef)
+        # A force that vanishes by symmetry leaves only the effect of the FP32
+        # field error (~1e-9 per population, coherent over thousands of
+        # links: ~1e-7 per step): absolute floor of 1e-6 per step.
+        err = np.linalg.norm(F - Fr)
+        bound = max(tol_force * np.linalg.norm(Fr), 1e-6 * math.sqrt(F.shape[0]))
+        say("   force err %.3e bound %.3e (|F| %.3e)" % (err, bound, np.linalg.norm(Fr)))
+        assert err <= bound, ("force", err, bound)
 
 
 CFG0 = dict(pos=(16.0, 16.0, 16.0), a0=4.0, anchoring="planar", W=0.01, S0=0.5)
@@ -136,7 +143,8 @@ def test_fp64_brute_force_modes(anch, motion, hydro):
     Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=21, noise=0.02, director=(1, 0.2, 0.4))
     r = run_pair((L, L, L), prm, 30, "fp64", colloid=col, Q0=Q0, hist=True)
     assert np.all(np.isfinite(r["Q"]))
-    check(r, 1e-10, 1e-12, tol_u=1e-8 if hydro else None, tol_force=1e-8 if hydro else None)
+    check(r, 1e-10, 1e-12 if hydro else None, tol_u=1e-8 if hydro else None,
+          tol_force=1e-8 if hydro else None)
     if motion:
         c = r["ctx"].get_colloid(0)
         oc = r["ref"].get_colloid()
