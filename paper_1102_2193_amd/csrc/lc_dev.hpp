@@ -126,90 +126,115 @@ struct Mat {
         Gamma((R)B.Gamma), tau((R)B.tau), rho0((R)B.rho0) {}
 };
 
-// Molecular field H (Eq. 2 applied to Eq. 1) and, if wanted, the stress P
-// of Eq. (4) without the fluid pressure rho c_s^2, at one node from its own
-// Q and the six face neighbours.  Central first derivatives, compact
-// Laplacian.  Chiral terms: H gains -2 K q0 (M + M^T) - 4 K q0^2 Q with
-// M_ab = e_agd d_g Q_db; P = f I + 2 xi (Q + I/3) Q:H - xi (H A + A H)
-// - E + QH - HQ, E_ab = K d_aQ:d_bQ + 2 K q0 e_bjk (d_aQ Q)_jk, and f the
-// one-constant free-energy density.
-template <typename R, bool WANT_P>
-__device__ inline void field_and_stress(const Mat<R>& p, const R c5[5], const R xp[5],
-                                        const R xm[5], const R yp[5], const R ym[5],
-                                        const R zp[5], const R zm[5], R H5[5], R P[9]) {
-  R q[3][3], d[3][3][3], lap[3][3];
-  full5(c5, q);
-  {
-    R a[3][3], b[3][3];
-    full5(xp, a); full5(xm, b);
-    for (int i = 0; i < 3; i++)
-      for (int j = 0; j < 3; j++) { d[0][i][j] = (R)0.5 * (a[i][j] - b[i][j]); lap[i][j] = a[i][j] + b[i][j]; }
-    full5(yp, a); full5(ym, b);
-    for (int i = 0; i < 3; i++)
-      for (int j = 0; j < 3; j++) { d[1][i][j] = (R)0.5 * (a[i][j] - b[i][j]); lap[i][j] += a[i][j] + b[i][j]; }
-    full5(zp, a); full5(zm, b);
-    for (int i = 0; i < 3; i++)
-      for (int j = 0; j < 3; j++) {
-        d[2][i][j] = (R)0.5 * (a[i][j] - b[i][j]);
-        lap[i][j] += a[i][j] + b[i][j] - (R)6 * q[i][j];
-      }
+// Local stencil quantities at one node from its own Q and the six face
+// neighbours: Q, central first derivatives d[g] = D0_g Q and the compact
+// Laplacian, each as five stored components.
+template <typename R>
+struct Stencil {
+  R q[5], d[3][5], lap[5];
+};
+
+template <typename R>
+__device__ inline void stencil5(const R c5[5], const R xp[5], const R xm[5], const R yp[5], const R ym[5],
+                                const R zp[5], const R zm[5], Stencil<R>& st) {
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    st.q[k] = c5[k];
+    st.d[0][k] = (R)0.5 * (xp[k] - xm[k]);
+    st.d[1][k] = (R)0.5 * (yp[k] - ym[k]);
+    st.d[2][k] = (R)0.5 * (zp[k] - zm[k]);
+    st.lap[k] = ((xp[k] + xm[k]) + (yp[k] + ym[k])) + (zp[k] + zm[k]) - (R)6 * c5[k];
   }
-  R q2[3][3];
+}
+
+// Full contraction A:B of two traceless symmetric tensors in five components.
+template <typename R>
+__device__ inline R dot5(const R a[5], const R b[5]) {
+  return (R)2 * (a[0] * b[0] + a[3] * b[3] + a[1] * b[1] + a[2] * b[2] + a[4] * b[4]) + a[0] * b[3] +
+         a[3] * b[0];
+}
+
+// Molecular field H (Eq. 2 applied to Eq. 1): bulk part
+// -A0(1-g/3)Q + A0 g (Q.Q - Tr(Q^2)/3 I) - A0 g Tr(Q^2) Q, plus K lap Q and,
+// for a cholesteric, -2 K q0 (M + M^T) - 4 K q0^2 Q with M_ab = e_agd d_g Q_db.
+// Also returns Q.Q (symmetric, 3x3) and Tr(Q^2) for the stress.
+template <typename R, bool CHIRAL>
+__device__ inline void mol_field(const Mat<R>& p, const Stencil<R>& st, R q[3][3], R q2[3][3], R& tr2,
+                                 R M[3][3], R h[3][3]) {
+  full5(st.q, q);
   for (int i = 0; i < 3; i++)
-    for (int j = 0; j < 3; j++) q2[i][j] = q[i][0] * q[0][j] + q[i][1] * q[1][j] + q[i][2] * q[2][j];
-  const R tr2 = q2[0][0] + q2[1][1] + q2[2][2];
-  // M_ab = e_agd d_g Q_db
-  R M[3][3];
-  for (int b = 0; b < 3; b++) {
-    M[0][b] = d[1][2][b] - d[2][1][b];
-    M[1][b] = d[2][0][b] - d[0][2][b];
-    M[2][b] = d[0][1][b] - d[1][0][b];
-  }
+    for (int j = i; j < 3; j++) q2[i][j] = q2[j][i] = q[i][0] * q[0][j] + q[i][1] * q[1][j] + q[i][2] * q[2][j];
+  tr2 = dot5(st.q, st.q);
+  R lap[3][3];
+  full5(st.lap, lap);
   const R A0 = p.A0, g = p.gamma, K = p.K, q0 = p.q0;
-  const R cq = -A0 * ((R)1 - g / (R)3) - A0 * g * tr2 - (R)4 * K * q0 * q0;
-  R h[3][3];
-  for (int i = 0; i < 3; i++)
-    for (int j = 0; j < 3; j++)
-      h[i][j] = cq * q[i][j] + A0 * g * (q2[i][j] - (i == j ? tr2 / (R)3 : (R)0)) + K * lap[i][j] -
-                (R)2 * K * q0 * (M[i][j] + M[j][i]);
-  H5[0] = h[0][0]; H5[1] = h[0][1]; H5[2] = h[0][2]; H5[3] = h[1][1]; H5[4] = h[1][2];
-  if (!WANT_P) return;
-  // one-constant free-energy density
-  R tr3 = (R)0, qm = (R)0, dd = (R)0;
-  for (int i = 0; i < 3; i++)
-    for (int j = 0; j < 3; j++) {
-      tr3 += q[i][j] * q2[j][i];
-      qm += q[i][j] * M[i][j];
-    }
-  R E1[3][3];
-  for (int a = 0; a < 3; a++)
-    for (int b = a; b < 3; b++) {
-      R s = (R)0;
-      for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) s += d[a][i][j] * d[b][i][j];
-      E1[a][b] = E1[b][a] = s;
-    }
-  dd = E1[0][0] + E1[1][1] + E1[2][2];
-  const R fe = (R)0.5 * A0 * ((R)1 - g / (R)3) * tr2 - A0 * g / (R)3 * tr3 +
-               (R)0.25 * A0 * g * tr2 * tr2 + (R)0.5 * K * dd + (R)2 * K * q0 * qm +
-               (R)2 * K * q0 * q0 * tr2;
-  R qh[3][3];
-  for (int i = 0; i < 3; i++)
-    for (int j = 0; j < 3; j++) qh[i][j] = q[i][0] * h[0][j] + q[i][1] * h[1][j] + q[i][2] * h[2][j];
-  const R trqh = qh[0][0] + qh[1][1] + qh[2][2];
-  const R xi = p.xi;
-  for (int a = 0; a < 3; a++) {
-    // axial vector of the antisymmetric part of (d_a Q) Q
-    R dq[3][3];
-    for (int i = 0; i < 3; i++)
-      for (int j = 0; j < 3; j++)
-        dq[i][j] = d[a][i][0] * q[0][j] + d[a][i][1] * q[1][j] + d[a][i][2] * q[2][j];
-    const R ax[3] = {dq[1][2] - dq[2][1], dq[2][0] - dq[0][2], dq[0][1] - dq[1][0]};
+  R cq = -A0 * ((R)1 - g / (R)3) - A0 * g * tr2;
+  if (CHIRAL) {
+    R d[3][3][3];
+    full5(st.d[0], d[0]); full5(st.d[1], d[1]); full5(st.d[2], d[2]);
     for (int b = 0; b < 3; b++) {
-      const R E = K * E1[a][b] + (R)2 * K * q0 * ax[b];
-      P[3 * a + b] = (a == b ? fe : (R)0) + (R)2 * xi * (q[a][b] + (a == b ? (R)1 / (R)3 : (R)0)) * trqh -
-                     (R)2 * xi / (R)3 * h[a][b] - E + ((R)1 - xi) * qh[a][b] - ((R)1 + xi) * qh[b][a];
+      M[0][b] = d[1][2][b] - d[2][1][b];
+      M[1][b] = d[2][0][b] - d[0][2][b];
+      M[2][b] = d[0][1][b] - d[1][0][b];
     }
+    cq -= (R)4 * K * q0 * q0;
+  }
+  const R t3 = tr2 / (R)3;
+  for (int i = 0; i < 3; i++)
+    for (int j = i; j < 3; j++) {
+      R v = cq * q[i][j] + A0 * g * (q2[i][j] - (i == j ? t3 : (R)0)) + K * lap[i][j];
+      if (CHIRAL) v -= (R)2 * K * q0 * (M[i][j] + M[j][i]);
+      h[i][j] = h[j][i] = v;
+    }
+}
+
+// One-constant free-energy density f (Eq. 1 with the P:96 equivalence):
+// bulk + K/2 |dQ|^2 + 2 K q0 Q:M + 2 K q0^2 |Q|^2.
+template <typename R, bool CHIRAL>
+__device__ inline R energy_density(const Mat<R>& p, const Stencil<R>& st, const R q[3][3], const R q2[3][3],
+                                   R tr2, const R M[3][3]) {
+  R tr3 = (R)0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) tr3 += q[i][j] * q2[j][i];
+  const R dd = dot5(st.d[0], st.d[0]) + dot5(st.d[1], st.d[1]) + dot5(st.d[2], st.d[2]);
+  const R A0 = p.A0, g = p.gamma, K = p.K;
+  R fe = (R)0.5 * A0 * ((R)1 - g / (R)3) * tr2 - A0 * g / (R)3 * tr3 + (R)0.25 * A0 * g * tr2 * tr2 +
+         (R)0.5 * K * dd;
+  if (CHIRAL) {
+    R qm = (R)0;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) qm += q[i][j] * M[i][j];
+    fe += (R)2 * K * p.q0 * qm + (R)2 * K * p.q0 * p.q0 * tr2;
+  }
+  return fe;
+}
+
+// Stress of Eq. (4) without the fluid pressure rho c_s^2, column b only:
+// P_ab = f d_ab + 2 xi (Q + I/3)_ab Q:H - (2 xi/3) H_ab - E_ab
+//        + (1 - xi)(QH)_ab - (1 + xi)(QH)_ba,
+// E_ab = K d_aQ:d_bQ + 2 K q0 e_bjk (d_aQ Q)_jk.
+template <typename R, bool CHIRAL, int b>
+__device__ inline void stress_col(const Mat<R>& p, const Stencil<R>& st, const R q[3][3], const R h[3][3], R fe,
+                                  R out[3]) {
+  R d[3][3][3];
+  full5(st.d[0], d[0]); full5(st.d[1], d[1]); full5(st.d[2], d[2]);
+  R trqh = (R)0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) trqh += q[i][j] * h[i][j];
+  const R K = p.K, xi = p.xi;
+  constexpr int b1 = b == 2 ? 0 : b + 1, b2 = b == 0 ? 2 : b - 1;
+  for (int a = 0; a < 3; a++) {
+    const R qh_ab = q[a][0] * h[0][b] + q[a][1] * h[1][b] + q[a][2] * h[2][b];
+    const R qh_ba = q[b][0] * h[0][a] + q[b][1] * h[1][a] + q[b][2] * h[2][a];
+    R E = K * dot5(st.d[a], st.d[b]);
+    if (CHIRAL) {
+      // (d_a Q Q)_{b1 b2} - (d_a Q Q)_{b2 b1}
+      R ax = (R)0;
+      for (int n = 0; n < 3; n++) ax += d[a][b1][n] * q[n][b2] - d[a][b2][n] * q[n][b1];
+      E += (R)2 * K * p.q0 * ax;
+    }
+    out[a] = (a == b ? fe + (R)2 * xi * (q[a][b] + (R)1 / (R)3) * trqh : (R)2 * xi * q[a][b] * trqh) -
+             (R)2 * xi / (R)3 * h[a][b] - E + ((R)1 - xi) * qh_ab - ((R)1 + xi) * qh_ba;
   }
 }
 

@@ -14,6 +14,8 @@
 // Populations are stored shifted, f~ = f - w_i, which keeps FP32 rounding
 // relative to the small deviations from rest.  Every array is
 // structure-of-arrays [component][site] over the concatenation of all boxes.
+#include <type_traits>
+
 #include "lc_kernels.hpp"
 
 namespace lc {
@@ -45,152 +47,272 @@ __device__ inline void block_sum(double (&v)[NV], double* sred, double* out) {
 // ---------------------------------------------------------------------
 // fused step
 // ---------------------------------------------------------------------
+
+// Element idx of an array whose byte size fits in 32 bits: the byte offset
+// is formed in 32 bits so that the access can use a scalar base address.
+template <typename T>
+__device__ inline const T* at32(const T* base, unsigned idx) {
+  return (const T*)((const char*)base + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ inline T* at32(T* base, unsigned idx) {
+  return (T*)((char*)base + idx * (unsigned)sizeof(T));
+}
+
+// Barrier that orders LDS only: global loads issued before it stay in
+// flight (the populations are requested at kernel entry).
+__device__ inline void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Block = one TX x TY x TZ tile, one thread per node.  LDS holds Q with a
+// halo of two nodes, solid flags, the velocity with a halo of one, the full
+// stress P at the tile's nodes and, on the six face layers around the tile,
+// only the column of P that the neighbouring face difference uses.
+// Site offsets are 32-bit and added to per-component base pointers held in
+// scalar registers.  Blocks whose stencils cannot reach the colloid take a
+// path without any solid-node test.
+// LDS of one block of the fused kernel.
+template <typename R, int TX, int TY, int TZ>
+struct StepSmem {
+  static constexpr int NT = TX * TY * TZ;
+  static constexpr int QN = (TX + 4) * (TY + 4) * (TZ + 4);
+  static constexpr int PN = (TX + 2) * (TY + 2) * (TZ + 2);
+  static constexpr int NF = 2 * (TX * TY + TY * TZ + TX * TZ);
+  R Q[5 * QN];            // Q with a halo of two nodes
+  R Pi[9 * NT];           // full stress at the tile's nodes
+  R Ph[3 * NF];           // one column of the stress on the face layers
+  R U[3 * PN];            // velocity with a halo of one node
+  unsigned char S[QN];    // solid flags of the Q box
+  double red[(NT / 64) * 12];
+};
+
+template <typename R, int TX, int TY, int TZ, bool CHIRAL>
+__device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const StepPtrs<R>& a,
+                                          StepSmem<R, TX, TY, TZ>& sm);
+
+// One launch serves every box of the batch; each block takes the nematic or
+// the cholesteric specialisation from its own box, so a box gives the same
+// bits whether it runs alone or in a batch.
 template <typename R, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(TX* TY* TZ)
     k_step(const BoxDev* __restrict__ boxes, const int2* __restrict__ tiles, StepPtrs<R> a) {
-  constexpr int NT = TX * TY * TZ;
-  constexpr int QX = TX + 4, QY = TY + 4, QZ = TZ + 4, QN = QX * QY * QZ;
-  constexpr int PX = TX + 2, PY = TY + 2, PZ = TZ + 2, PN = PX * PY * PZ;
-  constexpr int NF = 2 * (TX * TY + TY * TZ + TX * TZ);
-  constexpr int QSY = QX, QSZ = QX * QY;     // strides in the Q box
-  constexpr int PSY = PX, PSZ = PX * PY;     // strides in the P box
-
-  __shared__ R sQ[5 * QN];
-  __shared__ R sP[9 * PN];
-  __shared__ R sH[5 * NT];
-  __shared__ R sU[3 * PN];
-  __shared__ unsigned char sS[QN];
-  __shared__ double sred[(NT / 64) * 12];
-
   const int2 tt = tiles[blockIdx.x];
   if (tt.x < 0) return;  // padding entry (whole block)
   const BoxDev& B = boxes[tt.x];
+  __shared__ StepSmem<R, TX, TY, TZ> sm;
+  if (B.q0 != 0.0) step_tile<R, TX, TY, TZ, true>(B, tt, a, sm);
+  else step_tile<R, TX, TY, TZ, false>(B, tt, a, sm);
+}
+
+template <typename R, int TX, int TY, int TZ, bool CHIRAL>
+__device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const StepPtrs<R>& a,
+                                          StepSmem<R, TX, TY, TZ>& sm) {
+  constexpr int NT = TX * TY * TZ;
+  constexpr int QX = TX + 4, QY = TY + 4, QZ = TZ + 4, QN = QX * QY * QZ;
+  constexpr int PX = TX + 2, PY = TY + 2, PZ = TZ + 2, PN = PX * PY * PZ;
+  constexpr int NFZ = TX * TY, NFX = TY * TZ, NFY = TX * TZ, NF = 2 * (NFZ + NFX + NFY);
+  constexpr int QSY = QX, QSZ = QX * QY;     // strides in the Q box
+  constexpr int PSY = PX, PSZ = PX * PY;     // strides in the velocity box
+
+  R* const sQ = sm.Q;
+  R* const sPi = sm.Pi;
+  R* const sPh = sm.Ph;
+  R* const sU = sm.U;
+  unsigned char* const sS = sm.S;
+  double* const sred = sm.red;
+
   const int nx = B.nx, ny = B.ny, nz = B.nz, hydro = B.hydro;
+  const int nxy = nx * ny;
   const int tix = tt.y % B.ntx, tiy = (tt.y / B.ntx) % B.nty, tiz = tt.y / (B.ntx * B.nty);
   const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
-  const long long off = B.off;
+  const unsigned off = (unsigned)B.off;
   const long long NS = a.nsites;
   const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
   const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, TZ + 4);
+  // a single conditional correction wraps every halo coordinate
+  const bool wide = nx >= TX + 2 && ny >= TY + 2 && nz >= TZ + 2;
   const Mat<R> mp(B);
   const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+  const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+  const bool inbox = gx < nx && gy < ny && gz < nz;
+  const unsigned g = off + (unsigned)(gx + nx * gy + nxy * gz);
 
-  // Phase 1: Q with a halo of two nodes, solid flags.
-  for (int s = tid; s < QN; s += NT) {
-    const int lx = s % QX, ly = (s / QX) % QY, lz = s / QSZ;
-    const int gx = wrapc(x0 - 2 + lx, nx), gy = wrapc(y0 - 2 + ly, ny), gz = wrapc(z0 - 2 + lz, nz);
-    const long long g = off + gx + (long long)nx * (gy + (long long)ny * gz);
+  auto wrap3 = [&](int& wx, int& wy, int& wz) {
+    if (wide) {
+      wx += wx < 0 ? nx : 0; wx -= wx >= nx ? nx : 0;
+      wy += wy < 0 ? ny : 0; wy -= wy >= ny ? ny : 0;
+      wz += wz < 0 ? nz : 0; wz -= wz >= nz ? nz : 0;
+    } else {
+      wx = wrapc(wx, nx); wy = wrapc(wy, ny); wz = wrapc(wz, nz);
+    }
+  };
+
+  // populations of the own node, requested first so that their latency
+  // overlaps the stencil phases
+  R f[19];
+  if (hydro && inbox) {
 #pragma unroll
-    for (int c = 0; c < 5; c++) sQ[c * QN + s] = a.Qin[c * NS + g];
-    sS[s] = near ? (unsigned char)inside(B, Rc, gx, gy, gz) : (unsigned char)0;
+    for (int i = 0; i < 19; i++) f[i] = __builtin_nontemporal_load(at32(a.fin + i * NS, g));
   }
-  __syncthreads();
 
-  // Phase 2: H and P at the tile and its face halo (plus-shaped region);
-  // velocity of the last collision with a halo of one (rigid-body motion at
-  // solid nodes).
-  for (int p = tid; p < NT + NF; p += NT) {
-    int px, py, pz;
-    if (p < NT) {
-      px = p % TX + 1; py = (p / TX) % TY + 1; pz = p / (TX * TY) + 1;
-    } else {
-      int h = p - NT;
-      if (h < 2 * TX * TY) {
-        const int r = h % (TX * TY);
-        px = r % TX + 1; py = r / TX + 1; pz = h < TX * TY ? 0 : PZ - 1;
-      } else if ((h -= 2 * TX * TY) < 2 * TY * TZ) {
-        const int r = h % (TY * TZ);
-        py = r % TY + 1; pz = r / TY + 1; px = h < TY * TZ ? 0 : PX - 1;
-      } else {
-        h -= 2 * TY * TZ;
-        const int r = h % (TX * TZ);
-        px = r % TX + 1; pz = r / TX + 1; py = h < TX * TZ ? 0 : PY - 1;
-      }
-    }
-    const int qc = (pz + 1) * QSZ + (py + 1) * QSY + (px + 1);
-    if (sS[qc]) continue;
-    R c5[5], xp[5], xm[5], yp[5], ym[5], zp[5], zm[5], H5[5], P9[9];
+  // Phase 1: Q with a halo of two nodes, velocity with a halo of one.
+  for (int s = tid; s < QN; s += NT) {
+    const int qz = s / QSZ, rem = s - qz * QSZ, qy = rem / QX, qx = rem - qy * QX;
+    int wx = x0 - 2 + qx, wy = y0 - 2 + qy, wz = z0 - 2 + qz;
+    wrap3(wx, wy, wz);
+    const unsigned gs = off + (unsigned)(wx + nx * wy + nxy * wz);
 #pragma unroll
-    for (int c = 0; c < 5; c++) {
-      const R* q = sQ + c * QN + qc;
-      c5[c] = q[0]; xp[c] = q[1]; xm[c] = q[-1]; yp[c] = q[QSY]; ym[c] = q[-QSY];
-      zp[c] = q[QSZ]; zm[c] = q[-QSZ];
-    }
-    if (hydro) {
-      field_and_stress<R, true>(mp, c5, xp, xm, yp, ym, zp, zm, H5, P9);
-      const int pc = pz * PSZ + py * PSY + px;
-#pragma unroll
-      for (int k = 0; k < 9; k++) sP[k * PN + pc] = P9[k];
-    } else {
-      field_and_stress<R, false>(mp, c5, xp, xm, yp, ym, zp, zm, H5, P9);
-    }
-    if (p < NT) {
-#pragma unroll
-      for (int c = 0; c < 5; c++) sH[c * NT + p] = H5[c];
-    }
+    for (int c = 0; c < 5; c++) sQ[c * QN + s] = *at32(a.Qin + c * NS, gs);
+    sS[s] = near ? (unsigned char)inside(B, Rc, wx, wy, wz) : (unsigned char)0;
   }
   if (hydro) {
     for (int s = tid; s < PN; s += NT) {
-      const int lx = s % PX, ly = (s / PX) % PY, lz = s / PSZ;
-      const int gx = wrapc(x0 - 1 + lx, nx), gy = wrapc(y0 - 1 + ly, ny), gz = wrapc(z0 - 1 + lz, nz);
-      const int qs = (lz + 1) * QSZ + (ly + 1) * QSY + (lx + 1);
-      if (sS[qs]) {
+      const int uz = s / PSZ, rem = s - uz * PSZ, uy = rem / PX, ux = rem - uy * PX;
+      int wx = x0 - 1 + ux, wy = y0 - 1 + uy, wz = z0 - 1 + uz;
+      wrap3(wx, wy, wz);
+      const unsigned gs = off + (unsigned)(wx + nx * wy + nxy * wz);
+#pragma unroll
+      for (int c = 0; c < 3; c++) sU[c * PN + s] = *at32(a.uin + c * NS, gs);
+    }
+  }
+  lds_sync();
+
+  // Phase 2a: own node: H (kept in registers) and the full stress.
+  const int qc = (lz + 2) * QSZ + (ly + 2) * QSY + (lx + 2);
+  const bool fluid = !sS[qc];
+  R h5[5];
+  {
+    Stencil<R> st;
+    {
+      R c5[5], xp[5], xm[5], yp[5], ym[5], zp[5], zm[5];
+#pragma unroll
+      for (int c = 0; c < 5; c++) {
+        const R* q = sQ + c * QN + qc;
+        c5[c] = q[0]; xp[c] = q[1]; xm[c] = q[-1]; yp[c] = q[QSY]; ym[c] = q[-QSY];
+        zp[c] = q[QSZ]; zm[c] = q[-QSZ];
+      }
+      stencil5(c5, xp, xm, yp, ym, zp, zm, st);
+    }
+    R q[3][3], q2[3][3], tr2, M[3][3], h[3][3];
+    mol_field<R, CHIRAL>(mp, st, q, q2, tr2, M, h);
+    h5[0] = h[0][0]; h5[1] = h[0][1]; h5[2] = h[0][2]; h5[3] = h[1][1]; h5[4] = h[1][2];
+    if (hydro && fluid) {
+      const R fe = energy_density<R, CHIRAL>(mp, st, q, q2, tr2, M);
+      R col[3][3];
+      stress_col<R, CHIRAL, 0>(mp, st, q, h, fe, col[0]);
+      stress_col<R, CHIRAL, 1>(mp, st, q, h, fe, col[1]);
+      stress_col<R, CHIRAL, 2>(mp, st, q, h, fe, col[2]);
+#pragma unroll
+      for (int b = 0; b < 3; b++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) sPi[(3 * c + b) * NT + tid] = col[b][c];
+    }
+  }
+  // Phase 2b: face layers: the one column of P each needs.
+  if (hydro) {
+    for (int hsite = tid; hsite < NF; hsite += NT) {
+      int px, py, pz, b;
+      int hh = hsite;
+      if (hh < 2 * NFZ) {
+        const int r = hh % NFZ;
+        px = r % TX + 1; py = r / TX + 1; pz = hh < NFZ ? 0 : PZ - 1; b = 2;
+      } else if ((hh -= 2 * NFZ) < 2 * NFX) {
+        const int r = hh % NFX;
+        py = r % TY + 1; pz = r / TY + 1; px = hh < NFX ? 0 : PX - 1; b = 0;
+      } else {
+        hh -= 2 * NFX;
+        const int r = hh % NFY;
+        px = r % TX + 1; pz = r / TX + 1; py = hh < NFY ? 0 : PY - 1; b = 1;
+      }
+      const int qh = (pz + 1) * QSZ + (py + 1) * QSY + (px + 1);
+      if (near && sS[qh]) continue;
+      Stencil<R> st;
+      {
+        R c5[5], xp[5], xm[5], yp[5], ym[5], zp[5], zm[5];
+#pragma unroll
+        for (int c = 0; c < 5; c++) {
+          const R* q = sQ + c * QN + qh;
+          c5[c] = q[0]; xp[c] = q[1]; xm[c] = q[-1]; yp[c] = q[QSY]; ym[c] = q[-QSY];
+          zp[c] = q[QSZ]; zm[c] = q[-QSZ];
+        }
+        stencil5(c5, xp, xm, yp, ym, zp, zm, st);
+      }
+      R q[3][3], q2[3][3], tr2, M[3][3], h[3][3];
+      mol_field<R, CHIRAL>(mp, st, q, q2, tr2, M, h);
+      const R fe = energy_density<R, CHIRAL>(mp, st, q, q2, tr2, M);
+      R col[3];
+      if (b == 0) stress_col<R, CHIRAL, 0>(mp, st, q, h, fe, col);
+      else if (b == 1) stress_col<R, CHIRAL, 1>(mp, st, q, h, fe, col);
+      else stress_col<R, CHIRAL, 2>(mp, st, q, h, fe, col);
+#pragma unroll
+      for (int c = 0; c < 3; c++) sPh[c * NF + hsite] = col[c];
+    }
+    // rigid-body velocity at solid nodes of the velocity box
+    if (near) {
+      for (int s = tid; s < PN; s += NT) {
+        const int uz = s / PSZ, rem = s - uz * PSZ, uy = rem / PX, ux = rem - uy * PX;
+        if (!sS[(uz + 1) * QSZ + (uy + 1) * QSY + (ux + 1)]) continue;
+        int wx = x0 - 1 + ux, wy = y0 - 1 + uy, wz = z0 - 1 + uz;
+        wrap3(wx, wy, wz);
         double r[3], ub[3];
-        rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
+        rel_pos(B, Rc, (double)wx, (double)wy, (double)wz, r);
         rigid_vel(B, r, ub);
 #pragma unroll
         for (int c = 0; c < 3; c++) sU[c * PN + s] = (R)ub[c];
-      } else {
-        const long long g = off + gx + (long long)nx * (gy + (long long)ny * gz);
-#pragma unroll
-        for (int c = 0; c < 3; c++) sU[c * PN + s] = a.uin[c * NS + g];
       }
     }
   }
-  __syncthreads();
+  lds_sync();
 
   // Phase 3: own node.
-  const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-  const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-  const int qc = (lz + 2) * QSZ + (ly + 2) * QSY + (lx + 2);
   const int pc = (lz + 1) * PSZ + (ly + 1) * PSY + (lx + 1);
-  const bool active = gx < nx && gy < ny && gz < nz && !sS[qc];
   double part[12];
 #pragma unroll
   for (int k = 0; k < 12; k++) part[k] = 0.0;
 
-  if (active) {
-    const long long g = off + gx + (long long)nx * (gy + (long long)ny * gz);
+  auto update = [&](auto near_tag) {
+    constexpr bool NEAR = decltype(near_tag)::value;
     const int qst[3] = {1, QSY, QSZ}, pst[3] = {1, PSY, PSZ};
     R q5[5], dQ[5];
 #pragma unroll
     for (int c = 0; c < 5; c++) {
       q5[c] = sQ[c * QN + qc];
-      dQ[c] = mp.Gamma * sH[c * NT + tid];
+      dQ[c] = mp.Gamma * h5[c];
     }
     R F[3] = {(R)0, (R)0, (R)0};
+    bool solid_nb[19];
+#pragma unroll
+    for (int i = 0; i < 19; i++) solid_nb[i] = NEAR ? (bool)sS[qc + cx(i) + cy(i) * QSY + cz(i) * QSZ] : false;
     if (hydro) {
       // force on the fluid: differences of P between opposite faces
-      R Pc[9];
-#pragma unroll
-      for (int k = 0; k < 9; k++) Pc[k] = sP[k * PN + pc];
+      const int loc[3] = {lx, ly, lz}, ext[3] = {TX, TY, TZ}, ist[3] = {1, TX, TX * TY};
+      // face-layer index of the neighbour across the + and - faces
+      const int hp[3] = {2 * NFZ + NFX + ly + lz * TY, 2 * NFZ + 2 * NFX + NFY + lx + lz * TX, NFZ + lx + ly * TX};
+      const int hm[3] = {2 * NFZ + ly + lz * TY, 2 * NFZ + 2 * NFX + lx + lz * TX, lx + ly * TX};
 #pragma unroll
       for (int b = 0; b < 3; b++) {
-        const bool sp = sS[qc + qst[b]], sm = sS[qc - qst[b]];
+        const bool sp = solid_nb[2 * b + 1], sm = solid_nb[2 * b + 2];
+        const bool ip = loc[b] + 1 < ext[b], im = loc[b] > 0;
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-          const R pcv = Pc[3 * c + b];
-          const R pp = sp ? pcv : (R)0.5 * (pcv + sP[(3 * c + b) * PN + pc + pst[b]]);
-          const R pm = sm ? pcv : (R)0.5 * (pcv + sP[(3 * c + b) * PN + pc - pst[b]]);
+          const R pcv = sPi[(3 * c + b) * NT + tid];
+          const R pn = ip ? sPi[(3 * c + b) * NT + tid + ist[b]] : sPh[c * NF + hp[b]];
+          const R pmv = im ? sPi[(3 * c + b) * NT + tid - ist[b]] : sPh[c * NF + hm[b]];
+          const R pp = sp ? pcv : (R)0.5 * (pcv + pn);
+          const R pm = sm ? pcv : (R)0.5 * (pcv + pmv);
           F[c] += pp - pm;
         }
         // colloid force and torque from the solid-fluid faces
-        if (sp || sm) {
+        if (NEAR && (sp || sm)) {
 #pragma unroll
           for (int sg = 1; sg >= -1; sg -= 2) {
             if (sg > 0 ? !sp : !sm) continue;
             double ps[3], r[3];
-            for (int c = 0; c < 3; c++) ps[c] = -(double)sg * (double)Pc[3 * c + b];
+            for (int c = 0; c < 3; c++) ps[c] = -(double)sg * (double)sPi[(3 * c + b) * NT + tid];
             const double e[3] = {b == 0 ? 0.5 * sg : 0.0, b == 1 ? 0.5 * sg : 0.0, b == 2 ? 0.5 * sg : 0.0};
             rel_pos(B, Rc, gx + e[0], gy + e[1], gz + e[2], r);
             part[3] += ps[0]; part[4] += ps[1]; part[5] += ps[2];
@@ -217,25 +339,14 @@ __global__ void __launch_bounds__(TX* TY* TZ)
           um[c] = sU[c * PN + pc - pst[b]];
           W[c][b] = (R)0.5 * (up[c] - um[c]);
         }
-        R phip[5], phim[5];
-        if (!sS[qc + qst[b]]) {
-          const R uf = (R)0.5 * (u0[b] + up[b]);
+        const bool fp = !solid_nb[2 * b + 1], fm = !solid_nb[2 * b + 2];
+        const R ufp = (R)0.5 * (u0[b] + up[b]), ufm = (R)0.5 * (um[b] + u0[b]);
 #pragma unroll
-          for (int c = 0; c < 5; c++) phip[c] = uf * (uf >= (R)0 ? q5[c] : sQ[c * QN + qc + qst[b]]);
-        } else {
-#pragma unroll
-          for (int c = 0; c < 5; c++) phip[c] = (R)0;
+        for (int c = 0; c < 5; c++) {
+          const R phip = fp ? ufp * (ufp >= (R)0 ? q5[c] : sQ[c * QN + qc + qst[b]]) : (R)0;
+          const R phim = fm ? ufm * (ufm >= (R)0 ? sQ[c * QN + qc - qst[b]] : q5[c]) : (R)0;
+          dQ[c] -= phip - phim;
         }
-        if (!sS[qc - qst[b]]) {
-          const R uf = (R)0.5 * (um[b] + u0[b]);
-#pragma unroll
-          for (int c = 0; c < 5; c++) phim[c] = uf * (uf >= (R)0 ? sQ[c * QN + qc - qst[b]] : q5[c]);
-        } else {
-#pragma unroll
-          for (int c = 0; c < 5; c++) phim[c] = (R)0;
-        }
-#pragma unroll
-        for (int c = 0; c < 5; c++) dQ[c] -= phip[c] - phim[c];
       }
       R S5[5];
       corotation<R>(mp.xi, W, q5, S5);
@@ -246,50 +357,59 @@ __global__ void __launch_bounds__(TX* TY* TZ)
 #pragma unroll
     for (int c = 0; c < 5; c++) {
       const R v = q5[c] + dQ[c];
-      a.Qout[c * NS + g] = v;
+      __builtin_nontemporal_store(v, at32(a.Qout + c * NS, g));
       qn2 += v * v;
     }
     bool bad = !(qn2 < (R)100);
 
     if (hydro) {
-      // LB collision (BGK, Guo forcing with the half-force velocity)
-      R f[19];
+      // LB collision (BGK, Guo forcing with the half-force velocity); f holds
+      // f - w_i, so rho = 1 + sum and sum(w_i c_i) = 0
+      R rm1 = (R)0;
 #pragma unroll
-      for (int i = 0; i < 19; i++) f[i] = a.fin[i * NS + g];
-      R rm1 = (R)0, j[3] = {(R)0, (R)0, (R)0};
-#pragma unroll
-      for (int i = 0; i < 19; i++) {
-        rm1 += f[i];
-        if (cx(i)) j[0] += cx(i) > 0 ? f[i] : -f[i];
-        if (cy(i)) j[1] += cy(i) > 0 ? f[i] : -f[i];
-        if (cz(i)) j[2] += cz(i) > 0 ? f[i] : -f[i];
-      }
+      for (int i = 0; i < 19; i++) rm1 += f[i];
+      const R j[3] = {((f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10])) + ((f[11] - f[12]) + (f[13] - f[14])),
+                      ((f[3] - f[4]) + (f[7] - f[8]) - (f[9] - f[10])) + ((f[15] - f[16]) + (f[17] - f[18])),
+                      ((f[5] - f[6]) + (f[11] - f[12]) - (f[13] - f[14])) + ((f[15] - f[16]) - (f[17] - f[18]))};
       const R rho = (R)1 + rm1;
+      const R irho = (R)1 / rho;
       R u[3];
 #pragma unroll
-      for (int c = 0; c < 3; c++) u[c] = (j[c] + (R)0.5 * F[c]) / rho;
+      for (int c = 0; c < 3; c++) u[c] = (j[c] + (R)0.5 * F[c]) * irho;
       const R usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
       const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
       const R itau = (R)1 / mp.tau, fsrc = (R)1 - (R)0.5 * itau;
       bad = bad || !(usq < (R)0.09);
-      // neighbour indices for push streaming
-      const int gxp = gx + 1 == nx ? 0 : gx + 1, gxm = gx == 0 ? nx - 1 : gx - 1;
-      const int gyp = gy + 1 == ny ? 0 : gy + 1, gym = gy == 0 ? ny - 1 : gy - 1;
-      const int gzp = gz + 1 == nz ? 0 : gz + 1, gzm = gz == 0 ? nz - 1 : gz - 1;
-      const int xs[3] = {gxm, gx, gxp}, ys[3] = {gym, gy, gyp}, zs[3] = {gzm, gz, gzp};
+      R fs[19];
+      {
+        const R w = (R)wgt(0);
+        const R feq = w * rm1 + w * rho * ((R)-1.5 * usq);
+        const R src = w * ((R)-3 * uF);
+        fs[0] = f[0] - (f[0] - feq) * itau + fsrc * src;
+      }
 #pragma unroll
-      for (int i = 0; i < 19; i++) {
+      for (int i = 1; i < 19; i += 2) {
+        // the pair (i, i+1) has opposite velocities: shared even parts
         const R w = (R)wgt(i);
         const R cu = (R)cx(i) * u[0] + (R)cy(i) * u[1] + (R)cz(i) * u[2];
         const R cF = (R)cx(i) * F[0] + (R)cy(i) * F[1] + (R)cz(i) * F[2];
-        const R feq = w * rm1 + w * rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * usq);
-        const R src = w * ((R)3 * (cF - uF) + (R)9 * cu * cF);
-        const R fs = f[i] - (f[i] - feq) * itau + fsrc * src;
-        const int qn = qc + cx(i) + cz(i) * QSZ + cy(i) * QSY;
-        if (!sS[qn]) {
-          const long long gn = off + xs[cx(i) + 1] +
-                               (long long)nx * (ys[cy(i) + 1] + (long long)ny * zs[cz(i) + 1]);
-          a.fout[i * NS + gn] = fs;
+        const R even = w * rm1 + w * rho * ((R)4.5 * cu * cu - (R)1.5 * usq);
+        const R odd = w * rho * (R)3 * cu;
+        const R seven = w * ((R)9 * cu * cF - (R)3 * uF);
+        const R sodd = w * (R)3 * cF;
+        fs[i] = f[i] - (f[i] - (even + odd)) * itau + fsrc * (seven + sodd);
+        fs[i + 1] = f[i + 1] - (f[i + 1] - (even - odd)) * itau + fsrc * (seven - sodd);
+      }
+      // push streaming: 32-bit offsets of the 26 neighbours
+      const int dxp = gx + 1 == nx ? 1 - nx : 1, dxm = gx == 0 ? nx - 1 : -1;
+      const int dyp = gy + 1 == ny ? nx * (1 - ny) : nx, dym = gy == 0 ? nx * (ny - 1) : -nx;
+      const int dzp = gz + 1 == nz ? nxy * (1 - nz) : nxy, dzm = gz == 0 ? nxy * (nz - 1) : -nxy;
+      const int dxs[3] = {dxm, 0, dxp}, dys[3] = {dym, 0, dyp}, dzs[3] = {dzm, 0, dzp};
+#pragma unroll
+      for (int i = 0; i < 19; i++) {
+        if (!NEAR || !solid_nb[i]) {
+          const unsigned gn = g + (unsigned)(dxs[cx(i) + 1] + dys[cy(i) + 1] + dzs[cz(i) + 1]);
+          __builtin_nontemporal_store(fs[i], at32(a.fout + i * NS, gn));
         } else {
           // bounce-back on the link with the moving-wall correction
           double r[3], ub[3];
@@ -297,8 +417,8 @@ __global__ void __launch_bounds__(TX* TY* TZ)
           rigid_vel(B, r, ub);
           const double cub = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
           const double corr = 6.0 * wgt(i) * B.rho0 * cub;
-          a.fout[opp(i) * NS + g] = (R)((double)fs - corr);
-          const double m = 2.0 * ((double)fs + wgt(i)) - corr;
+          __builtin_nontemporal_store((R)((double)fs[i] - corr), at32(a.fout + opp(i) * NS, g));
+          const double m = 2.0 * ((double)fs[i] + wgt(i)) - corr;
           const double dp[3] = {m * cx(i), m * cy(i), m * cz(i)};
           part[0] += dp[0]; part[1] += dp[1]; part[2] += dp[2];
           part[6] += r[1] * dp[2] - r[2] * dp[1];
@@ -307,9 +427,14 @@ __global__ void __launch_bounds__(TX* TY* TZ)
         }
       }
 #pragma unroll
-      for (int c = 0; c < 3; c++) a.uout[c * NS + g] = u[c];
+      for (int c = 0; c < 3; c++) __builtin_nontemporal_store(u[c], at32(a.uout + c * NS, g));
     }
     if (bad) atomicOr(a.flag, 1);
+  };
+
+  if (inbox && fluid) {
+    if (near) update(std::true_type{});
+    else update(std::false_type{});
   }
 
   if (near) {
@@ -674,8 +799,8 @@ __global__ void __launch_bounds__(256) k_fill_f(R* f, long long NS, const double
 // launchers
 // ---------------------------------------------------------------------
 template <typename R>
-hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const StepPtrs<R>& a,
-                       hipStream_t s) {
+hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles,
+                       const StepPtrs<R>& a, hipStream_t s) {
 #define LC_TILE_CASE(ID, X, Y, Z) \
   case ID: k_step<R, X, Y, Z><<<nblk, X * Y * Z, 0, s>>>(boxes, tiles, a); break;
   if constexpr (sizeof(R) == 4) {
@@ -749,7 +874,8 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
 }
 
 #define LC_INST(R)                                                                                        \
-  template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const StepPtrs<R>&, hipStream_t); \
+  template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const StepPtrs<R>&,               \
+                                     hipStream_t);                                                          \
   template hipError_t launch_finalize<R>(int, int, BoxDev*, const double*, const double*, double*, double*,  \
                                          int, long long*, hipStream_t);                                     \
   template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, hipStream_t);           \

@@ -36,8 +36,8 @@ struct StepPtrs {
   X(2, 16, 4, 2)
 
 template <typename R>
-hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const StepPtrs<R>& a,
-                       hipStream_t s);
+hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles,
+                       const StepPtrs<R>& a, hipStream_t s);
 template <typename R>
 hipError_t launch_finalize(int tile, int nbox, BoxDev* boxes, const double* part, const double* epart,
                            double* force, double* hist, int cap, long long* count, hipStream_t s);

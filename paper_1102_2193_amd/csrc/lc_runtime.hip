@@ -354,6 +354,11 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
     for (int a = 0; a < 3; a++) B.body[a] = q.body_force[a];
   }
   c->nsites = off;
+  // kernels address each component with 32-bit byte offsets
+  if ((double)off * (c->prec == LC_FP32 ? 4.0 : 8.0) >= 4294967296.0) {
+    delete c;
+    return fail(nullptr, LC_EINVAL, "too many lattice sites for one context (32-bit offsets)");
+  }
   int rc = LC_OK;
   auto bail = [&](int code, const std::string& m) {
     g_create_error = m;
