@@ -44,6 +44,25 @@ __device__ inline void block_sum(double (&v)[NV], double* sred, double* out) {
   }
 }
 
+// Add the block sums of NV doubles per thread to acc[0..NV) (threads < NV);
+// acc is read back after a later barrier.
+template <int NT, int NV>
+__device__ inline void block_accumulate(double (&v)[NV], double* sred, double* acc) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    double s = wave_sum(v[k]);
+    if (lane == 0) sred[w * NV + k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int i = 0; i < NW; i++) s += sred[i * NV + threadIdx.x];
+    acc[threadIdx.x] += s;
+  }
+}
+
 // ---------------------------------------------------------------------
 // fused step
 // ---------------------------------------------------------------------
@@ -446,6 +465,459 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
 }
 
 // ---------------------------------------------------------------------
+// fused step, z-marching form
+// ---------------------------------------------------------------------
+
+// LDS of one block of the z-marching kernel: rolling planes.
+template <typename R, int TX, int TY>
+struct MarchSmem {
+  static constexpr int NT = TX * TY;
+  static constexpr int QPX = TX + 4, QP = (TX + 4) * (TY + 4);   // Q plane, halo 2
+  static constexpr int UPX = TX + 2, UP = (TX + 2) * (TY + 2);   // velocity plane, halo 1
+  static constexpr int NRX = 2 * TY, NRY = 2 * TX;               // face rings of a plane
+  static constexpr int PS = 6 * NT + 3 * (NRX + NRY);           // x and y stress columns of a plane
+  R Q[5][5 * QP];
+  unsigned char S[5][QP];
+  R U[4][3 * UP];
+  R P[2][PS];
+  double red[(NT / 64) * 12];
+  double acc[12];         // colloid force/torque accumulated over the planes
+};
+
+// Block = TX x TY columns marching through CZ planes in z, one thread per
+// column.  Each plane's stress is computed once per column (full at the
+// columns, the x or y column on the four face rows around the tile); the
+// z faces take their stress from the neighbouring planes' results held in
+// registers.  Planes of Q (halo 2) and u (halo 1) are loaded one step ahead
+// into registers and rotated through LDS, so one barrier per plane suffices.
+template <typename R, int TX, int TY, int CZ, bool CHIRAL>
+__device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const StepPtrs<R>& a,
+                                           MarchSmem<R, TX, TY>& sm);
+
+template <typename R, int TX, int TY, int CZ>
+__global__ void __launch_bounds__(TX* TY)
+    k_march(const BoxDev* __restrict__ boxes, const int2* __restrict__ tiles, StepPtrs<R> a) {
+  const int2 tt = tiles[blockIdx.x];
+  if (tt.x < 0) return;  // padding entry (whole block)
+  const BoxDev& B = boxes[tt.x];
+  __shared__ MarchSmem<R, TX, TY> sm;
+  if (B.q0 != 0.0) march_tile<R, TX, TY, CZ, true>(B, tt, a, sm);
+  else march_tile<R, TX, TY, CZ, false>(B, tt, a, sm);
+}
+
+template <typename R, int TX, int TY, int CZ, bool CHIRAL>
+__device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const StepPtrs<R>& a,
+                                           MarchSmem<R, TX, TY>& sm) {
+  using SM = MarchSmem<R, TX, TY>;
+  constexpr int NT = SM::NT, QPX = SM::QPX, QP = SM::QP, UPX = SM::UPX, UP = SM::UP;
+  constexpr int NRX = SM::NRX, NRY = SM::NRY;
+  constexpr int MQ = (QP + NT - 1) / NT, MU = (UP + NT - 1) / NT;
+  constexpr int NR = NRX + NRY;
+
+  const int nx = B.nx, ny = B.ny, nz = B.nz, hydro = B.hydro;
+  const int nxy = nx * ny;
+  const int tix = tt.y % B.ntx, tiy = (tt.y / B.ntx) % B.nty, tiz = tt.y / (B.ntx * B.nty);
+  const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * CZ;
+  const int zend = z0 + CZ < nz ? z0 + CZ : nz;
+  const unsigned off = (unsigned)B.off;
+  const long long NS = a.nsites;
+  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, CZ + 4);
+  const Mat<R> mp(B);
+  const int tid = threadIdx.x;
+  const int lx = tid % TX, ly = tid / TX;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool incol = gx < nx && gy < ny;
+
+  auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+  auto wrapn = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
+
+  // this thread's elements of a halo plane: 2D offsets computed once
+  int qo[MQ], qwx[MQ], qwy[MQ];
+#pragma unroll
+  for (int m = 0; m < MQ; m++) {
+    const int e = tid + m * NT;
+    const int ex = e % QPX, ey = e / QPX;
+    qwx[m] = wrapn(x0 - 2 + ex, nx);
+    qwy[m] = wrapn(y0 - 2 + ey, ny);
+    qo[m] = qwx[m] + nx * qwy[m];
+  }
+  int uo[MU];
+#pragma unroll
+  for (int m = 0; m < MU; m++) {
+    const int e = tid + m * NT;
+    const int ex = e % UPX, ey = e / UPX;
+    uo[m] = wrapn(x0 - 1 + ex, nx) + nx * wrapn(y0 - 1 + ey, ny);
+  }
+  R rq[MQ][5], ru[MU][3];
+  auto fetch_q = [&](int z) {
+    const unsigned zo = off + (unsigned)(nxy * wrapn(z, nz));
+#pragma unroll
+    for (int m = 0; m < MQ; m++)
+      if (m < MQ - 1 || tid + m * NT < QP)
+#pragma unroll
+        for (int c = 0; c < 5; c++) rq[m][c] = *at32(a.Qin + c * NS, zo + (unsigned)qo[m]);
+  };
+  auto fetch_u = [&](int z) {
+    const unsigned zo = off + (unsigned)(nxy * wrapn(z, nz));
+#pragma unroll
+    for (int m = 0; m < MU; m++)
+      if (m < MU - 1 || tid + m * NT < UP)
+#pragma unroll
+        for (int c = 0; c < 3; c++) ru[m][c] = *at32(a.uin + c * NS, zo + (unsigned)uo[m]);
+  };
+  auto store_q = [&](int slot, int z) {
+    const int wz = wrapn(z, nz);
+#pragma unroll
+    for (int m = 0; m < MQ; m++) {
+      const int e = tid + m * NT;
+      if (m < MQ - 1 || e < QP) {
+#pragma unroll
+        for (int c = 0; c < 5; c++) sm.Q[slot][c * QP + e] = rq[m][c];
+        sm.S[slot][e] = near ? (unsigned char)inside(B, Rc, qwx[m], qwy[m], wz) : (unsigned char)0;
+      }
+    }
+  };
+  auto store_u = [&](int slot) {
+#pragma unroll
+    for (int m = 0; m < MU; m++) {
+      const int e = tid + m * NT;
+      if (m < MU - 1 || e < UP)
+#pragma unroll
+        for (int c = 0; c < 3; c++) sm.U[slot][c * UP + e] = ru[m][c];
+    }
+  };
+  // rigid-body velocity at the solid nodes of a velocity plane (after the
+  // plane's solid flags are in LDS)
+  auto fix_u = [&](int uslot, int qslot, int z) {
+    if (!near) return;
+    const int wz = wrapn(z, nz);
+    for (int e = tid; e < UP; e += NT) {
+      const int ex = e % UPX, ey = e / UPX;
+      if (!sm.S[qslot][(ey + 1) * QPX + ex + 1]) continue;
+      double r[3], ub[3];
+      rel_pos(B, Rc, (double)wrapn(x0 - 1 + ex, nx), (double)wrapn(y0 - 1 + ey, ny), (double)wz, r);
+      rigid_vel(B, r, ub);
+#pragma unroll
+      for (int c = 0; c < 3; c++) sm.U[uslot][c * UP + e] = (R)ub[c];
+    }
+  };
+
+  // Stress and field of plane p at the own column (full) and, if ring, on
+  // the face rows (one column each).  Q slots of planes p-1, p, p+1.
+  auto plane_stress = [&](int qm, int q0, int qp, int pslot, bool ring, R h5[5], R pz[3]) {
+    const int ic = (ly + 2) * QPX + lx + 2;
+    Stencil<R> st;
+    {
+      R c5[5], xp[5], xm[5], yp[5], ym[5], zp[5], zm[5];
+#pragma unroll
+      for (int c = 0; c < 5; c++) {
+        const R* q = sm.Q[q0] + c * QP + ic;
+        c5[c] = q[0]; xp[c] = q[1]; xm[c] = q[-1]; yp[c] = q[QPX]; ym[c] = q[-QPX];
+        zp[c] = sm.Q[qp][c * QP + ic]; zm[c] = sm.Q[qm][c * QP + ic];
+      }
+      stencil5(c5, xp, xm, yp, ym, zp, zm, st);
+    }
+    R q[3][3], q2[3][3], tr2, M[3][3], h[3][3];
+    mol_field<R, CHIRAL>(mp, st, q, q2, tr2, M, h);
+    h5[0] = h[0][0]; h5[1] = h[0][1]; h5[2] = h[0][2]; h5[3] = h[1][1]; h5[4] = h[1][2];
+    if (hydro && !sm.S[q0][ic]) {
+      const R fe = energy_density<R, CHIRAL>(mp, st, q, q2, tr2, M);
+      R cxv[3], cyv[3];
+      stress_col<R, CHIRAL, 0>(mp, st, q, h, fe, cxv);
+      stress_col<R, CHIRAL, 1>(mp, st, q, h, fe, cyv);
+      stress_col<R, CHIRAL, 2>(mp, st, q, h, fe, pz);
+      if (ring) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          sm.P[pslot][(2 * c) * NT + tid] = cxv[c];
+          sm.P[pslot][(2 * c + 1) * NT + tid] = cyv[c];
+        }
+      }
+    }
+    if (hydro && ring && tid < NR) {
+      // face rows: x faces (x = -1, TX) then y faces (y = -1, TY)
+      int rx, ry, b;
+      if (tid < NRX) { rx = tid < TY ? -1 : TX; ry = tid % TY; b = 0; }
+      else { const int r = tid - NRX; ry = r < TX ? -1 : TY; rx = r % TX; b = 1; }
+      const int ir = (ry + 2) * QPX + rx + 2;
+      if (!sm.S[q0][ir]) {
+        Stencil<R> sr;
+        {
+          R c5[5], xp[5], xm[5], yp[5], ym[5], zp[5], zm[5];
+#pragma unroll
+          for (int c = 0; c < 5; c++) {
+            const R* qq = sm.Q[q0] + c * QP + ir;
+            c5[c] = qq[0]; xp[c] = qq[1]; xm[c] = qq[-1]; yp[c] = qq[QPX]; ym[c] = qq[-QPX];
+            zp[c] = sm.Q[qp][c * QP + ir]; zm[c] = sm.Q[qm][c * QP + ir];
+          }
+          stencil5(c5, xp, xm, yp, ym, zp, zm, sr);
+        }
+        R rq3[3][3], rq2[3][3], rtr2, rM[3][3], rh[3][3], col[3];
+        mol_field<R, CHIRAL>(mp, sr, rq3, rq2, rtr2, rM, rh);
+        const R fe = energy_density<R, CHIRAL>(mp, sr, rq3, rq2, rtr2, rM);
+        if (b == 0) stress_col<R, CHIRAL, 0>(mp, sr, rq3, rh, fe, col);
+        else stress_col<R, CHIRAL, 1>(mp, sr, rq3, rh, fe, col);
+        const int base = 6 * NT + (b == 0 ? 0 : 3 * NRX);
+        const int nr = b == 0 ? NRX : NRY;
+        const int idx = b == 0 ? tid : tid - NRX;
+#pragma unroll
+        for (int c = 0; c < 3; c++) sm.P[pslot][base + c * nr + idx] = col[c];
+      }
+    }
+  };
+
+  // prologue: Q planes z0-2 .. z0+2 in slots 0..4, u planes z0-1 .. z0+1
+  // in slots 0..2
+  for (int k = 0; k < 5; k++) {
+    fetch_q(z0 - 2 + k);
+    store_q(k, z0 - 2 + k);
+  }
+  if (hydro) {
+    for (int k = 0; k < 3; k++) {
+      fetch_u(z0 - 1 + k);
+      store_u(k);
+    }
+  }
+  lds_sync();
+  if (hydro)
+    for (int k = 0; k < 3; k++) fix_u(k, k + 1, z0 - 1 + k);
+  R h_cur[5], h_nxt[5], pz_m[3] = {(R)0, (R)0, (R)0}, pz_c[3] = {(R)0, (R)0, (R)0},
+                        pz_n[3] = {(R)0, (R)0, (R)0};
+  {
+    R hdummy[5];
+    plane_stress(0, 1, 2, 1, false, hdummy, pz_m);   // plane z0-1: z column only
+    plane_stress(1, 2, 3, 0, true, h_cur, pz_c);     // plane z0
+  }
+  lds_sync();
+
+  int qs_m1 = 1, qs_0 = 2, qs_p1 = 3, qs_p2 = 4, qs_free = 0;  // slots of planes k-1..k+2, k+3
+  int us_m1 = 0, us_0 = 1, us_p1 = 2, us_free = 3;
+  int ps_0 = 0;
+  if (tid < 12) sm.acc[tid] = 0.0;
+
+  for (int k = z0; k < zend; k++) {
+    double part[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) part[c] = 0.0;
+    const int gz = k;
+    const unsigned g = off + (unsigned)(gx + nx * gy + nxy * gz);
+    R f[19];
+    if (hydro && incol) {
+#pragma unroll
+      for (int i = 0; i < 19; i++) f[i] = __builtin_nontemporal_load(at32(a.fin + i * NS, g));
+    }
+    const bool more = k + 1 < zend;
+    if (more) {
+      fetch_q(k + 3);
+      if (hydro) fetch_u(k + 2);
+    }
+    // stress of plane k+1
+    plane_stress(qs_0, qs_p1, qs_p2, ps_0 ^ 1, true, h_nxt, pz_n);
+
+    // own node of plane k
+    const int ic = (ly + 2) * QPX + lx + 2;
+    const int iu = (ly + 1) * UPX + lx + 1;
+    const bool fluid = !sm.S[qs_0][ic];
+    auto update = [&](auto near_tag) {
+      constexpr bool NEAR = decltype(near_tag)::value;
+      R q5[5], dQ[5];
+#pragma unroll
+      for (int c = 0; c < 5; c++) {
+        q5[c] = sm.Q[qs_0][c * QP + ic];
+        dQ[c] = mp.Gamma * h_cur[c];
+      }
+      // solid flags of the 18 link neighbours
+      bool sn[19];
+#pragma unroll
+      for (int i = 0; i < 19; i++) {
+        const int sl = cz(i) > 0 ? qs_p1 : (cz(i) < 0 ? qs_m1 : qs_0);
+        sn[i] = NEAR ? (bool)sm.S[sl][ic + cx(i) + cy(i) * QPX] : false;
+      }
+      R F[3] = {(R)0, (R)0, (R)0};
+      if (hydro) {
+        const R* Pp = sm.P[ps_0];
+        R Pc[3][3];   // own stress, [c][b]
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          Pc[c][0] = Pp[(2 * c) * NT + tid];
+          Pc[c][1] = Pp[(2 * c + 1) * NT + tid];
+          Pc[c][2] = pz_c[c];
+        }
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          const bool sp = sn[2 * b + 1], sm_ = sn[2 * b + 2];
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            R pn, pmv;
+            if (b == 0) {
+              pn = lx + 1 < TX ? Pp[(2 * c) * NT + tid + 1] : Pp[6 * NT + c * NRX + TY + ly];
+              pmv = lx > 0 ? Pp[(2 * c) * NT + tid - 1] : Pp[6 * NT + c * NRX + ly];
+            } else if (b == 1) {
+              pn = ly + 1 < TY ? Pp[(2 * c + 1) * NT + tid + TX] : Pp[6 * NT + 3 * NRX + c * NRY + TX + lx];
+              pmv = ly > 0 ? Pp[(2 * c + 1) * NT + tid - TX] : Pp[6 * NT + 3 * NRX + c * NRY + lx];
+            } else {
+              pn = pz_n[c];
+              pmv = pz_m[c];
+            }
+            const R pcv = Pc[c][b];
+            const R pp = sp ? pcv : (R)0.5 * (pcv + pn);
+            const R pm = sm_ ? pcv : (R)0.5 * (pcv + pmv);
+            F[c] += pp - pm;
+          }
+          if (NEAR && (sp || sm_)) {
+#pragma unroll
+            for (int sg = 1; sg >= -1; sg -= 2) {
+              if (sg > 0 ? !sp : !sm_) continue;
+              double ps[3], r[3];
+              for (int c = 0; c < 3; c++) ps[c] = -(double)sg * (double)Pc[c][b];
+              const double e[3] = {b == 0 ? 0.5 * sg : 0.0, b == 1 ? 0.5 * sg : 0.0, b == 2 ? 0.5 * sg : 0.0};
+              rel_pos(B, Rc, gx + e[0], gy + e[1], gz + e[2], r);
+              part[3] += ps[0]; part[4] += ps[1]; part[5] += ps[2];
+              part[9] += r[1] * ps[2] - r[2] * ps[1];
+              part[10] += r[2] * ps[0] - r[0] * ps[2];
+              part[11] += r[0] * ps[1] - r[1] * ps[0];
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) F[c] += (R)B.body[c];
+
+        // Beris-Edwards: velocity gradient, upwind fluxes, co-rotation
+        R u0[3], W[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) u0[c] = sm.U[us_0][c * UP + iu];
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          R up[3], um[3];
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            if (b == 0) { up[c] = sm.U[us_0][c * UP + iu + 1]; um[c] = sm.U[us_0][c * UP + iu - 1]; }
+            else if (b == 1) { up[c] = sm.U[us_0][c * UP + iu + UPX]; um[c] = sm.U[us_0][c * UP + iu - UPX]; }
+            else { up[c] = sm.U[us_p1][c * UP + iu]; um[c] = sm.U[us_m1][c * UP + iu]; }
+            W[c][b] = (R)0.5 * (up[c] - um[c]);
+          }
+          const bool fp = !sn[2 * b + 1], fm = !sn[2 * b + 2];
+          const R ufp = (R)0.5 * (u0[b] + up[b]), ufm = (R)0.5 * (um[b] + u0[b]);
+#pragma unroll
+          for (int c = 0; c < 5; c++) {
+            R qn_p, qn_m;
+            if (b == 0) { qn_p = sm.Q[qs_0][c * QP + ic + 1]; qn_m = sm.Q[qs_0][c * QP + ic - 1]; }
+            else if (b == 1) { qn_p = sm.Q[qs_0][c * QP + ic + QPX]; qn_m = sm.Q[qs_0][c * QP + ic - QPX]; }
+            else { qn_p = sm.Q[qs_p1][c * QP + ic]; qn_m = sm.Q[qs_m1][c * QP + ic]; }
+            const R phip = fp ? ufp * (ufp >= (R)0 ? q5[c] : qn_p) : (R)0;
+            const R phim = fm ? ufm * (ufm >= (R)0 ? qn_m : q5[c]) : (R)0;
+            dQ[c] -= phip - phim;
+          }
+        }
+        R S5[5];
+        corotation<R>(mp.xi, W, q5, S5);
+#pragma unroll
+        for (int c = 0; c < 5; c++) dQ[c] += S5[c];
+      }
+      R qn2 = (R)0;
+#pragma unroll
+      for (int c = 0; c < 5; c++) {
+        const R v = q5[c] + dQ[c];
+        __builtin_nontemporal_store(v, at32(a.Qout + c * NS, g));
+        qn2 += v * v;
+      }
+      bool bad = !(qn2 < (R)100);
+      if (hydro) {
+        R rm1 = (R)0;
+#pragma unroll
+        for (int i = 0; i < 19; i++) rm1 += f[i];
+        const R j[3] = {((f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10])) + ((f[11] - f[12]) + (f[13] - f[14])),
+                        ((f[3] - f[4]) + (f[7] - f[8]) - (f[9] - f[10])) + ((f[15] - f[16]) + (f[17] - f[18])),
+                        ((f[5] - f[6]) + (f[11] - f[12]) - (f[13] - f[14])) + ((f[15] - f[16]) - (f[17] - f[18]))};
+        const R rho = (R)1 + rm1;
+        const R irho = (R)1 / rho;
+        R u[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) u[c] = (j[c] + (R)0.5 * F[c]) * irho;
+        const R usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+        const R itau = (R)1 / mp.tau, fsrc = (R)1 - (R)0.5 * itau;
+        bad = bad || !(usq < (R)0.09);
+        R fs[19];
+        {
+          const R w = (R)wgt(0);
+          const R feq = w * rm1 + w * rho * ((R)-1.5 * usq);
+          const R src = w * ((R)-3 * uF);
+          fs[0] = f[0] - (f[0] - feq) * itau + fsrc * src;
+        }
+#pragma unroll
+        for (int i = 1; i < 19; i += 2) {
+          const R w = (R)wgt(i);
+          const R cu = (R)cx(i) * u[0] + (R)cy(i) * u[1] + (R)cz(i) * u[2];
+          const R cF = (R)cx(i) * F[0] + (R)cy(i) * F[1] + (R)cz(i) * F[2];
+          const R even = w * rm1 + w * rho * ((R)4.5 * cu * cu - (R)1.5 * usq);
+          const R odd = w * rho * (R)3 * cu;
+          const R seven = w * ((R)9 * cu * cF - (R)3 * uF);
+          const R sodd = w * (R)3 * cF;
+          fs[i] = f[i] - (f[i] - (even + odd)) * itau + fsrc * (seven + sodd);
+          fs[i + 1] = f[i + 1] - (f[i + 1] - (even - odd)) * itau + fsrc * (seven - sodd);
+        }
+        const int dxp = gx + 1 == nx ? 1 - nx : 1, dxm = gx == 0 ? nx - 1 : -1;
+        const int dyp = gy + 1 == ny ? nx * (1 - ny) : nx, dym = gy == 0 ? nx * (ny - 1) : -nx;
+        const int dzp = gz + 1 == nz ? nxy * (1 - nz) : nxy, dzm = gz == 0 ? nxy * (nz - 1) : -nxy;
+        const int dxs[3] = {dxm, 0, dxp}, dys[3] = {dym, 0, dyp}, dzs[3] = {dzm, 0, dzp};
+#pragma unroll
+        for (int i = 0; i < 19; i++) {
+          if (!NEAR || !sn[i]) {
+            const unsigned gn = g + (unsigned)(dxs[cx(i) + 1] + dys[cy(i) + 1] + dzs[cz(i) + 1]);
+            __builtin_nontemporal_store(fs[i], at32(a.fout + i * NS, gn));
+          } else {
+            double r[3], ub[3];
+            rel_pos(B, Rc, gx + 0.5 * cx(i), gy + 0.5 * cy(i), gz + 0.5 * cz(i), r);
+            rigid_vel(B, r, ub);
+            const double cub = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
+            const double corr = 6.0 * wgt(i) * B.rho0 * cub;
+            __builtin_nontemporal_store((R)((double)fs[i] - corr), at32(a.fout + opp(i) * NS, g));
+            const double m = 2.0 * ((double)fs[i] + wgt(i)) - corr;
+            const double dp[3] = {m * cx(i), m * cy(i), m * cz(i)};
+            part[0] += dp[0]; part[1] += dp[1]; part[2] += dp[2];
+            part[6] += r[1] * dp[2] - r[2] * dp[1];
+            part[7] += r[2] * dp[0] - r[0] * dp[2];
+            part[8] += r[0] * dp[1] - r[1] * dp[0];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) __builtin_nontemporal_store(u[c], at32(a.uout + c * NS, g));
+      }
+      if (bad) atomicOr(a.flag, 1);
+    };
+    if (incol && fluid) {
+      if (near) update(std::true_type{});
+      else update(std::false_type{});
+    }
+    if (near) block_accumulate<NT, 12>(part, sm.red, sm.acc);
+
+    // rotate: planes k+3 (Q) and k+2 (u) enter the free slots
+    if (more) {
+      store_q(qs_free, k + 3);
+      if (hydro) store_u(us_free);
+    }
+    lds_sync();
+    if (more && hydro) {
+      fix_u(us_free, qs_p2, k + 2);
+      if (near) lds_sync();
+    }
+    const int qf = qs_m1;
+    qs_m1 = qs_0; qs_0 = qs_p1; qs_p1 = qs_p2; qs_p2 = qs_free; qs_free = qf;
+    const int uf = us_m1;
+    us_m1 = us_0; us_0 = us_p1; us_p1 = us_free; us_free = uf;
+    ps_0 ^= 1;
+#pragma unroll
+    for (int c = 0; c < 5; c++) h_cur[c] = h_nxt[c];
+#pragma unroll
+    for (int c = 0; c < 3; c++) { pz_m[c] = pz_c[c]; pz_c[c] = pz_n[c]; }
+  }
+
+  if (near && tid < 12) a.part[12LL * (B.tile_base + tt.y) + tid] = sm.acc[tid];
+}
+
+// ---------------------------------------------------------------------
 // ghost Q at boundary solid nodes
 // ---------------------------------------------------------------------
 __device__ inline int find_box(const BoxDev* boxes, int nbox, long long t, int which) {
@@ -599,10 +1071,10 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------
 // finalize: fixed-order sums, force history, colloid position
 // ---------------------------------------------------------------------
-template <int TX, int TY, int TZ>
 __global__ void __launch_bounds__(256)
-    k_finalize(BoxDev* __restrict__ boxes, const double* __restrict__ part, const double* __restrict__ epart,
-               double* __restrict__ force, double* __restrict__ hist, int cap, long long* __restrict__ count) {
+    k_finalize(int TX, int TY, int TZ, BoxDev* __restrict__ boxes, const double* __restrict__ part,
+               const double* __restrict__ epart, double* __restrict__ force, double* __restrict__ hist, int cap,
+               long long* __restrict__ count) {
   __shared__ double sred[4 * 12];
   __shared__ double sres[12];
   const int b = blockIdx.x;
@@ -799,10 +1271,13 @@ __global__ void __launch_bounds__(256) k_fill_f(R* f, long long NS, const double
 // launchers
 // ---------------------------------------------------------------------
 template <typename R>
-hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles,
-                       const StepPtrs<R>& a, hipStream_t s) {
-#define LC_TILE_CASE(ID, X, Y, Z) \
-  case ID: k_step<R, X, Y, Z><<<nblk, X * Y * Z, 0, s>>>(boxes, tiles, a); break;
+hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const StepPtrs<R>& a,
+                       hipStream_t s) {
+#define LC_TILE_CASE(ID, X, Y, Z, KIND)                                               \
+  case ID:                                                                             \
+    if constexpr (KIND == 0) k_step<R, X, Y, Z><<<nblk, X * Y * Z, 0, s>>>(boxes, tiles, a); \
+    else k_march<R, X, Y, Z><<<nblk, X * Y, 0, s>>>(boxes, tiles, a);                       \
+    break;
   if constexpr (sizeof(R) == 4) {
     switch (tile) {
       LC_TILES_F32(LC_TILE_CASE)
@@ -818,23 +1293,10 @@ hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tile
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_finalize(int tile, int nbox, BoxDev* boxes, const double* part, const double* epart,
-                           double* force, double* hist, int cap, long long* count, hipStream_t s) {
-#define LC_TILE_CASE(ID, X, Y, Z) \
-  case ID: k_finalize<X, Y, Z><<<nbox, 256, 0, s>>>(boxes, part, epart, force, hist, cap, count); break;
-  if constexpr (sizeof(R) == 4) {
-    switch (tile) {
-      LC_TILES_F32(LC_TILE_CASE)
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    switch (tile) {
-      LC_TILES_F64(LC_TILE_CASE)
-      default: return hipErrorInvalidValue;
-    }
-  }
-#undef LC_TILE_CASE
+hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part,
+                           const double* epart, double* force, double* hist, int cap, long long* count,
+                           hipStream_t s) {
+  k_finalize<<<nbox, 256, 0, s>>>(tx, ty, tz, boxes, part, epart, force, hist, cap, count);
   return hipGetLastError();
 }
 
@@ -876,8 +1338,6 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
 #define LC_INST(R)                                                                                        \
   template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const StepPtrs<R>&,               \
                                      hipStream_t);                                                          \
-  template hipError_t launch_finalize<R>(int, int, BoxDev*, const double*, const double*, double*, double*,  \
-                                         int, long long*, hipStream_t);                                     \
   template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, hipStream_t);           \
   template hipError_t launch_events<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*,          \
                                        hipStream_t);                                                        \

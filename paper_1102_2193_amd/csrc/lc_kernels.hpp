@@ -21,26 +21,30 @@ struct StepPtrs {
   int* flag;          // set to 1 on a non-finite value or |u| >= 0.3
 };
 
-// Block shapes (TX, TY, TZ) of the fused kernel, per precision.
+// Block shapes of the fused kernel, per precision: (id, TX, TY, TZ, kind).
+// kind 0: 3D tile of TX x TY x TZ nodes; kind 1: TX x TY columns marching
+// through TZ planes.
 #define LC_TILES_F32(X)  \
-  X(0, 8, 8, 4)          \
-  X(1, 16, 8, 2)         \
-  X(2, 16, 4, 4)         \
-  X(3, 32, 4, 2)         \
-  X(4, 8, 4, 4)          \
-  X(5, 16, 8, 4)         \
-  X(6, 8, 8, 8)
+  X(0, 32, 8, 16, 1)     \
+  X(1, 32, 8, 8, 1)      \
+  X(2, 32, 8, 32, 1)     \
+  X(3, 64, 4, 16, 1)     \
+  X(4, 16, 16, 16, 1)    \
+  X(5, 32, 4, 16, 1)     \
+  X(6, 16, 8, 2, 0)      \
+  X(7, 16, 4, 4, 0)
 #define LC_TILES_F64(X)  \
-  X(0, 8, 4, 4)          \
-  X(1, 8, 8, 4)          \
-  X(2, 16, 4, 2)
+  X(0, 16, 8, 8, 1)      \
+  X(1, 8, 4, 4, 0)       \
+  X(2, 16, 4, 2, 0)
 
 template <typename R>
 hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles,
                        const StepPtrs<R>& a, hipStream_t s);
-template <typename R>
-hipError_t launch_finalize(int tile, int nbox, BoxDev* boxes, const double* part, const double* epart,
-                           double* force, double* hist, int cap, long long* count, hipStream_t s);
+// tx, ty, tz: extents of one tile (3D tile or marching column chunk)
+hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part,
+                           const double* epart, double* force, double* hist, int cap, long long* count,
+                           hipStream_t s);
 template <typename R>
 hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, hipStream_t s);
 template <typename R>

@@ -17,10 +17,10 @@ using lc::BoxDev;
 namespace {
 
 struct TileShape {
-  int x, y, z;
+  int x, y, z, kind;   // kind 1: x*y columns marching through z planes
 };
 
-#define LC_SHAPE(ID, X, Y, Z) {X, Y, Z},
+#define LC_SHAPE(ID, X, Y, Z, KIND) {X, Y, Z, KIND},
 const TileShape kTilesF32[] = {LC_TILES_F32(LC_SHAPE)};
 const TileShape kTilesF64[] = {LC_TILES_F64(LC_SHAPE)};
 #undef LC_SHAPE
@@ -223,8 +223,9 @@ hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t
     e = lc::launch_events<R>(c->dbox, c->nbox, c->event_total, a, c->depart, c->stream);
     if (e != hipSuccess) return e;
   }
-  return lc::launch_finalize<R>(c->tile, c->nbox, c->dbox, c->dpart, c->depart, c->dforce, c->dhist, kHistCap,
-                                c->dcount, c->stream);
+  const TileShape& T = tile_shape(c, c->tile);
+  return lc::launch_finalize(T.x, T.y, T.z, c->nbox, c->dbox, c->dpart, c->depart, c->dforce, c->dhist,
+                             kHistCap, c->dcount, c->stream);
 }
 
 hipError_t enqueue(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t k1 = nullptr) {
@@ -713,7 +714,7 @@ int lc_launch_info(const lc_ctx* c, long out[2]) {
   if (!c || !out) return LC_EINVAL;
   const TileShape& t = tile_shape(c, c->tile);
   out[0] = c->nblk;
-  out[1] = (long)t.x * t.y * t.z;
+  out[1] = t.kind ? (long)t.x * t.y : (long)t.x * t.y * t.z;
   return LC_OK;
 }
 
