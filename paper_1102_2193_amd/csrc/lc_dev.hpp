@@ -21,6 +21,7 @@ struct BoxDev {
   int event_base, event_ext;             // event launch: thread range, bbox edge
   int event_blk0, event_nblk;            // event partial-sum blocks of this box
   double tau, rho0, A0, gamma, K, q0, xi, Gamma;
+  double itau, fsrc;                     // 1/tau and 1 - 1/(2 tau)
   double body[3];
   int present, motion, anchoring, pad_;
   double pos[3], a0, vel[3], omega[3], S0, W;
@@ -120,11 +121,19 @@ __device__ inline void full5(const R q5[5], R q[3][3]) {
 // Material constants in the arithmetic precision of a kernel.
 template <typename R>
 struct Mat {
-  R A0, gamma, K, q0, xi, Gamma, tau, rho0;
+  R A0, gamma, K, q0, xi, Gamma, tau, rho0, itau, fsrc;
   __device__ explicit Mat(const BoxDev& B)
       : A0((R)B.A0), gamma((R)B.gamma), K((R)B.K), q0((R)B.q0), xi((R)B.xi),
-        Gamma((R)B.Gamma), tau((R)B.tau), rho0((R)B.rho0) {}
+        Gamma((R)B.Gamma), tau((R)B.tau), rho0((R)B.rho0), itau((R)B.itau), fsrc((R)B.fsrc) {}
 };
+
+// 1/x: exact division in FP64; in FP32 the hardware reciprocal refined by
+// one Newton step (within an ulp or two of the correctly rounded value).
+__device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return r * (2.0f - x * r);
+}
 
 // Local stencil quantities at one node from its own Q and the six face
 // neighbours: Q, central first derivatives d[g] = D0_g Q and the compact

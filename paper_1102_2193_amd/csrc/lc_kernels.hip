@@ -391,13 +391,13 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
                       ((f[3] - f[4]) + (f[7] - f[8]) - (f[9] - f[10])) + ((f[15] - f[16]) + (f[17] - f[18])),
                       ((f[5] - f[6]) + (f[11] - f[12]) - (f[13] - f[14])) + ((f[15] - f[16]) - (f[17] - f[18]))};
       const R rho = (R)1 + rm1;
-      const R irho = (R)1 / rho;
+      const R irho = recip(rho);
       R u[3];
 #pragma unroll
       for (int c = 0; c < 3; c++) u[c] = (j[c] + (R)0.5 * F[c]) * irho;
       const R usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
       const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-      const R itau = (R)1 / mp.tau, fsrc = (R)1 - (R)0.5 * itau;
+      const R itau = mp.itau, fsrc = mp.fsrc;
       bad = bad || !(usq < (R)0.09);
       R fs[19];
       {
@@ -428,7 +428,7 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
       for (int i = 0; i < 19; i++) {
         if (!NEAR || !solid_nb[i]) {
           const unsigned gn = g + (unsigned)(dxs[cx(i) + 1] + dys[cy(i) + 1] + dzs[cz(i) + 1]);
-          __builtin_nontemporal_store(fs[i], at32(a.fout + i * NS, gn));
+          *at32(a.fout + i * NS, gn) = fs[i];
         } else {
           // bounce-back on the link with the moving-wall correction
           double r[3], ub[3];
@@ -696,17 +696,24 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   int ps_0 = 0;
   if (tid < 12) sm.acc[tid] = 0.0;
 
+  // populations of the own column, one plane ahead of their use
+  R f[19];
+  const unsigned gcol = off + (unsigned)(gx + nx * gy);
+  auto fetch_f = [&](int z) {
+    if (hydro && incol) {
+      const unsigned gf = gcol + (unsigned)(nxy * z);
+#pragma unroll
+      for (int i = 0; i < 19; i++) f[i] = __builtin_nontemporal_load(at32(a.fin + i * NS, gf));
+    }
+  };
+  fetch_f(z0);
+
   for (int k = z0; k < zend; k++) {
     double part[12];
 #pragma unroll
     for (int c = 0; c < 12; c++) part[c] = 0.0;
     const int gz = k;
-    const unsigned g = off + (unsigned)(gx + nx * gy + nxy * gz);
-    R f[19];
-    if (hydro && incol) {
-#pragma unroll
-      for (int i = 0; i < 19; i++) f[i] = __builtin_nontemporal_load(at32(a.fin + i * NS, g));
-    }
+    const unsigned g = gcol + (unsigned)(nxy * gz);
     const bool more = k + 1 < zend;
     if (more) {
       fetch_q(k + 3);
@@ -831,13 +838,13 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
                         ((f[3] - f[4]) + (f[7] - f[8]) - (f[9] - f[10])) + ((f[15] - f[16]) + (f[17] - f[18])),
                         ((f[5] - f[6]) + (f[11] - f[12]) - (f[13] - f[14])) + ((f[15] - f[16]) - (f[17] - f[18]))};
         const R rho = (R)1 + rm1;
-        const R irho = (R)1 / rho;
+        const R irho = recip(rho);
         R u[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) u[c] = (j[c] + (R)0.5 * F[c]) * irho;
         const R usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const R uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-        const R itau = (R)1 / mp.tau, fsrc = (R)1 - (R)0.5 * itau;
+        const R itau = mp.itau, fsrc = mp.fsrc;
         bad = bad || !(usq < (R)0.09);
         R fs[19];
         {
@@ -866,7 +873,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
         for (int i = 0; i < 19; i++) {
           if (!NEAR || !sn[i]) {
             const unsigned gn = g + (unsigned)(dxs[cx(i) + 1] + dys[cy(i) + 1] + dzs[cz(i) + 1]);
-            __builtin_nontemporal_store(fs[i], at32(a.fout + i * NS, gn));
+            *at32(a.fout + i * NS, gn) = fs[i];
           } else {
             double r[3], ub[3];
             rel_pos(B, Rc, gx + 0.5 * cx(i), gy + 0.5 * cy(i), gz + 0.5 * cz(i), r);
@@ -891,6 +898,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
       if (near) update(std::true_type{});
       else update(std::false_type{});
     }
+    if (more) fetch_f(k + 1);
     if (near) block_accumulate<NT, 12>(part, sm.red, sm.acc);
 
     // rotate: planes k+3 (Q) and k+2 (u) enter the free slots

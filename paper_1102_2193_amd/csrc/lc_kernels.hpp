@@ -30,9 +30,9 @@ struct StepPtrs {
   X(2, 32, 8, 32, 1)     \
   X(3, 64, 4, 16, 1)     \
   X(4, 16, 16, 16, 1)    \
-  X(5, 32, 4, 16, 1)     \
+  X(5, 32, 16, 8, 1)     \
   X(6, 16, 8, 2, 0)      \
-  X(7, 16, 4, 4, 0)
+  X(7, 32, 16, 16, 1)
 #define LC_TILES_F64(X)  \
   X(0, 16, 8, 8, 1)      \
   X(1, 8, 4, 4, 0)       \

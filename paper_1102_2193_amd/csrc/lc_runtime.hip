@@ -352,6 +352,8 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
     off += (box_sites(q) + 63) / 64 * 64;
     B.tau = q.tau; B.rho0 = q.rho0; B.A0 = q.A0; B.gamma = q.gamma; B.K = q.K; B.q0 = q.q0;
     B.xi = q.xi; B.Gamma = q.Gamma;
+    B.itau = 1.0 / q.tau;
+    B.fsrc = 1.0 - 0.5 / q.tau;
     for (int a = 0; a < 3; a++) B.body[a] = q.body_force[a];
   }
   c->nsites = off;
