@@ -63,6 +63,34 @@ def workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lc_kernels.hip", "lc_dev.hpp", "lc_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1102_2193_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload, tile):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload, if it was taken on the current kernel sources and tile."""
+    import glob
+    want = kernel_sources_hash()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        meta = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and line.split(":")[0] in ("kernel_sources_sha256", "tile", "traffic_bytes_per_launch",
+                                                          "workload"):
+                    k, v = line.split(":", 1)
+                    meta[k.strip()] = v.strip()
+        if (meta.get("kernel_sources_sha256") == want and meta.get("tile") == str(tile)
+                and meta.get("workload", "drag128_fp32") == workload and "traffic_bytes_per_launch" in meta):
+            return float(meta["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def cpu_baseline(wl, target_s):
     """FP64 oracle on the first steps of the same workload (box 0)."""
     from oracle import lco
@@ -145,6 +173,7 @@ def main():
     mlups = sites / (ms_step * 1e-3) / 1e6
     bpl = BYTES_PER_LU[wl["prec"]]
     achieved = bpl * sites / (tk["kernel_ms"] * 1e-3) / 1e9
+    traffic, traffic_src = profiled_traffic(wl["config"]["workload"], tile)
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
@@ -152,7 +181,8 @@ def main():
         "config": dict(wl["config"], tile=list(ctx.tile_shape(tile)), sites=sites),
         "hbm_gbps_effective": round(bpl * sites / (ms_step * 1e-3) / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic), "traffic_source": traffic_src,
                      "kernel": "k_step (fused)", "kernel_ms": round(tk["kernel_ms"], 5),
                      "bytes_per_launch": bpl * sites},
         "wall_s": round(wall, 3),
