@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblc.so")
-SOURCES = ["lc_kernels.hip", "lc_runtime.hip"]
+SOURCES = ["lc_kernels.hip", "lc_runtime.hip", "nn_kernels.hip", "nn_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          # packed FP32 instructions are disabled on purpose

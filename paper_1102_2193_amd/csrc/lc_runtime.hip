@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/lc.h"
+#include "lc_internal.hpp"
 #include "lc_kernels.hpp"
 
 using lc::BoxDev;
@@ -317,6 +318,20 @@ int check_flag(lc_ctx* c) {
 }
 
 }  // namespace
+
+int lc_internal_q_view(lc_ctx* c, int box, LcQView* out) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  out->Q = c->Q[c->cur];
+  out->nsites = c->nsites;
+  out->off = c->hb[box].off;
+  out->prec = c->prec;
+  out->nx = c->prm[box].nx;
+  out->ny = c->prm[box].ny;
+  out->nz = c->prm[box].nz;
+  out->stream = c->stream;
+  return LC_OK;
+}
 
 extern "C" {
 

@@ -1,0 +1,462 @@
+// nn_kernels.hip -- gfx950 kernels of the warm-start network (include/lc_nn.h).
+//
+// Activations are BF16, channels-last [voxel][C] with C padded to 16 or 32.
+// A 3x3x3 periodic convolution is an implicit GEMM: M = voxels of an
+// 8x8x4 tile, N = output channels, K = 27 taps x input channels.  Each
+// wave owns one z-layer of the tile (64 voxels = four 16-row M tiles) and
+// multiplies BF16 fragments on the matrix cores
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation).  Fragment layout of that
+// instruction for a wave of 64 lanes: A[i][k] -> lane i + 16*(k/4),
+// element k%4; B[k][j] -> lane j + 16*(k/4), element k%4; D[i][j] -> lane
+// j + 16*(i/4), element i%4.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nn_kernels.hpp"
+
+namespace lcnn {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+constexpr int TX = 8, TY = 8, TZ = 4, TV = TX * TY * TZ;
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HV = HX * HY * HZ;
+
+__device__ inline int wrap1(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+// ---------------------------------------------------------------------
+// input features
+// ---------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_features(int L, Case c, uint16_t* __restrict__ x0, float* __restrict__ f32) {
+  const long long V = (long long)L * L * L;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int x = (int)(v % L), y = (int)((v / L) % L), z = (int)(v / ((long long)L * L));
+  double r[3] = {x - c.pos[0], y - c.pos[1], z - c.pos[2]};
+  for (int k = 0; k < 3; k++) r[k] = r[k] > 0.5 * L ? r[k] - L : (r[k] < -0.5 * L ? r[k] + L : r[k]);
+  const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  double f[16];
+  double sd = (rn - c.a0) / 8.0;
+  f[0] = sd < -1.0 ? -1.0 : (sd > 2.0 ? 2.0 : sd);
+  for (int k = 0; k < 3; k++) f[1 + k] = rn > 0.0 ? r[k] / rn : 0.0;
+  const double q0 = 2.0 * M_PI / c.pitch;
+  const double cz = cos(q0 * z), sz = sin(q0 * z);
+  f[4] = cz * cz - 1.0 / 3.0;
+  f[5] = cz * sz;
+  f[6] = 0.0;
+  f[7] = sz * sz - 1.0 / 3.0;
+  f[8] = 0.0;
+  f[9] = c.a0 / 16.0;
+  f[10] = 32.0 / c.pitch;
+  f[11] = c.anchoring == 2 ? -1.0 : 1.0;
+  for (int k = 12; k < 16; k++) f[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) x0[v * 16 + k] = f2bf((float)f[k]);
+  if (f32)
+    for (int k = 0; k < 12; k++) f32[k * V + v] = (float)f[k];
+}
+
+// ---------------------------------------------------------------------
+// convolution as implicit GEMM on the matrix cores
+// ---------------------------------------------------------------------
+// x [V][CIN] bf16, w [27][COUT][CIN] bf16.  MODE 0: z = acc + b, store z
+// (FP32) and bf16(silu(z)); MODE 1: z = acc + b (FP32); MODE 2: acc times
+// silu'(zprev) stored as bf16 (data gradient through an activation);
+// MODE 3: acc stored as FP32 (plain data gradient).
+template <int CIN, int COUT, int MODE>
+__global__ void __launch_bounds__(256)
+    k_conv(int L, const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias,
+           const float* __restrict__ zprev, float* __restrict__ zout, uint16_t* __restrict__ aout) {
+  constexpr int CS = CIN + 4;   // LDS voxel stride (bank spread)
+  __shared__ uint16_t sx[HV * CS];
+  const int tid = threadIdx.x;
+  const int ntx = L / TX, nty = L / TY;
+  const int b = blockIdx.x;
+  const int x0 = (b % ntx) * TX, y0 = ((b / ntx) % nty) * TY, z0 = (b / (ntx * nty)) * TZ;
+  constexpr int CH = CIN / 4;   // 8-byte chunks per voxel
+  for (int e = tid; e < HV * CH; e += 256) {
+    const int v = e / CH, c = e - v * CH;
+    const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+    const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
+    const long long gv = gx + (long long)L * (gy + (long long)L * gz);
+    *(uint2*)(sx + v * CS + 4 * c) = *(const uint2*)(x + gv * CIN + 4 * c);
+  }
+  __syncthreads();
+  const int wv = tid >> 6, lane = tid & 63;
+  const int ri = lane & 15, kq = lane >> 4;
+  f4 acc[4][COUT / 16];
+#pragma unroll
+  for (int m = 0; m < 4; m++)
+#pragma unroll
+    for (int n = 0; n < COUT / 16; n++) acc[m][n] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 27; t++) {
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+#pragma unroll
+    for (int kc = 0; kc < CIN / 16; kc++) {
+      s4 bf[COUT / 16];
+#pragma unroll
+      for (int n = 0; n < COUT / 16; n++)
+        bf[n] = *(const s4*)(w + ((long long)(t * COUT + n * 16 + ri) * CIN + kc * 16 + 4 * kq));
+#pragma unroll
+      for (int m = 0; m < 4; m++) {
+        const int lx = ri & 7, ly = 2 * m + (ri >> 3);
+        const int hv = (lx + 1 + dx) + HX * ((ly + 1 + dy) + HY * (wv + 1 + dz));
+        const s4 af = *(const s4*)(sx + hv * CS + kc * 16 + 4 * kq);
+#pragma unroll
+        for (int n = 0; n < COUT / 16; n++)
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[n], acc[m][n], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; m++)
+#pragma unroll
+    for (int n = 0; n < COUT / 16; n++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int i = 4 * kq + e, j = n * 16 + ri;
+        const int lx = i & 7, ly = 2 * m + (i >> 3);
+        const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + wv));
+        const float val = acc[m][n][e];
+        if (MODE == 0) {
+          const float z = val + bias[j];
+          zout[gv * COUT + j] = z;
+          aout[gv * COUT + j] = f2bf(z * sigmoidf_(z));
+        } else if (MODE == 1) {
+          zout[gv * COUT + j] = val + bias[j];
+        } else if (MODE == 2) {
+          const float zp = zprev[gv * COUT + j];
+          const float s = sigmoidf_(zp);
+          aout[gv * COUT + j] = f2bf(val * (s * (1.0f + zp * (1.0f - s))));
+        } else {
+          zout[gv * COUT + j] = val;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------
+// weight gradient: dW[t][o][c] = sum_p dz[p][o] x[p + d_t][c]
+// ---------------------------------------------------------------------
+// Block b accumulates over tiles [b*tpb, (b+1)*tpb) and writes its partial
+// sums part[b][27][COUT][CIN]; wave w owns taps w, w+4, ...
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256)
+    k_wgrad(int L, int tpb, const uint16_t* __restrict__ dz, const uint16_t* __restrict__ x, float* __restrict__ part) {
+  constexpr int PS = TV + 8, XS = HV + 8;   // LDS row strides
+  __shared__ uint16_t sd[COUT * PS];        // [o][p]
+  __shared__ uint16_t sx[CIN * XS];         // [c][halo voxel]
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int ri = lane & 15, kq = lane >> 4;
+  const int ntx = L / TX, nty = L / TY, ntz = L / TZ, ntile = ntx * nty * ntz;
+  constexpr int NTAP = 7;
+  f4 acc[NTAP][COUT / 16][CIN / 16];
+#pragma unroll
+  for (int a = 0; a < NTAP; a++)
+#pragma unroll
+    for (int m = 0; m < COUT / 16; m++)
+#pragma unroll
+      for (int n = 0; n < CIN / 16; n++) acc[a][m][n] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int tile = blockIdx.x * tpb; tile < (blockIdx.x + 1) * tpb && tile < ntile; tile++) {
+    const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
+    __syncthreads();
+    for (int e = tid; e < TV * COUT; e += 256) {
+      const int p = e / COUT, o = e - p * COUT;
+      const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+      const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + lz));
+      sd[o * PS + p] = dz[gv * COUT + o];
+    }
+    for (int e = tid; e < HV * CIN; e += 256) {
+      const int v = e / CIN, c = e - v * CIN;
+      const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+      const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
+      const long long gv = gx + (long long)L * (gy + (long long)L * gz);
+      sx[c * XS + v] = x[gv * CIN + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NTAP; a++) {
+      const int t = wv + 4 * a;
+      if (t >= 27) break;
+      const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dzz = t / 9 - 1;
+      for (int ks = 0; ks < TV / 16; ks++) {
+        const int p0 = ks * 16 + 4 * kq;   // four voxels along x in one row
+        const int lx = p0 % TX, ly = (p0 / TX) % TY, lz = p0 / (TX * TY);
+        const int hv = (lx + 1 + dx) + HX * ((ly + 1 + dy) + HY * (lz + 1 + dzz));
+        s4 bfr[CIN / 16];
+#pragma unroll
+        for (int n = 0; n < CIN / 16; n++) {
+          const uint16_t* q = sx + (n * 16 + ri) * XS + hv;
+          bfr[n] = s4{(short)q[0], (short)q[1], (short)q[2], (short)q[3]};
+        }
+#pragma unroll
+        for (int m = 0; m < COUT / 16; m++) {
+          const s4 af = *(const s4*)(sd + (m * 16 + ri) * PS + ks * 16 + 4 * kq);
+#pragma unroll
+          for (int n = 0; n < CIN / 16; n++)
+            acc[a][m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bfr[n], acc[a][m][n], 0, 0, 0);
+        }
+      }
+    }
+  }
+  float* out = part + (long long)blockIdx.x * 27 * COUT * CIN;
+#pragma unroll
+  for (int a = 0; a < NTAP; a++) {
+    const int t = wv + 4 * a;
+    if (t >= 27) break;
+#pragma unroll
+    for (int m = 0; m < COUT / 16; m++)
+#pragma unroll
+      for (int n = 0; n < CIN / 16; n++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int o = m * 16 + 4 * kq + e, c = n * 16 + ri;
+          out[(t * COUT + o) * CIN + c] = acc[a][m][n][e];
+        }
+  }
+}
+
+// Sum of the block partials in block order; dW[o][c][t] for the real
+// channel counts (cout x cin), db[o] = sum over the bias partials.
+__global__ void __launch_bounds__(256)
+    k_wgrad_reduce(int nblk, int COUTP, int CINP, int cout, int cin, const float* __restrict__ part,
+                   float* __restrict__ dW) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cout * cin * 27) return;
+  const int t = e % 27, c = (e / 27) % cin, o = e / (27 * cin);
+  float s = 0.f;
+  for (int k = 0; k < nblk; k++) s += part[((long long)k * 27 + t) * COUTP * CINP + o * CINP + c];
+  dW[e] = s;
+}
+
+// Bias gradient partials: part[b][o] = sum of dz over voxels [b*chunk, ...)
+__global__ void __launch_bounds__(256)
+    k_bgrad(long long V, int chunk, int COUTP, const uint16_t* __restrict__ dz, float* __restrict__ part) {
+  __shared__ float s[256];
+  const int o = threadIdx.x % COUTP, lane = threadIdx.x / COUTP, nl = 256 / COUTP;
+  float acc = 0.f;
+  const long long v0 = (long long)blockIdx.x * chunk;
+  for (long long v = v0 + lane; v < v0 + chunk && v < V; v += nl) acc += bf2f(dz[v * COUTP + o]);
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < COUTP) {
+    float t = 0.f;
+    for (int k = 0; k < nl; k++) t += s[k * COUTP + threadIdx.x];
+    part[(long long)blockIdx.x * COUTP + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_bgrad_reduce(int nblk, int COUTP, int cout, const float* __restrict__ part, float* __restrict__ db) {
+  const int o = threadIdx.x;
+  if (o >= cout) return;
+  float s = 0.f;
+  for (int k = 0; k < nblk; k++) s += part[k * COUTP + o];
+  db[o] = s;
+}
+
+// ---------------------------------------------------------------------
+// loss and its gradient; warm-start output
+// ---------------------------------------------------------------------
+__device__ inline void helix_unit(double q0, int z, double h[5]) {
+  const double c = cos(q0 * z), s = sin(q0 * z);
+  h[0] = c * c - 1.0 / 3.0; h[1] = c * s; h[2] = 0.0; h[3] = s * s - 1.0 / 3.0; h[4] = 0.0;
+}
+
+// out [V][16] (channels 0..4 = dQ); Qt [5][V]; grad dz [V][16] bf16;
+// part[b] = block sum of |d|^2 over fluid voxels (FP64).
+__global__ void __launch_bounds__(256)
+    k_loss(int L, Case c, const float* __restrict__ out, const float* __restrict__ Qt, const uint8_t* __restrict__ fluid,
+           double inv_nf, uint16_t* __restrict__ dz, double* __restrict__ part) {
+  __shared__ double s[256];
+  const long long V = (long long)L * L * L;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double l2 = 0.0;
+  if (v < V) {
+    const int z = (int)(v / ((long long)L * L));
+    double h[5];
+    helix_unit(2.0 * M_PI / c.pitch, z, h);
+    float d[5];
+    for (int k = 0; k < 5; k++) d[k] = (float)(c.q_amp * h[k]) + (float)c.q_eq * out[v * 16 + k] - Qt[k * V + v];
+    const bool f = fluid[v] != 0;
+    if (f) {
+      const double xx = d[0], xy = d[1], xz = d[2], yy = d[3], yz = d[4];
+      l2 = 2.0 * (xx * xx + yy * yy + xx * yy + xy * xy + xz * xz + yz * yz);
+    }
+    const float sc = f ? (float)(c.q_eq * inv_nf) : 0.f;
+    const float g[5] = {4.f * d[0] + 2.f * d[3], 4.f * d[1], 4.f * d[2], 4.f * d[3] + 2.f * d[0], 4.f * d[4]};
+    for (int k = 0; k < 16; k++) dz[v * 16 + k] = k < 5 ? f2bf(sc * g[k]) : (uint16_t)0;
+  }
+  s[threadIdx.x] = l2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// Q_warm = q_amp * helix + q_eq * dQ into a field [5][nsites] at offset off
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_warm(int L, Case c, const float* __restrict__ out, R* __restrict__ Q, long long nsites, long long off) {
+  const long long V = (long long)L * L * L;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  double h[5];
+  helix_unit(2.0 * M_PI / c.pitch, (int)(v / ((long long)L * L)), h);
+  for (int k = 0; k < 5; k++) Q[k * nsites + off + v] = (R)(c.q_amp * h[k] + c.q_eq * (double)out[v * 16 + k]);
+}
+
+// ---------------------------------------------------------------------
+// Adam on the FP32 masters and the BF16 copies
+// ---------------------------------------------------------------------
+// W [cout][cin][27] and b [cout]; wf [27][COUTP][CINP] (forward), wb
+// [27][CINP][COUTP] with the mirrored tap (data gradient).
+__global__ void __launch_bounds__(256)
+    k_adam(int cout, int cin, int COUTP, int CINP, float* __restrict__ W, float* __restrict__ b, const float* __restrict__ dW,
+           const float* __restrict__ db, float* __restrict__ mW, float* __restrict__ vW, float* __restrict__ mb,
+           float* __restrict__ vb, float lr, float c1, float c2, int update, uint16_t* __restrict__ wf,
+           uint16_t* __restrict__ wb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nW = cout * cin * 27;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  if (e < nW) {
+    float w = W[e];
+    if (update) {
+      const float g = dW[e];
+      const float m = b1 * mW[e] + (1.f - b1) * g;
+      const float v = b2 * vW[e] + (1.f - b2) * g * g;
+      mW[e] = m;
+      vW[e] = v;
+      w -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+      W[e] = w;
+    }
+    const int t = e % 27, c = (e / 27) % cin, o = e / (27 * cin);
+    const uint16_t h = f2bf(w);
+    wf[(t * COUTP + o) * CINP + c] = h;
+    wb[((26 - t) * CINP + c) * COUTP + o] = h;
+  } else if (e < nW + cout && update) {
+    const int o = e - nW;
+    const float g = db[o];
+    const float m = b1 * mb[o] + (1.f - b1) * g;
+    const float v = b2 * vb[o] + (1.f - b2) * g * g;
+    mb[o] = m;
+    vb[o] = v;
+    b[o] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+  }
+}
+
+// conversions for the layer-level entry points: FP32 [C][V] <-> padded
+// BF16 / FP32 channels-last
+__global__ void k_pack_bf16(long long V, int C, int CP, const float* __restrict__ src, uint16_t* __restrict__ dst) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  for (int k = 0; k < CP; k++) dst[v * CP + k] = k < C ? f2bf(src[k * V + v]) : (uint16_t)0;
+}
+__global__ void k_unpack_f32(long long V, int C, int CP, const float* __restrict__ src, float* __restrict__ dst) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  for (int k = 0; k < C; k++) dst[k * V + v] = src[v * CP + k];
+}
+
+// ---------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------
+hipError_t launch_features(int L, const Case& c, uint16_t* x0, float* f32, hipStream_t s) {
+  const long long V = (long long)L * L * L;
+  k_features<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(L, c, x0, f32);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv(int cinp, int coutp, int mode, int L, const uint16_t* x, const uint16_t* w, const float* bias,
+                       const float* zprev, float* zout, uint16_t* aout, hipStream_t s) {
+  const int nblk = (L / TX) * (L / TY) * (L / TZ);
+#define LCNN_CONV(CI, CO, M)                                                            \
+  if (cinp == CI && coutp == CO && mode == M) {                                         \
+    k_conv<CI, CO, M><<<nblk, 256, 0, s>>>(L, x, w, bias, zprev, zout, aout);           \
+    return hipGetLastError();                                                           \
+  }
+  LCNN_CONV(16, 32, 0)
+  LCNN_CONV(32, 32, 0)
+  LCNN_CONV(32, 16, 1)
+  LCNN_CONV(32, 32, 2)
+  LCNN_CONV(16, 32, 2)
+  LCNN_CONV(32, 32, 3)
+  LCNN_CONV(16, 32, 3)
+  LCNN_CONV(32, 16, 3)
+#undef LCNN_CONV
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wgrad(int cinp, int coutp, int L, int nblk, int tpb, const uint16_t* dz, const uint16_t* x,
+                        float* part, hipStream_t s) {
+#define LCNN_WG(CI, CO)                                                  \
+  if (cinp == CI && coutp == CO) {                                       \
+    k_wgrad<CI, CO><<<nblk, 256, 0, s>>>(L, tpb, dz, x, part);           \
+    return hipGetLastError();                                            \
+  }
+  LCNN_WG(16, 32)
+  LCNN_WG(32, 32)
+  LCNN_WG(32, 16)
+#undef LCNN_WG
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wgrad_reduce(int nblk, int coutp, int cinp, int cout, int cin, const float* part, float* dW,
+                               hipStream_t s) {
+  const int n = cout * cin * 27;
+  k_wgrad_reduce<<<(n + 255) / 256, 256, 0, s>>>(nblk, coutp, cinp, cout, cin, part, dW);
+  return hipGetLastError();
+}
+
+hipError_t launch_bgrad(long long V, int nblk, int coutp, int cout, const uint16_t* dz, float* part, float* db,
+                        hipStream_t s) {
+  const int chunk = (int)((V + nblk - 1) / nblk);
+  k_bgrad<<<nblk, 256, 0, s>>>(V, chunk, coutp, dz, part);
+  k_bgrad_reduce<<<1, 64, 0, s>>>(nblk, coutp, cout, part, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(int L, const Case& c, const float* out, const float* Qt, const uint8_t* fluid, double inv_nf,
+                       uint16_t* dz, double* part, hipStream_t s) {
+  const long long V = (long long)L * L * L;
+  k_loss<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(L, c, out, Qt, fluid, inv_nf, dz, part);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_warm(int L, const Case& c, const float* out, R* Q, long long nsites, long long off, hipStream_t s) {
+  const long long V = (long long)L * L * L;
+  k_warm<R><<<(unsigned)((V + 255) / 256), 256, 0, s>>>(L, c, out, Q, nsites, off);
+  return hipGetLastError();
+}
+template hipError_t launch_warm<float>(int, const Case&, const float*, float*, long long, long long, hipStream_t);
+template hipError_t launch_warm<double>(int, const Case&, const float*, double*, long long, long long, hipStream_t);
+
+hipError_t launch_adam(int cout, int cin, int coutp, int cinp, float* W, float* b, const float* dW, const float* db,
+                       float* mW, float* vW, float* mb, float* vb, float lr, float c1, float c2, int update,
+                       uint16_t* wf, uint16_t* wb, hipStream_t s) {
+  const int n = cout * cin * 27 + cout;
+  k_adam<<<(n + 255) / 256, 256, 0, s>>>(cout, cin, coutp, cinp, W, b, dW, db, mW, vW, mb, vb, lr, c1, c2, update,
+                                         wf, wb);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(long long V, int C, int CP, const float* src, uint16_t* dst, hipStream_t s) {
+  k_pack_bf16<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(V, C, CP, src, dst);
+  return hipGetLastError();
+}
+hipError_t launch_unpack(long long V, int C, int CP, const float* src, float* dst, hipStream_t s) {
+  k_unpack_f32<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(V, C, CP, src, dst);
+  return hipGetLastError();
+}
+
+}  // namespace lcnn

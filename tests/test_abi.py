@@ -70,3 +70,22 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.lc_step(None, 1) == 1
     assert lib.lc_sync(None) == 1
     assert lib.lc_get_nstep(None) == -1
+
+
+def test_nn_header_symbols_exported(lib):
+    from paper_1102_2193_amd import nn
+    src = open(os.path.join(ROOT, "include", "lc_nn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(lc_nn_[A-Za-z0-9_]+)\s*\(", src)))
+    assert names == sorted(nn.EXPORTS)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert ctypes.sizeof(nn.Case) == 8 * 3 + 8 + 8 + 4 + 4 + 8 + 8
+
+
+def test_nn_create_rejects_bad_grid(lib):
+    from paper_1102_2193_amd import nn
+    L = nn._lib()
+    h = ctypes.c_void_p()
+    assert L.lc_nn_create(12, 0, None, ctypes.byref(h)) == 1
+    assert b"multiple of 8" in L.lc_nn_last_error(None)

@@ -1,0 +1,143 @@
+"""GPU checks of the warm-start network kernels against the FP64 oracle.
+
+The oracle rounds the operands to bfloat16 exactly as the kernels do and
+accumulates in FP64; the kernels accumulate in FP32 on the matrix cores, so
+layer outputs and gradients agree to FP32 accumulation error (norm-relative
+1e-5).  A chained forward pass can differ by one bfloat16 rounding of an
+intermediate activation, so it is compared at 2e-2.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+L = 16
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def nrel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.fixture(scope="module")
+def net():
+    from paper_1102_2193_amd import nn
+    say("case: network on a 16^3 grid")
+    return nn.Net(L, seed=3)
+
+
+def rand_layer(rng, l):
+    from paper_1102_2193_amd import nn
+    W = rng.normal(size=(nn.COUT[l], nn.CIN[l], 27)).astype(np.float32) * 0.1
+    b = rng.normal(size=nn.COUT[l]).astype(np.float32) * 0.1
+    return W, b
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 3])
+def test_layer_forward_matches_oracle(net, l):
+    from oracle import cnn
+    from paper_1102_2193_amd import nn
+    say("case: layer %d forward" % l)
+    rng = np.random.default_rng(10 + l)
+    W, b = rand_layer(rng, l)
+    net.set_layer(l, W, b)
+    x = rng.normal(size=(nn.CIN[l], L, L, L)).astype(np.float32)
+    z = net.layer_forward(l, x)
+    ref = cnn.conv3d(cnn.bf16_round(x), cnn.bf16_round(W), b.astype(np.float64))
+    e = nrel(z, ref)
+    say("   rel err %.3e" % e)
+    assert e < 1e-5
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 3])
+def test_layer_backward_matches_oracle(net, l):
+    from oracle import cnn
+    from paper_1102_2193_amd import nn
+    say("case: layer %d backward" % l)
+    rng = np.random.default_rng(20 + l)
+    W, b = rand_layer(rng, l)
+    net.set_layer(l, W, b)
+    x = rng.normal(size=(nn.CIN[l], L, L, L)).astype(np.float32)
+    dz = rng.normal(size=(nn.COUT[l], L, L, L)).astype(np.float32)
+    dW, db, dx = net.layer_backward(l, x, dz)
+    rdx, rdW, rdb = cnn.conv3d_backward(cnn.bf16_round(x), cnn.bf16_round(W), cnn.bf16_round(dz))
+    e = (nrel(dW, rdW), nrel(db, rdb), nrel(dx, rdx))
+    say("   rel err dW %.3e db %.3e dx %.3e" % e)
+    assert max(e) < 1e-5
+
+
+def test_features_match_oracle(net):
+    from oracle import cnn
+    from paper_1102_2193_amd import inputs, nn
+    say("case: features")
+    pitch = 16.0
+    c = nn.make_case((7.3, 8.0, 8.6), 4.5, pitch, "planar", 0.495, 0.5)
+    f = net.features(c)
+    qh = inputs.helix_q(L, L, L, 2 * math.pi / pitch, 1.0)
+    ref = cnn.features(L, (7.3, 8.0, 8.6), 4.5, pitch, -1.0, qh)
+    np.testing.assert_allclose(f, ref, atol=2e-7)
+
+
+def test_chained_forward_and_warm_start(net):
+    from oracle import cnn
+    from paper_1102_2193_amd import inputs, lc, nn
+    say("case: chained forward, warm start into a context")
+    rng = np.random.default_rng(5)
+    params = cnn.init_params(11)
+    for l, (W, b) in enumerate(params):
+        net.set_layer(l, W.astype(np.float32), (rng.normal(size=b.shape) * 0.05).astype(np.float32))
+    params = [(net.get_layer(l)[0].astype(np.float64), net.get_layer(l)[1].astype(np.float64)) for l in range(4)]
+    pitch = 16.0
+    c = nn.make_case((8.0, 8.0, 8.0), 3.5, pitch, "normal", 0.495, 0.5)
+    dq = net.predict(c)
+    qh = inputs.helix_q(L, L, L, 2 * math.pi / pitch, 1.0)
+    x = cnn.features(L, (8.0, 8.0, 8.0), 3.5, pitch, 1.0, qh)
+    ref, _ = cnn.forward(params, x, bf16=True)
+    e = nrel(dq, ref)
+    say("   chained rel err %.3e" % e)
+    assert e < 2e-2
+    ctx = lc.Context([dict(nx=L, precision="fp64", **inputs.NEMATIC)])
+    net.warm_start(c, ctx, 0)
+    Q = ctx.get_Q(0)
+    np.testing.assert_allclose(Q, 0.495 * qh + 0.5 * dq, atol=1e-6)
+
+
+def test_training_step_follows_gradient(net):
+    from oracle import cnn
+    from paper_1102_2193_amd import inputs, nn
+    say("case: one training step")
+    rng = np.random.default_rng(6)
+    params = cnn.init_params(12)
+    for l, (W, b) in enumerate(params):
+        net.set_layer(l, W.astype(np.float32), b.astype(np.float32))
+    params = [(net.get_layer(l)[0].astype(np.float64), net.get_layer(l)[1].astype(np.float64)) for l in range(4)]
+    pitch = 16.0
+    c = nn.make_case((8.0, 8.0, 8.0), 3.5, pitch, "normal", 0.495, 0.5)
+    qh = inputs.helix_q(L, L, L, 2 * math.pi / pitch, 1.0)
+    target = 0.495 * qh + 0.05 * rng.normal(size=(5, L, L, L))
+    fluid = rng.uniform(size=(L, L, L)) > 0.1
+    x = cnn.features(L, (8.0, 8.0, 8.0), 3.5, pitch, 1.0, qh)
+    out, cache = cnn.forward(params, x, bf16=True)
+    loss_ref, g = cnn.loss_and_grad(out, 0.495 * qh, target, fluid, 0.5)
+    grads = cnn.backward(params, cache, g, bf16=True)
+    lr = 1e-3
+    loss = net.train_step(c, target, fluid, lr)
+    say("   loss %.6e vs oracle %.6e" % (loss, loss_ref))
+    assert loss == pytest.approx(loss_ref, rel=1e-2)
+    for l in range(4):
+        W1, _ = net.get_layer(l)
+        step = params[l][0] - W1.astype(np.float64)
+        gW = grads[l][0]
+        big = np.abs(gW) > 0.05 * np.abs(gW).max()
+        # first Adam step moves each weight by lr against the sign of its gradient
+        agree = np.mean(np.sign(step[big]) == np.sign(gW[big]))
+        say("   layer %d: sign agreement %.4f, |step| %.3e" % (l, agree, np.abs(step[big]).mean()))
+        assert agree > 0.97
+        np.testing.assert_allclose(np.abs(step[big]), lr, rtol=1e-2)
