@@ -91,8 +91,27 @@ def batch_boxes(seed, nbox=48, sizes=(32, 40, 48, 56, 64), a_range=(3.0, 12.0),
     return out
 
 
+# Warm-start cases on a 64^3 box: pitches 128/k, each a whole number of half
+# pitches in the box.
+WARM_PITCHES = tuple(128.0 / k for k in (8, 7, 6, 5, 4, 3))
+
+
+def warmstart_case(seed, a_range=(3.0, 12.0)):
+    """One seeded warm-start case: radius ~ U[a_range], pitch drawn from
+    WARM_PITCHES, normal or planar anchoring with equal odds."""
+    r = uniform(seed, 3, stream=11)
+    a = a_range[0] + (a_range[1] - a_range[0]) * r[0]
+    p = WARM_PITCHES[min(len(WARM_PITCHES) - 1, int(r[1] * len(WARM_PITCHES)))]
+    return {"seed": int(seed), "a": float(a), "pitch": float(p), "anchoring": "normal" if r[2] < 0.5 else "planar"}
+
+
 # Material and LB parameters of the synthetic workloads (lattice units).
 NEMATIC = dict(tau=1.0, rho0=1.0, A0=0.01, gamma=3.0, K=0.01, q0=0.0, xi=0.7, Gamma=0.5)
+
+# Material parameters of the paper's cholesteric study (Sec. 3): A0 = 1,
+# K = 0.065, gamma = 3 (tau = 0), xi = 0.7, Gamma = 0.5; chirality 0.3 at
+# pitch 32.
+PAPER_CHOLESTERIC = dict(tau=1.0, rho0=1.0, A0=1.0, gamma=3.0, K=0.065, q0=0.0, xi=0.7, Gamma=0.5)
 
 # Uniaxial amplitude for S = 0.33 in the convention Q = (S/2)(3nn - I),
 # i.e. q = 1.5 S in the paper's Q = q(nn - I/3).

@@ -1,0 +1,99 @@
+"""Host-side logic of the warm-start pipeline (no GPU): case generator,
+convergence bookkeeping, steps-to-relax, the Q error measure and the
+weights file round trip."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1102_2193_amd import inputs
+from paper_1102_2193_amd import warmstart as ws
+
+
+def test_cases_are_seeded_and_in_range():
+    cs = [inputs.warmstart_case(5000 + i) for i in range(300)]
+    assert cs[7] == inputs.warmstart_case(5007)
+    assert all(3.0 <= c["a"] <= 12.0 for c in cs)
+    assert {c["pitch"] for c in cs} == set(inputs.WARM_PITCHES)
+    assert {c["anchoring"] for c in cs} == {"normal", "planar"}
+    # every pitch holds a whole number of half pitches in a 64 box
+    for p in inputs.WARM_PITCHES:
+        assert 2 * 64 / p == pytest.approx(round(2 * 64 / p), abs=1e-12)
+
+
+class _FakeContext:
+    """Stands in for a context: F of box b at step n is seq[b](n)."""
+
+    def __init__(self, seq):
+        self.seq, self.n = seq, 0
+
+    def set_Q(self, b, q):
+        pass
+
+    def step(self, n):
+        self.n += n
+
+    def diag(self, b):
+        return {"free_energy": self.seq[b](self.n)}
+
+
+def test_convergence_must_hold_for_the_whole_window(monkeypatch):
+    decay = lambda n: -1000.0 - math.exp(-n / 2000.0)
+    wobble = lambda n: -1000.0 - 0.01 * math.sin(n / 3000.0)   # turning points pass a single-window test
+    monkeypatch.setattr(ws, "make_context", lambda cases, L, hydro, tile: _FakeContext([decay, wobble]))
+    monkeypatch.setattr(ws, "helix", lambda c, L: None)
+    _, F, conv, ok = ws.relax([{}, {}], cap=60000)
+    assert ok and len(F[0]) == 60000 // ws.EVERY + 1
+    # |F(n) - F(n-1000)| = e^{-n/2000} (e^{1/2} - 1) < 1e-7 * 1000 first at
+    # n = 17557.8..., i.e. the sample at 17600; held for 4000 more steps
+    assert conv[0] == 21600
+    assert conv[1] is None
+
+
+def test_steps_to_band():
+    E = ws.EVERY
+    F = np.array([10, 5, 2, 1.0002, 1.00005, 0.99999, 1.00001, 1.0])
+    assert ws.steps_to_band(F, 1.0, 7 * E) == 4 * E
+    assert ws.steps_to_band(F, 1.0, 5 * E) == 4 * E
+    assert ws.steps_to_band(np.array([1.0, 1.0]), 1.0, E) == 0
+    # outside the band at the end: a different minimum, i.e. a fallback
+    assert ws.steps_to_band(np.array([10, 1.0, 1.5]), 1.0, 2 * E) is None
+    assert ws.steps_to_band(np.array([10, 1.0, np.nan]), 1.0, 2 * E) is None
+
+
+def test_q_error_is_the_full_tensor_frobenius_norm():
+    rng = np.random.default_rng(0)
+    d = rng.normal(size=(5, 3, 2, 2))
+    xx, xy, xz, yy, yz = d
+    M = np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, -xx - yy]])
+    fluid = np.ones((3, 2, 2), np.uint8)
+    fluid[0, 0, 0] = 0
+    ref = ((M ** 2).sum(axis=(0, 1)) * fluid).sum() / fluid.sum()
+    assert ws.q_error(d, 0 * d, fluid) == pytest.approx(ref, rel=1e-14)
+
+
+def test_fluid_mask_counts_lattice_points_outside_the_sphere():
+    for a in (3.0, 4.5, 7.3):
+        m = ws.fluid_mask({"a": a}, 32)
+        r = np.arange(-16, 16)
+        inside = sum(1 for x in r for y in r for z in r if x * x + y * y + z * z < a * a)
+        assert m.size - int(m.sum()) == inside
+
+
+def test_summary_charges_fallbacks():
+    rows = [{"n_plain": 1000, "n_warm_charged": 100, "fallback": False, "q_err_helix": 1e-2, "q_err_warm": 1e-3},
+            {"n_plain": 500, "n_warm_charged": 9500, "fallback": True, "q_err_helix": 1e-2, "q_err_warm": 1e-3},
+            {"conv": None, "q_err_helix": 1e-2, "q_err_warm": 1e-3}]
+    s = ws.summary(rows)
+    assert s["evaluated"] == 2 and s["not_converged"] == 1 and s["fallbacks"] == 1
+    assert s["ratio_of_means"] == pytest.approx(9600 / 1500)
+    assert s["warm_faster"] == 1 and s["warm_slower"] == 1
+
+
+def test_committed_weights_have_the_network_shapes():
+    from paper_1102_2193_amd import nn
+    with np.load(ws.WEIGHTS) as z:
+        for l in range(4):
+            assert z["W%d" % l].shape == (nn.COUT[l], nn.CIN[l], 27)
+            assert z["b%d" % l].shape == (nn.COUT[l],)
+            assert np.all(np.isfinite(z["W%d" % l]))
