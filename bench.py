@@ -9,7 +9,11 @@ the fused per-site kernel, moving-boundary events and the colloid update.
 Prints one JSON line: MLUPS (million lattice-site updates per second) over
 the timed steps, the fused kernel's achieved algorithmic bandwidth against
 the HBM peak, and the FP64 CPU oracle timed on a bounded sample on this
-host's cores.
+host's cores.  With the default workload it also reports the learned warm
+start, measured live: two held-out 64^3 cholesteric cases relaxed from the
+helix and from the trained network's prediction (steps to reach 1e-4 of the
+converged free energy), and the network's forward and training-step times
+against the BF16 matrix-core peak.
 """
 import argparse
 import json
@@ -26,6 +30,14 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per lattice update in FP32: f (19) + Q (5) + u (3) values,
 # each read once and written once
 BYTES_PER_LU = {"fp32": 2 * (19 + 5 + 3) * 4, "fp64": 2 * (19 + 5 + 3) * 8}
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# multiply-adds per voxel of the warm-start network (3^3 taps, channels
+# 12 -> 32 -> 32 -> 32 -> 5): forward; a training step adds the weight
+# gradients of all four layers and the input gradients of layers 1-3
+NN_MACS = [27 * ci * co for ci, co in ((12, 32), (32, 32), (32, 32), (32, 5))]
+NN_FWD_FLOP_PER_VOXEL = 2 * sum(NN_MACS)
+NN_TRAIN_FLOP_PER_VOXEL = 2 * (2 * sum(NN_MACS) + sum(NN_MACS[1:]))
+WARM_SEEDS = (9010, 9042)
 
 
 def workload(name):
@@ -118,6 +130,51 @@ def cpu_baseline(wl, target_s):
             "sample": "first %d steps of the %d^3 box in FP64 (%.1f s)" % (n, L, dt)}
 
 
+def network_leg(L=64, reps=20):
+    """Forward and training-step time of the warm-start network (HIP events
+    on its stream) against the BF16 dense matrix-core peak."""
+    import numpy as np
+    from paper_1102_2193_amd import inputs, nn
+    from paper_1102_2193_amd import warmstart as ws
+    net = nn.Net(L)
+    ws.load_weights(net, ws.WEIGHTS)
+    c = inputs.warmstart_case(WARM_SEEDS[0])
+    target = ws.helix(c, L)
+    fluid = ws.fluid_mask(c, L)
+    net.time(ws.nn_case(c, L), target, fluid, n=3)
+    t = net.time(ws.nn_case(c, L), target, fluid, n=reps)
+    net.close()
+    fwd = NN_FWD_FLOP_PER_VOXEL * L ** 3 / (t["forward_ms"] * 1e-3) / 1e12
+    trn = NN_TRAIN_FLOP_PER_VOXEL * L ** 3 / (t["train_step_ms"] * 1e-3) / 1e12
+    return {"grid": [L, L, L], "forward_ms": round(t["forward_ms"], 4), "train_step_ms": round(t["train_step_ms"], 4),
+            "roofline": {"bound": "mfma", "achieved": round(fwd, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(fwd / MFMA_BF16_PEAK_TFLOPS, 4),
+                         "flop_per_launch": NN_FWD_FLOP_PER_VOXEL * L ** 3, "pass": "forward"},
+            "train_tflops": round(trn, 1), "train_frac": round(trn / MFMA_BF16_PEAK_TFLOPS, 4),
+            "train_flop": NN_TRAIN_FLOP_PER_VOXEL * L ** 3}
+
+
+def warm_start_leg(L=64):
+    """Plain vs warm relaxation of two held-out cases, live."""
+    from paper_1102_2193_amd import inputs, nn
+    from paper_1102_2193_amd import warmstart as ws
+    t0 = time.perf_counter()
+    net = nn.Net(L)
+    ws.load_weights(net, ws.WEIGHTS)
+    cases = [inputs.warmstart_case(s) for s in WARM_SEEDS]
+    held = ws.relaxed_states(cases, L, 60000, len(cases), 0, None, "plain")
+    rows = ws.compare(net, held, L, 60000, 0, None, len(cases))
+    net.close()
+    s = ws.summary(rows)
+    return {"metric": "steps to |F - F*| <= 1e-4 |F*|", "grid": [L, L, L],
+            "params": "A0=1, K=0.065, gamma=3, xi=0.7, Gamma=0.5, flow off, W=inf",
+            "cases": [{k: r.get(k) for k in ("seed", "a", "pitch", "anchoring", "n_plain", "n_warm", "fallback")}
+                      for r in rows],
+            "plain_steps_mean": s.get("plain_steps_mean"), "warm_steps_mean": s.get("warm_steps_mean"),
+            "fallbacks": s.get("fallbacks"), "sample_every": ws.EVERY,
+            "seconds": round(time.perf_counter() - t0, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +185,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="also time graph replay (1)")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start and network legs")
+    ap.add_argument("--network-only", action="store_true", help="only time the warm-start network")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -138,6 +197,10 @@ def main():
 
     import torch
     from paper_1102_2193_amd import lc, tune
+
+    if args.network_only:
+        print(json.dumps({"network": network_leg()}), flush=True)
+        return
 
     if args.calib_copy_mib:
         n = args.calib_copy_mib << 20
@@ -183,7 +246,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic), "traffic_source": traffic_src,
-                     "kernel": "k_step (fused)", "kernel_ms": round(tk["kernel_ms"], 5),
+                     "kernel": "fused step kernel", "kernel_ms": round(tk["kernel_ms"], 5),
                      "bytes_per_launch": bpl * sites},
         "wall_s": round(wall, 3),
     }
@@ -198,6 +261,9 @@ def main():
         out["ms_per_step_graph"] = round(start.elapsed_time(stop) / args.steps, 5)
     ctx.sync()
     ctx.close()
+    if not args.no_warm_start and args.workload == "drag128_fp32":
+        out["warm_start"] = warm_start_leg()
+        out["network"] = network_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

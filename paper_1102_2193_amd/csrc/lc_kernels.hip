@@ -20,6 +20,14 @@
 
 namespace lc {
 
+// Barrier that orders LDS only: global loads issued before it stay in
+// flight (the populations are requested at kernel entry).
+__device__ inline void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename R>
 __device__ inline R wave_sum(R v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -44,25 +52,6 @@ __device__ inline void block_sum(double (&v)[NV], double* sred, double* out) {
   }
 }
 
-// Add the block sums of NV doubles per thread to acc[0..NV) (threads < NV);
-// acc is read back after a later barrier.
-template <int NT, int NV>
-__device__ inline void block_accumulate(double (&v)[NV], double* sred, double* acc) {
-  constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; k++) {
-    double s = wave_sum(v[k]);
-    if (lane == 0) sred[w * NV + k] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    double s = 0.0;
-    for (int i = 0; i < NW; i++) s += sred[i * NV + threadIdx.x];
-    acc[threadIdx.x] += s;
-  }
-}
-
 // ---------------------------------------------------------------------
 // fused step
 // ---------------------------------------------------------------------
@@ -78,13 +67,6 @@ __device__ inline T* at32(T* base, unsigned idx) {
   return (T*)((char*)base + idx * (unsigned)sizeof(T));
 }
 
-// Barrier that orders LDS only: global loads issued before it stay in
-// flight (the populations are requested at kernel entry).
-__device__ inline void lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // Block = one TX x TY x TZ tile, one thread per node.  LDS holds Q with a
 // halo of two nodes, solid flags, the velocity with a halo of one, the full
@@ -306,6 +288,14 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
     bool solid_nb[19];
 #pragma unroll
     for (int i = 0; i < 19; i++) solid_nb[i] = NEAR ? (bool)sS[qc + cx(i) + cy(i) * QSY + cz(i) * QSZ] : false;
+    // solid-link sums of this site: stress-face force and its torque about
+    // r_site, bounce-back momentum
+    double fps[3] = {0.0, 0.0, 0.0}, fts[3] = {0.0, 0.0, 0.0}, bbp[3] = {0.0, 0.0, 0.0};
+    bool anys = false;
+    if (NEAR) {
+#pragma unroll
+      for (int i = 1; i < 19; i++) anys = anys || solid_nb[i];
+    }
     if (hydro) {
       // force on the fluid: differences of P between opposite faces
       const int loc[3] = {lx, ly, lz}, ext[3] = {TX, TY, TZ}, ist[3] = {1, TX, TX * TY};
@@ -325,20 +315,18 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
           const R pm = sm ? pcv : (R)0.5 * (pcv + pmv);
           F[c] += pp - pm;
         }
-        // colloid force and torque from the solid-fluid faces
+        // colloid force and torque from the solid-fluid faces: a face with
+        // sign sg passes -sg P[:,b] at r_site + (sg/2) x_b, whose torque
+        // about the centre is r_site x ps - (1/2) x_b x P[:,b]
         if (NEAR && (sp || sm)) {
-#pragma unroll
-          for (int sg = 1; sg >= -1; sg -= 2) {
-            if (sg > 0 ? !sp : !sm) continue;
-            double ps[3], r[3];
-            for (int c = 0; c < 3; c++) ps[c] = -(double)sg * (double)sPi[(3 * c + b) * NT + tid];
-            const double e[3] = {b == 0 ? 0.5 * sg : 0.0, b == 1 ? 0.5 * sg : 0.0, b == 2 ? 0.5 * sg : 0.0};
-            rel_pos(B, Rc, gx + e[0], gy + e[1], gz + e[2], r);
-            part[3] += ps[0]; part[4] += ps[1]; part[5] += ps[2];
-            part[9] += r[1] * ps[2] - r[2] * ps[1];
-            part[10] += r[2] * ps[0] - r[0] * ps[2];
-            part[11] += r[0] * ps[1] - r[1] * ps[0];
-          }
+          const double nsg = (sp ? 1.0 : 0.0) - (sm ? 1.0 : 0.0);
+          const double hc = 0.5 * ((sp ? 1.0 : 0.0) + (sm ? 1.0 : 0.0));
+          const double p0 = (double)sPi[(3 * 0 + b) * NT + tid], p1 = (double)sPi[(3 * 1 + b) * NT + tid],
+                       p2 = (double)sPi[(3 * 2 + b) * NT + tid];
+          fps[0] -= nsg * p0; fps[1] -= nsg * p1; fps[2] -= nsg * p2;
+          if (b == 0) { fts[1] += hc * p2; fts[2] -= hc * p1; }
+          else if (b == 1) { fts[0] -= hc * p2; fts[2] += hc * p0; }
+          else { fts[0] += hc * p1; fts[1] -= hc * p0; }
         }
       }
 #pragma unroll
@@ -424,29 +412,48 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
       const int dyp = gy + 1 == ny ? nx * (1 - ny) : nx, dym = gy == 0 ? nx * (ny - 1) : -nx;
       const int dzp = gz + 1 == nz ? nxy * (1 - nz) : nxy, dzm = gz == 0 ? nxy * (nz - 1) : -nxy;
       const int dxs[3] = {dxm, 0, dxp}, dys[3] = {dym, 0, dyp}, dzs[3] = {dzm, 0, dzp};
+      // rigid-body velocity at this site: on a link of direction c its
+      // projection equals that at the link midpoint, c.(w x c/2) = 0
+      R ubs[3] = {(R)0, (R)0, (R)0};
+      if (NEAR && anys) {
+        double r[3], ub[3];
+        rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
+        rigid_vel(B, r, ub);
+#pragma unroll
+        for (int c = 0; c < 3; c++) ubs[c] = (R)ub[c];
+      }
 #pragma unroll
       for (int i = 0; i < 19; i++) {
         if (!NEAR || !solid_nb[i]) {
           const unsigned gn = g + (unsigned)(dxs[cx(i) + 1] + dys[cy(i) + 1] + dzs[cz(i) + 1]);
           *at32(a.fout + i * NS, gn) = fs[i];
         } else {
-          // bounce-back on the link with the moving-wall correction
-          double r[3], ub[3];
-          rel_pos(B, Rc, gx + 0.5 * cx(i), gy + 0.5 * cy(i), gz + 0.5 * cz(i), r);
-          rigid_vel(B, r, ub);
-          const double cub = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
-          const double corr = 6.0 * wgt(i) * B.rho0 * cub;
-          __builtin_nontemporal_store((R)((double)fs[i] - corr), at32(a.fout + opp(i) * NS, g));
-          const double m = 2.0 * ((double)fs[i] + wgt(i)) - corr;
-          const double dp[3] = {m * cx(i), m * cy(i), m * cz(i)};
-          part[0] += dp[0]; part[1] += dp[1]; part[2] += dp[2];
-          part[6] += r[1] * dp[2] - r[2] * dp[1];
-          part[7] += r[2] * dp[0] - r[0] * dp[2];
-          part[8] += r[0] * dp[1] - r[1] * dp[0];
+          // bounce-back on the link with the moving-wall correction; the
+          // link passes (2 f_i - corr) c_i to the colloid at r_site + c_i/2,
+          // whose torque about the centre is r_site x dp (c_i x c_i = 0)
+          const R cub = (R)cx(i) * ubs[0] + (R)cy(i) * ubs[1] + (R)cz(i) * ubs[2];
+          const R corr = (R)(6.0 * wgt(i)) * (R)B.rho0 * cub;
+          __builtin_nontemporal_store(fs[i] - corr, at32(a.fout + opp(i) * NS, g));
+          const double m = 2.0 * ((double)fs[i] + wgt(i)) - (double)corr;
+          if (cx(i)) bbp[0] += cx(i) > 0 ? m : -m;
+          if (cy(i)) bbp[1] += cy(i) > 0 ? m : -m;
+          if (cz(i)) bbp[2] += cz(i) > 0 ? m : -m;
         }
       }
 #pragma unroll
       for (int c = 0; c < 3; c++) __builtin_nontemporal_store(u[c], at32(a.uout + c * NS, g));
+    }
+    if (NEAR && anys) {
+      double r[3];
+      rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
+      part[0] += bbp[0]; part[1] += bbp[1]; part[2] += bbp[2];
+      part[6] += r[1] * bbp[2] - r[2] * bbp[1];
+      part[7] += r[2] * bbp[0] - r[0] * bbp[2];
+      part[8] += r[0] * bbp[1] - r[1] * bbp[0];
+      part[3] += fps[0]; part[4] += fps[1]; part[5] += fps[2];
+      part[9] += (r[1] * fps[2] - r[2] * fps[1]) + fts[0];
+      part[10] += (r[2] * fps[0] - r[0] * fps[2]) + fts[1];
+      part[11] += (r[0] * fps[1] - r[1] * fps[0]) + fts[2];
     }
     if (bad) atomicOr(a.flag, 1);
   };
@@ -480,8 +487,7 @@ struct MarchSmem {
   unsigned char S[5][QP];
   R U[4][3 * UP];
   R P[2][PS];
-  double red[(NT / 64) * 12];
-  double acc[12];         // colloid force/torque accumulated over the planes
+  double red[(NT / 64) * 12];   // per-wave colloid force/torque, summed over the planes
 };
 
 // Block = TX x TY columns marching through CZ planes in z, one thread per
@@ -694,7 +700,8 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   int qs_m1 = 1, qs_0 = 2, qs_p1 = 3, qs_p2 = 4, qs_free = 0;  // slots of planes k-1..k+2, k+3
   int us_m1 = 0, us_0 = 1, us_p1 = 2, us_free = 3;
   int ps_0 = 0;
-  if (tid < 12) sm.acc[tid] = 0.0;
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane < 12) sm.red[wv * 12 + lane] = 0.0;
 
   // populations of the own column, one plane ahead of their use
   R f[19];
@@ -726,6 +733,8 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     const int ic = (ly + 2) * QPX + lx + 2;
     const int iu = (ly + 1) * UPX + lx + 1;
     const bool fluid = !sm.S[qs_0][ic];
+    // the solid-aware update only where plane k's links can reach the colloid
+    const bool pnear = near && block_near(B, Rc, x0 - 2, y0 - 2, k - 2, TX + 4, TY + 4, 5);
     auto update = [&](auto near_tag) {
       constexpr bool NEAR = decltype(near_tag)::value;
       R q5[5], dQ[5];
@@ -742,6 +751,14 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
         sn[i] = NEAR ? (bool)sm.S[sl][ic + cx(i) + cy(i) * QPX] : false;
       }
       R F[3] = {(R)0, (R)0, (R)0};
+      // solid-link sums of this site: stress-face force and its torque about
+      // r_site, bounce-back momentum
+      double fps[3] = {0.0, 0.0, 0.0}, fts[3] = {0.0, 0.0, 0.0}, bbp[3] = {0.0, 0.0, 0.0};
+      bool anys = false;
+      if (NEAR) {
+#pragma unroll
+        for (int i = 1; i < 19; i++) anys = anys || sn[i];
+      }
       if (hydro) {
         const R* Pp = sm.P[ps_0];
         R Pc[3][3];   // own stress, [c][b]
@@ -773,18 +790,16 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
             F[c] += pp - pm;
           }
           if (NEAR && (sp || sm_)) {
-#pragma unroll
-            for (int sg = 1; sg >= -1; sg -= 2) {
-              if (sg > 0 ? !sp : !sm_) continue;
-              double ps[3], r[3];
-              for (int c = 0; c < 3; c++) ps[c] = -(double)sg * (double)Pc[c][b];
-              const double e[3] = {b == 0 ? 0.5 * sg : 0.0, b == 1 ? 0.5 * sg : 0.0, b == 2 ? 0.5 * sg : 0.0};
-              rel_pos(B, Rc, gx + e[0], gy + e[1], gz + e[2], r);
-              part[3] += ps[0]; part[4] += ps[1]; part[5] += ps[2];
-              part[9] += r[1] * ps[2] - r[2] * ps[1];
-              part[10] += r[2] * ps[0] - r[0] * ps[2];
-              part[11] += r[0] * ps[1] - r[1] * ps[0];
-            }
+            // a face to a solid node with sign sg passes -sg P[:,b] to the
+            // colloid at r_site + (sg/2) x_b; its torque about the centre
+            // is r_site x ps - (1/2) x_b x P[:,b] for either sign
+            const double nsg = (sp ? 1.0 : 0.0) - (sm_ ? 1.0 : 0.0);
+            const double hc = 0.5 * ((sp ? 1.0 : 0.0) + (sm_ ? 1.0 : 0.0));
+            const double p0 = (double)Pc[0][b], p1 = (double)Pc[1][b], p2 = (double)Pc[2][b];
+            fps[0] -= nsg * p0; fps[1] -= nsg * p1; fps[2] -= nsg * p2;
+            if (b == 0) { fts[1] += hc * p2; fts[2] -= hc * p1; }
+            else if (b == 1) { fts[0] -= hc * p2; fts[2] += hc * p0; }
+            else { fts[0] += hc * p1; fts[1] -= hc * p0; }
           }
         }
 #pragma unroll
@@ -869,37 +884,70 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
         const int dyp = gy + 1 == ny ? nx * (1 - ny) : nx, dym = gy == 0 ? nx * (ny - 1) : -nx;
         const int dzp = gz + 1 == nz ? nxy * (1 - nz) : nxy, dzm = gz == 0 ? nxy * (nz - 1) : -nxy;
         const int dxs[3] = {dxm, 0, dxp}, dys[3] = {dym, 0, dyp}, dzs[3] = {dzm, 0, dzp};
+        // rigid-body velocity at this site: on a link of direction c its
+        // projection equals that at the link midpoint, c.(w x c/2) = 0
+        R ubs[3] = {(R)0, (R)0, (R)0};
+        if (NEAR && anys) {
+          double r[3], ub[3];
+          rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
+          rigid_vel(B, r, ub);
+#pragma unroll
+          for (int c = 0; c < 3; c++) ubs[c] = (R)ub[c];
+        }
 #pragma unroll
         for (int i = 0; i < 19; i++) {
           if (!NEAR || !sn[i]) {
             const unsigned gn = g + (unsigned)(dxs[cx(i) + 1] + dys[cy(i) + 1] + dzs[cz(i) + 1]);
             *at32(a.fout + i * NS, gn) = fs[i];
           } else {
-            double r[3], ub[3];
-            rel_pos(B, Rc, gx + 0.5 * cx(i), gy + 0.5 * cy(i), gz + 0.5 * cz(i), r);
-            rigid_vel(B, r, ub);
-            const double cub = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
-            const double corr = 6.0 * wgt(i) * B.rho0 * cub;
-            __builtin_nontemporal_store((R)((double)fs[i] - corr), at32(a.fout + opp(i) * NS, g));
-            const double m = 2.0 * ((double)fs[i] + wgt(i)) - corr;
-            const double dp[3] = {m * cx(i), m * cy(i), m * cz(i)};
-            part[0] += dp[0]; part[1] += dp[1]; part[2] += dp[2];
-            part[6] += r[1] * dp[2] - r[2] * dp[1];
-            part[7] += r[2] * dp[0] - r[0] * dp[2];
-            part[8] += r[0] * dp[1] - r[1] * dp[0];
+            // link bounce-back with the moving-wall term; the link passes
+            // (2 f_i - corr) c_i to the colloid at r_site + c_i/2, whose
+            // torque about the centre is r_site x dp (c_i x c_i = 0)
+            const R cub = (R)cx(i) * ubs[0] + (R)cy(i) * ubs[1] + (R)cz(i) * ubs[2];
+            const R corr = (R)(6.0 * wgt(i)) * (R)B.rho0 * cub;
+            __builtin_nontemporal_store(fs[i] - corr, at32(a.fout + opp(i) * NS, g));
+            const double m = 2.0 * ((double)fs[i] + wgt(i)) - (double)corr;
+            if (cx(i)) bbp[0] += cx(i) > 0 ? m : -m;
+            if (cy(i)) bbp[1] += cy(i) > 0 ? m : -m;
+            if (cz(i)) bbp[2] += cz(i) > 0 ? m : -m;
           }
         }
 #pragma unroll
         for (int c = 0; c < 3; c++) __builtin_nontemporal_store(u[c], at32(a.uout + c * NS, g));
       }
+      if (NEAR && anys) {
+        double r[3];
+        rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
+        part[0] += bbp[0]; part[1] += bbp[1]; part[2] += bbp[2];
+        part[6] += r[1] * bbp[2] - r[2] * bbp[1];
+        part[7] += r[2] * bbp[0] - r[0] * bbp[2];
+        part[8] += r[0] * bbp[1] - r[1] * bbp[0];
+        part[3] += fps[0]; part[4] += fps[1]; part[5] += fps[2];
+        part[9] += (r[1] * fps[2] - r[2] * fps[1]) + fts[0];
+        part[10] += (r[2] * fps[0] - r[0] * fps[2]) + fts[1];
+        part[11] += (r[0] * fps[1] - r[1] * fps[0]) + fts[2];
+      }
       if (bad) atomicOr(a.flag, 1);
     };
     if (incol && fluid) {
-      if (near) update(std::true_type{});
+      if (pnear) update(std::true_type{});
       else update(std::false_type{});
     }
     if (more) fetch_f(k + 1);
-    if (near) block_accumulate<NT, 12>(part, sm.red, sm.acc);
+    if (pnear) {
+      // wave sums in plane order into the wave's own slots (no barrier);
+      // waves without a solid link this plane skip the reduction
+      bool any = false;
+#pragma unroll
+      for (int c = 0; c < 12; c++) any = any || part[c] != 0.0;
+      if (__any(any)) {
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+          const double v = wave_sum(part[c]);
+          if (lane == 0) sm.red[wv * 12 + c] += v;
+        }
+      }
+    }
 
     // rotate: planes k+3 (Q) and k+2 (u) enter the free slots
     if (more) {
@@ -922,7 +970,13 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     for (int c = 0; c < 3; c++) { pz_m[c] = pz_c[c]; pz_c[c] = pz_n[c]; }
   }
 
-  if (near && tid < 12) a.part[12LL * (B.tile_base + tt.y) + tid] = sm.acc[tid];
+  // the last plane's barrier has ordered every wave's sums: add them in
+  // wave order
+  if (near && tid < 12) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; w++) t += sm.red[w * 12 + tid];
+    a.part[12LL * (B.tile_base + tt.y) + tid] = t;
+  }
 }
 
 // ---------------------------------------------------------------------

@@ -224,17 +224,28 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Sum of the block partials in block order; dW[o][c][t] for the real
-// channel counts (cout x cin), db[o] = sum over the bias partials.
+// Sum of the weight-gradient block partials part[k][t][o][c] (padded
+// COUTP x CINP) into dW[o][c][t] for the real channel counts.  A workgroup
+// takes 64 consecutive partial entries (coalesced rows); wave w sums blocks
+// w, w+4, ... and the four wave sums are added in wave order, so the result
+// does not depend on timing.
 __global__ void __launch_bounds__(256)
     k_wgrad_reduce(int nblk, int COUTP, int CINP, int cout, int cin, const float* __restrict__ part,
                    float* __restrict__ dW) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= cout * cin * 27) return;
-  const int t = e % 27, c = (e / 27) % cin, o = e / (27 * cin);
-  float s = 0.f;
-  for (int k = 0; k < nblk; k++) s += part[((long long)k * 27 + t) * COUTP * CINP + o * CINP + c];
-  dW[e] = s;
+  __shared__ float s[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int np = 27 * COUTP * CINP;
+  const int i = blockIdx.x * 64 + lane;
+  float acc = 0.f;
+  if (i < np)
+    for (int k = w; k < nblk; k += 4) acc += part[(long long)k * np + i];
+  s[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && i < np) {
+    const float t4 = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
+    const int c = i % CINP, o = (i / CINP) % COUTP, t = i / (CINP * COUTP);
+    if (o < cout && c < cin) dW[(o * cin + c) * 27 + t] = t4;
+  }
 }
 
 // Bias gradient partials: part[b][o] = sum of dz over voxels [b*chunk, ...)
@@ -254,12 +265,21 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-__global__ void k_bgrad_reduce(int nblk, int COUTP, int cout, const float* __restrict__ part, float* __restrict__ db) {
-  const int o = threadIdx.x;
-  if (o >= cout) return;
-  float s = 0.f;
-  for (int k = 0; k < nblk; k++) s += part[k * COUTP + o];
-  db[o] = s;
+// db[o] = sum of the bias partials; thread group g sums blocks g, g+ng, ...
+// and the group sums are added in group order.
+__global__ void __launch_bounds__(256)
+    k_bgrad_reduce(int nblk, int COUTP, int cout, const float* __restrict__ part, float* __restrict__ db) {
+  __shared__ float s[256];
+  const int o = threadIdx.x % COUTP, g = threadIdx.x / COUTP, ng = 256 / COUTP;
+  float acc = 0.f;
+  for (int k = g; k < nblk; k += ng) acc += part[k * COUTP + o];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < cout) {
+    float t = 0.f;
+    for (int k = 0; k < ng; k++) t += s[k * COUTP + threadIdx.x];
+    db[threadIdx.x] = t;
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -412,8 +432,8 @@ hipError_t launch_wgrad(int cinp, int coutp, int L, int nblk, int tpb, const uin
 
 hipError_t launch_wgrad_reduce(int nblk, int coutp, int cinp, int cout, int cin, const float* part, float* dW,
                                hipStream_t s) {
-  const int n = cout * cin * 27;
-  k_wgrad_reduce<<<(n + 255) / 256, 256, 0, s>>>(nblk, coutp, cinp, cout, cin, part, dW);
+  const int np = 27 * coutp * cinp;
+  k_wgrad_reduce<<<(np + 63) / 64, 256, 0, s>>>(nblk, coutp, cinp, cout, cin, part, dW);
   return hipGetLastError();
 }
 
@@ -421,7 +441,7 @@ hipError_t launch_bgrad(long long V, int nblk, int coutp, int cout, const uint16
                         hipStream_t s) {
   const int chunk = (int)((V + nblk - 1) / nblk);
   k_bgrad<<<nblk, 256, 0, s>>>(V, chunk, coutp, dz, part);
-  k_bgrad_reduce<<<1, 64, 0, s>>>(nblk, coutp, cout, part, db);
+  k_bgrad_reduce<<<1, 256, 0, s>>>(nblk, coutp, cout, part, db);
   return hipGetLastError();
 }
 

@@ -184,7 +184,7 @@ int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out) 
   const int ntile = (L / 8) * (L / 8) * (L / 4);
   n->tpb = (ntile + 511) / 512;
   n->wblk = (ntile + n->tpb - 1) / n->tpb;
-  n->bblk = 256;
+  n->bblk = 1024;
   n->lblk = (int)((V + 255) / 256);
   bool ok = true;
   auto dmalloc = [&](void** p, size_t sz) {

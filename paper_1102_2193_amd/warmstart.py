@@ -61,7 +61,7 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_ne
 
 
 def log(*a):
-    print(*a, flush=True)
+    print(*a, file=sys.stderr, flush=True)
 
 
 def nn_case(c, L):
