@@ -487,11 +487,11 @@ struct MarchSmem {
   unsigned char S[5][QP];
   R U[4][3 * UP];
   R P[2][PS];
-  double red[(NT / 64) * 12];   // per-wave colloid force/torque, summed over the planes
+  double red[2][(NT / 64) * 12];   // per-wave colloid sums of the current z group (two sets)
 };
 
-// Block = TX x TY columns marching through CZ planes in z, one thread per
-// column.  Each plane's stress is computed once per column (full at the
+// Block = TX x TY columns marching through the z planes of one work item
+// (whole groups of kGroup planes), one thread per column.  Each plane's stress is computed once per column (full at the
 // columns, the x or y column on the four face rows around the tile); the
 // z faces take their stress from the neighbouring planes' results held in
 // registers.  Planes of Q (halo 2) and u (halo 1) are loaded one step ahead
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(TX* TY)
     k_march(const BoxDev* __restrict__ boxes, const int2* __restrict__ tiles, StepPtrs<R> a) {
   const int2 tt = tiles[blockIdx.x];
   if (tt.x < 0) return;  // padding entry (whole block)
-  const BoxDev& B = boxes[tt.x];
+  const BoxDev& B = boxes[item_box(tt.x)];
   __shared__ MarchSmem<R, TX, TY> sm;
   if (B.q0 != 0.0) march_tile<R, TX, TY, CZ, true>(B, tt, a, sm);
   else march_tile<R, TX, TY, CZ, false>(B, tt, a, sm);
@@ -522,13 +522,17 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
 
   const int nx = B.nx, ny = B.ny, nz = B.nz, hydro = B.hydro;
   const int nxy = nx * ny;
-  const int tix = tt.y % B.ntx, tiy = (tt.y / B.ntx) % B.nty, tiz = tt.y / (B.ntx * B.nty);
-  const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * CZ;
-  const int zend = z0 + CZ < nz ? z0 + CZ : nz;
+  const int cb = item_cb(tt.y), g0 = item_g0(tt.y), ng = item_ng(tt.x);
+  const int ncb = B.ntx * B.nty;
+  const int tix = cb % B.ntx, tiy = cb / B.ntx;
+  const int x0 = tix * TX, y0 = tiy * TY, z0 = g0 * kGroup;
+  const int zend = z0 + ng * kGroup < nz ? z0 + ng * kGroup : nz;
   const unsigned off = (unsigned)B.off;
   const long long NS = a.nsites;
   const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
-  const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, CZ + 4);
+  // nominal extent (whole groups): every group's own test (in k_finalize)
+  // covers a subset of this range, so a group counted there was written here
+  const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, ng * kGroup + 4);
   const Mat<R> mp(B);
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
@@ -673,6 +677,23 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     }
   };
 
+  constexpr int NW = NT / 64;
+  for (int e = tid; e < 2 * NW * 12; e += NT) (&sm.red[0][0])[e] = 0.0;
+  // colloid sums of group g of this item (after the barrier that ends its
+  // last plane): waves added in wave order, written to the group's slot, and
+  // the set cleared for group g + 2 (at least one barrier later)
+  auto flush = [&](int g) {
+    if (near && tid < 12) {
+      double* r = sm.red[g & 1];
+      double t = 0.0;
+      for (int w = 0; w < NW; w++) {
+        t += r[w * 12 + tid];
+        r[w * 12 + tid] = 0.0;
+      }
+      a.part[12LL * (B.tile_base + cb + (long long)ncb * (g0 + g)) + tid] = t;
+    }
+  };
+
   // prologue: Q planes z0-2 .. z0+2 in slots 0..4, u planes z0-1 .. z0+1
   // in slots 0..2
   for (int k = 0; k < 5; k++) {
@@ -701,7 +722,6 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   int us_m1 = 0, us_0 = 1, us_p1 = 2, us_free = 3;
   int ps_0 = 0;
   const int lane = tid & 63, wv = tid >> 6;
-  if (lane < 12) sm.red[wv * 12 + lane] = 0.0;
 
   // populations of the own column, one plane ahead of their use
   R f[19];
@@ -716,6 +736,8 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   fetch_f(z0);
 
   for (int k = z0; k < zend; k++) {
+    const int gi = (k - z0) / kGroup;
+    if (k > z0 && k - z0 == gi * kGroup) flush(gi - 1);
     double part[12];
 #pragma unroll
     for (int c = 0; c < 12; c++) part[c] = 0.0;
@@ -944,7 +966,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
 #pragma unroll
         for (int c = 0; c < 12; c++) {
           const double v = wave_sum(part[c]);
-          if (lane == 0) sm.red[wv * 12 + c] += v;
+          if (lane == 0) sm.red[gi & 1][wv * 12 + c] += v;
         }
       }
     }
@@ -970,13 +992,8 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     for (int c = 0; c < 3; c++) { pz_m[c] = pz_c[c]; pz_c[c] = pz_n[c]; }
   }
 
-  // the last plane's barrier has ordered every wave's sums: add them in
-  // wave order
-  if (near && tid < 12) {
-    double t = 0.0;
-    for (int w = 0; w < NT / 64; w++) t += sm.red[w * 12 + tid];
-    a.part[12LL * (B.tile_base + tt.y) + tid] = t;
-  }
+  // the last plane's barrier has ordered every wave's sums of the last group
+  flush((zend - 1 - z0) / kGroup);
 }
 
 // ---------------------------------------------------------------------

@@ -17,7 +17,8 @@ struct StepPtrs {
   const R* uin;
   R* uout;
   long long nsites;   // component stride (all boxes)
-  double* part;       // per-tile colloid partial sums, 12 doubles
+  double* part;       // colloid partial sums, 12 doubles per 3D tile or per
+                      // (column block, z group) of the marching kernel
   int* flag;          // set to 1 on a non-finite value or |u| >= 0.3
 };
 
@@ -33,10 +34,26 @@ struct StepPtrs {
   X(5, 32, 16, 8, 1)     \
   X(6, 16, 8, 2, 0)      \
   X(7, 32, 16, 16, 1)
+// FP64 (the verification precision) uses the 3D-tile form only.
 #define LC_TILES_F64(X)  \
-  X(0, 16, 8, 8, 1)      \
-  X(1, 8, 4, 4, 0)       \
-  X(2, 16, 4, 2, 0)
+  X(0, 8, 4, 4, 0)       \
+  X(1, 16, 4, 2, 0)
+
+// Marching kernel work items.  The z extent of a box is cut into groups of
+// kGroup planes; the colloid sums are kept per (column block, group), so they
+// do not depend on how groups are bundled into work items.  A work item is
+// the int2 (box | ng << 16, cb | g0 << 16): box, number of groups ng, column
+// block cb (x fastest) and first group g0.  Limits: box, cb < 2^16;
+// g0, ng < 2^15.  Padding items have x = -1.
+constexpr int kGroup = 1;
+constexpr int kMaxBoxes = 1 << 16, kMaxColBlocks = 1 << 16, kMaxGroups = 1 << 15;
+__host__ __device__ inline int2 march_item(int box, int cb, int g0, int ng) {
+  return make_int2(box | (ng << 16), cb | (g0 << 16));
+}
+__host__ __device__ inline int item_box(int x) { return x & 0xffff; }
+__host__ __device__ inline int item_ng(int x) { return x >> 16; }
+__host__ __device__ inline int item_cb(int y) { return y & 0xffff; }
+__host__ __device__ inline int item_g0(int y) { return y >> 16; }
 
 template <typename R>
 hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles,

@@ -115,25 +115,88 @@ int pull_boxes(lc_ctx* c) {
   return LC_OK;
 }
 
+// Can the colloid (radius + 3 + margin) reach the block [lo, lo + ext) in any
+// periodic image?  The integer test of the kernels, widened by `margin`
+// sites; used only to decide how work is cut, never what is computed.
+const int kMargin = 2;       // sites of colloid motion covered between layouts
+const int kNearPlanes = 2;   // planes per work item where the colloid can reach
+
+bool host_near(const lc_params& p, const lc_colloid& k, int x0, int y0, int z0, int ex, int ey, int ez,
+               int margin) {
+  if (!k.present) return false;
+  const int ra = (int)ceil(k.a0) + 3 + margin;
+  const int lo[3] = {x0, y0, z0}, ext[3] = {ex, ey, ez}, L[3] = {p.nx, p.ny, p.nz};
+  for (int a = 0; a < 3; a++) {
+    const int cc = (int)floor(k.pos[a]);
+    int best = 1 << 30;
+    for (int m = -1; m <= 1; m++) {
+      const int q = cc + m * L[a];
+      const int d = q < lo[a] ? lo[a] - q : (q > lo[a] + ext[a] - 1 ? q - (lo[a] + ext[a] - 1) : 0);
+      best = d < best ? d : best;
+    }
+    if (best > ra) return false;
+  }
+  return true;
+}
+
 // Rebuild descriptors, tile list and launch ranges for the current tile
 // shape and colloids; upload.
+//
+// Marching kernel: each column block's z groups are bundled into work items
+// of the shape's plane count, except where the colloid can reach, where
+// every group is an item of its own (the solid-aware path costs about twice
+// as much per plane).  Those short items go first in the launch, spread over
+// the dies, so that the hardware's in-order dispatch starts them at once and
+// fills the remaining time with the long items.
 int layout(lc_ctx* c) {
   const TileShape& T = tile_shape(c, c->tile);
   long long tb = 0, gb = 0, eb = 0;
   int eblk = 0;
   c->any_colloid = c->any_moving = false;
-  std::vector<int2> tiles;
+  std::vector<int2> tiles, near_items;
+  if (T.kind == 1 && c->nbox > lc::kMaxBoxes) return fail(c, LC_EINVAL, "too many boxes for the marching kernel");
   for (int b = 0; b < c->nbox; b++) {
     BoxDev& B = c->hb[b];
     const lc_params& p = c->prm[b];
     const lc_colloid& k = c->col[b];
     B.ntx = (p.nx + T.x - 1) / T.x;
     B.nty = (p.ny + T.y - 1) / T.y;
-    B.ntz = (p.nz + T.z - 1) / T.z;
     B.tile_base = (int)tb;
-    const int nt = B.ntx * B.nty * B.ntz;
-    for (int t = 0; t < nt; t++) tiles.push_back(make_int2(b, t));
-    tb += nt;
+    if (T.kind == 1) {
+      const int ngz = (p.nz + lc::kGroup - 1) / lc::kGroup;
+      const int ncb = B.ntx * B.nty;
+      if (ncb > lc::kMaxColBlocks || ngz > lc::kMaxGroups)
+        return fail(c, LC_EINVAL, "box too large for the marching kernel's work items");
+      B.ntz = ngz;
+      const int chunk = std::max(1, T.z / lc::kGroup);
+      const int near_chunk = std::max(1, kNearPlanes / lc::kGroup);
+      for (int cb = 0; cb < ncb; cb++) {
+        const int x0 = (cb % B.ntx) * T.x, y0 = (cb / B.ntx) * T.y;
+        auto gnear = [&](int g) {
+          return host_near(p, k, x0 - 2, y0 - 2, g * lc::kGroup - 2, T.x + 4, T.y + 4, lc::kGroup + 4, kMargin);
+        };
+        int g = 0;
+        while (g < ngz) {
+          if (gnear(g)) {
+            int n = 1;
+            while (n < near_chunk && g + n < ngz && gnear(g + n)) n++;
+            near_items.push_back(lc::march_item(b, cb, g, n));
+            g += n;
+            continue;
+          }
+          int n = 1;
+          while (n < chunk && g + n < ngz && !gnear(g + n)) n++;
+          tiles.push_back(lc::march_item(b, cb, g, n));
+          g += n;
+        }
+      }
+      tb += (long long)ncb * ngz;
+    } else {
+      B.ntz = (p.nz + T.z - 1) / T.z;
+      const int nt = B.ntx * B.nty * B.ntz;
+      for (int t = 0; t < nt; t++) tiles.push_back(make_int2(b, t));
+      tb += nt;
+    }
     B.present = k.present;
     B.motion = k.motion;
     B.anchoring = k.anchoring;
@@ -160,17 +223,40 @@ int layout(lc_ctx* c) {
     c->any_colloid |= (bool)k.present;
     c->any_moving |= moving;
   }
+  if (tb > (1LL << 30)) return fail(c, LC_EINVAL, "too many tiles");
+  if (T.kind == 1) {
+    // every (box, column block, group) exactly once, inside its box
+    std::vector<unsigned char> seen((size_t)tb, 0);
+    for (const auto* list : {&near_items, &tiles})
+      for (const int2& it : *list) {
+        const int b = lc::item_box(it.x), ng = lc::item_ng(it.x), cb = lc::item_cb(it.y), g0 = lc::item_g0(it.y);
+        if (b >= c->nbox) return fail(c, LC_EINVAL, "internal: bad marching work item");
+        const BoxDev& B = c->hb[b];
+        if (ng < 1 || cb >= B.ntx * B.nty || g0 + ng > B.ntz)
+          return fail(c, LC_EINVAL, "internal: bad marching work item");
+        for (int g = g0; g < g0 + ng; g++) {
+          unsigned char& s = seen[(size_t)B.tile_base + cb + (size_t)B.ntx * B.nty * g];
+          if (s++) return fail(c, LC_EINVAL, "internal: overlapping marching work items");
+        }
+      }
+    for (unsigned char s : seen)
+      if (!s) return fail(c, LC_EINVAL, "internal: marching work items leave a gap");
+  }
   c->ntile = (int)tb;
   c->ghost_total = gb;
   c->event_total = eb;
-  // XCD-aware order: workgroup i runs on die i % 8, so die d gets the
-  // contiguous chunk d of the spatial tile list.
-  const int per = (c->ntile + kXcd - 1) / kXcd;
-  c->nblk = per * kXcd;
+  // Launch order: the near items (padded to a whole number of rounds over
+  // the dies), then the rest so that workgroup i, which runs on die i % 8,
+  // takes from the contiguous chunk (i % 8) of the spatial list (L2 locality).
+  const int nn = (int)((near_items.size() + kXcd - 1) / kXcd) * kXcd;
+  const int nt = (int)tiles.size();
+  const int per = (nt + kXcd - 1) / kXcd;
+  c->nblk = nn + per * kXcd;
   std::vector<int2> order(c->nblk, make_int2(-1, 0));
-  for (int i = 0; i < c->nblk; i++) {
+  for (int i = 0; i < (int)near_items.size(); i++) order[i] = near_items[i];
+  for (int i = 0; i < per * kXcd; i++) {
     const int s = (i % kXcd) * per + i / kXcd;
-    if (s < c->ntile) order[i] = tiles[s];
+    if (s < nt) order[nn + i] = tiles[s];
   }
   if (c->dtiles) hipFree(c->dtiles);
   if (c->dpart) hipFree(c->dpart);
@@ -225,7 +311,7 @@ hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t
     if (e != hipSuccess) return e;
   }
   const TileShape& T = tile_shape(c, c->tile);
-  return lc::launch_finalize(T.x, T.y, T.z, c->nbox, c->dbox, c->dpart, c->depart, c->dforce, c->dhist,
+  return lc::launch_finalize(T.x, T.y, T.kind ? lc::kGroup : T.z, c->nbox, c->dbox, c->dpart, c->depart, c->dforce, c->dhist,
                              kHistCap, c->dcount, c->stream);
 }
 
