@@ -500,15 +500,20 @@ template <typename R, int TX, int TY, int CZ, bool CHIRAL>
 __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const StepPtrs<R>& a,
                                            MarchSmem<R, TX, TY>& sm);
 
+// Persistent form: block b works through its own list of items.
 template <typename R, int TX, int TY, int CZ>
 __global__ void __launch_bounds__(TX* TY)
-    k_march(const BoxDev* __restrict__ boxes, const int2* __restrict__ tiles, StepPtrs<R> a) {
-  const int2 tt = tiles[blockIdx.x];
-  if (tt.x < 0) return;  // padding entry (whole block)
-  const BoxDev& B = boxes[item_box(tt.x)];
+    k_march(const BoxDev* __restrict__ boxes, const int2* __restrict__ items, const int* __restrict__ offs,
+            StepPtrs<R> a) {
   __shared__ MarchSmem<R, TX, TY> sm;
-  if (B.q0 != 0.0) march_tile<R, TX, TY, CZ, true>(B, tt, a, sm);
-  else march_tile<R, TX, TY, CZ, false>(B, tt, a, sm);
+  const int i0 = offs[blockIdx.x], i1 = offs[blockIdx.x + 1];
+  for (int it = i0; it < i1; it++) {
+    const int2 tt = items[it];
+    const BoxDev& B = boxes[item_box(tt.x)];
+    if (it > i0) lds_sync();   // the previous item's LDS reads are done
+    if (B.q0 != 0.0) march_tile<R, TX, TY, CZ, true>(B, tt, a, sm);
+    else march_tile<R, TX, TY, CZ, false>(B, tt, a, sm);
+  }
 }
 
 template <typename R, int TX, int TY, int CZ, bool CHIRAL>
@@ -1350,12 +1355,12 @@ __global__ void __launch_bounds__(256) k_fill_f(R* f, long long NS, const double
 // launchers
 // ---------------------------------------------------------------------
 template <typename R>
-hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const StepPtrs<R>& a,
-                       hipStream_t s) {
+hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const int* offs,
+                       const StepPtrs<R>& a, hipStream_t s) {
 #define LC_TILE_CASE(ID, X, Y, Z, KIND)                                               \
   case ID:                                                                             \
     if constexpr (KIND == 0) k_step<R, X, Y, Z><<<nblk, X * Y * Z, 0, s>>>(boxes, tiles, a); \
-    else k_march<R, X, Y, Z><<<nblk, X * Y, 0, s>>>(boxes, tiles, a);                       \
+    else k_march<R, X, Y, Z><<<nblk, X * Y, 0, s>>>(boxes, tiles, offs, a);                 \
     break;
   if constexpr (sizeof(R) == 4) {
     switch (tile) {
@@ -1370,6 +1375,21 @@ hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tile
   }
 #undef LC_TILE_CASE
   return hipGetLastError();
+}
+
+int march_blocks_per_cu(int tile) {
+  int n = 0;
+#define LC_OCC_CASE(ID, X, Y, Z, KIND)                                                           \
+  case ID:                                                                                      \
+    if constexpr (KIND == 1)                                                                     \
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<float, X, Y, Z>, X * Y, 0) != hipSuccess) n = 0; \
+    break;
+  switch (tile) {
+    LC_TILES_F32(LC_OCC_CASE)
+    default: break;
+  }
+#undef LC_OCC_CASE
+  return n;
 }
 
 hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part,
@@ -1415,7 +1435,7 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
 }
 
 #define LC_INST(R)                                                                                        \
-  template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const StepPtrs<R>&,               \
+  template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const int*, const StepPtrs<R>&,               \
                                      hipStream_t);                                                          \
   template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, hipStream_t);           \
   template hipError_t launch_events<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*,          \

@@ -55,9 +55,15 @@ __host__ __device__ inline int item_ng(int x) { return x >> 16; }
 __host__ __device__ inline int item_cb(int y) { return y & 0xffff; }
 __host__ __device__ inline int item_g0(int y) { return y >> 16; }
 
+// One launch of the fused kernel.  3D tiles: one block per entry of
+// `tiles`.  Marching shapes: `nblk` persistent blocks, block b taking the
+// work items tiles[offs[b]] .. tiles[offs[b+1]-1] in order.
 template <typename R>
-hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles,
+hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const int* offs,
                        const StepPtrs<R>& a, hipStream_t s);
+// Resident blocks per compute unit of FP32 marching shape `tile` (0 if the
+// shape is not a marching one).
+int march_blocks_per_cu(int tile);
 // tx, ty, tz: extents of one tile (3D tile or marching column chunk)
 hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part,
                            const double* epart, double* force, double* hist, int cap, long long* count,

@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -56,6 +58,7 @@ struct lc_ctx {
   int nblk = 0;                 // fused-kernel blocks (incl. XCD padding)
   int ntile = 0;                // real tiles
   int2* dtiles = nullptr;
+  int* doffs = nullptr;         // marching shapes: item range of each persistent block
   double* dpart = nullptr;      // 12 per tile
   long long ghost_total = 0, event_total = 0;
   double* depart = nullptr;     // 6 per event block
@@ -119,7 +122,10 @@ int pull_boxes(lc_ctx* c) {
 // periodic image?  The integer test of the kernels, widened by `margin`
 // sites; used only to decide how work is cut, never what is computed.
 const int kMargin = 2;       // sites of colloid motion covered between layouts
-const int kNearPlanes = 2;   // planes per work item where the colloid can reach
+// Cost model of marching work, in plane-times of the solid-free path: a
+// fixed start per work item (prologue loads and stresses) plus one per
+// plane, about twice that per plane where the colloid can reach (measured).
+const double kItemStart = 1.08, kNearPlaneCost = 1.64;
 
 bool host_near(const lc_params& p, const lc_colloid& k, int x0, int y0, int z0, int ex, int ey, int ez,
                int margin) {
@@ -139,6 +145,107 @@ bool host_near(const lc_params& p, const lc_colloid& k, int x0, int y0, int z0, 
   return true;
 }
 
+// Persistent-block schedule of the marching kernel.  The z groups of every
+// column block, taken in spatial order (box, column block, z), carry an
+// estimated cost: one plane-time per plane, kNearPlaneCost where the
+// colloid can reach, plus kItemStart for each work item (run of groups of
+// one column block) a block starts.  The sequence is cut into at most
+// `slots` contiguous segments, each at most `cap`, with the smallest cap
+// found by bisection; segment r goes to block (r / per_die) + 8 (r % per_die),
+// so every die takes a contiguous part of the domain (L2 locality).  Every
+// (box, column block, group) is checked to be covered exactly once.
+int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& order, std::vector<int>& offs) {
+  struct Grp {
+    int b, cb, g;
+    double cost;
+  };
+  std::vector<Grp> grp;
+  for (int b = 0; b < c->nbox; b++) {
+    const BoxDev& B = c->hb[b];
+    const lc_params& p = c->prm[b];
+    const lc_colloid& k = c->col[b];
+    const int ncb = B.ntx * B.nty;
+    for (int cb = 0; cb < ncb; cb++) {
+      const int x0 = (cb % B.ntx) * T.x, y0 = (cb / B.ntx) * T.y;
+      for (int g = 0; g < B.ntz; g++) {
+        const bool nr =
+            host_near(p, k, x0 - 2, y0 - 2, g * lc::kGroup - 2, T.x + 4, T.y + 4, lc::kGroup + 4, kMargin);
+        grp.push_back({b, cb, g, lc::kGroup * (nr ? kNearPlaneCost : 1.0)});
+      }
+    }
+  }
+  // segments of the group sequence under a cap: start index of each
+  auto cut = [&](double cap, std::vector<size_t>* starts) {
+    int n = 0;
+    double load = 0.0;
+    for (size_t i = 0; i < grp.size(); i++) {
+      const bool cont = n > 0 && grp[i].b == grp[i - 1].b && grp[i].cb == grp[i - 1].cb;
+      const double add = grp[i].cost + (cont ? 0.0 : kItemStart);
+      if (n == 0 || load + add > cap) {
+        n++;
+        load = grp[i].cost + kItemStart;
+        if (starts) starts->push_back(i);
+      } else {
+        load += add;
+      }
+    }
+    return n;
+  };
+  double lo = kItemStart, hi = kItemStart;
+  for (const Grp& x : grp) {
+    lo = std::max(lo, x.cost + kItemStart);
+    hi += x.cost + kItemStart;
+  }
+  for (int it = 0; it < 60 && hi - lo > 1e-6 * hi; it++) {
+    const double mid = 0.5 * (lo + hi);
+    if (cut(mid, nullptr) <= slots) hi = mid;
+    else lo = mid;
+  }
+  std::vector<size_t> starts;
+  const int nseg = cut(hi, &starts);
+  if (nseg > slots) return fail(c, LC_EINVAL, "internal: marching schedule does not fit");
+  starts.push_back(grp.size());
+  const int per_die = slots / kXcd;
+  std::vector<std::vector<int2>> bins(slots);
+  for (int r = 0; r < nseg; r++) {
+    std::vector<int2>& bn = bins[(r / per_die) + kXcd * (r % per_die)];
+    size_t i = starts[r];
+    while (i < starts[r + 1]) {
+      size_t j = i + 1;
+      while (j < starts[r + 1] && grp[j].b == grp[i].b && grp[j].cb == grp[i].cb) j++;
+      if (j - i > (size_t)(lc::kMaxGroups - 1)) j = i + (lc::kMaxGroups - 1);
+      bn.push_back(lc::march_item(grp[i].b, grp[i].cb, grp[i].g, (int)(j - i)));
+      i = j;
+    }
+  }
+  // coverage: every (box, column block, group) exactly once
+  long long total = 0;
+  for (int b = 0; b < c->nbox; b++) total += (long long)c->hb[b].ntx * c->hb[b].nty * c->hb[b].ntz;
+  std::vector<unsigned char> seen((size_t)total, 0);
+  for (const auto& bn : bins)
+    for (const int2& it : bn) {
+      const int b = lc::item_box(it.x), ng = lc::item_ng(it.x), cb = lc::item_cb(it.y), g0 = lc::item_g0(it.y);
+      if (b >= c->nbox) return fail(c, LC_EINVAL, "internal: bad marching work item");
+      const BoxDev& B = c->hb[b];
+      if (ng < 1 || cb >= B.ntx * B.nty || g0 + ng > B.ntz)
+        return fail(c, LC_EINVAL, "internal: bad marching work item");
+      for (int g = g0; g < g0 + ng; g++) {
+        unsigned char& sn = seen[(size_t)B.tile_base + cb + (size_t)B.ntx * B.nty * g];
+        if (sn++) return fail(c, LC_EINVAL, "internal: overlapping marching work items");
+      }
+    }
+  for (unsigned char sn : seen)
+    if (!sn) return fail(c, LC_EINVAL, "internal: marching work items leave a gap");
+  order.clear();
+  offs.assign(1, 0);
+  for (const auto& bn : bins) {
+    for (const int2& it : bn) order.push_back(it);
+    offs.push_back((int)order.size());
+  }
+  if (order.empty()) order.push_back(make_int2(-1, 0));
+  return LC_OK;
+}
+
 // Rebuild descriptors, tile list and launch ranges for the current tile
 // shape and colloids; upload.
 //
@@ -153,7 +260,7 @@ int layout(lc_ctx* c) {
   long long tb = 0, gb = 0, eb = 0;
   int eblk = 0;
   c->any_colloid = c->any_moving = false;
-  std::vector<int2> tiles, near_items;
+  std::vector<int2> tiles;
   if (T.kind == 1 && c->nbox > lc::kMaxBoxes) return fail(c, LC_EINVAL, "too many boxes for the marching kernel");
   for (int b = 0; b < c->nbox; b++) {
     BoxDev& B = c->hb[b];
@@ -168,28 +275,6 @@ int layout(lc_ctx* c) {
       if (ncb > lc::kMaxColBlocks || ngz > lc::kMaxGroups)
         return fail(c, LC_EINVAL, "box too large for the marching kernel's work items");
       B.ntz = ngz;
-      const int chunk = std::max(1, T.z / lc::kGroup);
-      const int near_chunk = std::max(1, kNearPlanes / lc::kGroup);
-      for (int cb = 0; cb < ncb; cb++) {
-        const int x0 = (cb % B.ntx) * T.x, y0 = (cb / B.ntx) * T.y;
-        auto gnear = [&](int g) {
-          return host_near(p, k, x0 - 2, y0 - 2, g * lc::kGroup - 2, T.x + 4, T.y + 4, lc::kGroup + 4, kMargin);
-        };
-        int g = 0;
-        while (g < ngz) {
-          if (gnear(g)) {
-            int n = 1;
-            while (n < near_chunk && g + n < ngz && gnear(g + n)) n++;
-            near_items.push_back(lc::march_item(b, cb, g, n));
-            g += n;
-            continue;
-          }
-          int n = 1;
-          while (n < chunk && g + n < ngz && !gnear(g + n)) n++;
-          tiles.push_back(lc::march_item(b, cb, g, n));
-          g += n;
-        }
-      }
       tb += (long long)ncb * ngz;
     } else {
       B.ntz = (p.nz + T.z - 1) / T.z;
@@ -224,45 +309,43 @@ int layout(lc_ctx* c) {
     c->any_moving |= moving;
   }
   if (tb > (1LL << 30)) return fail(c, LC_EINVAL, "too many tiles");
-  if (T.kind == 1) {
-    // every (box, column block, group) exactly once, inside its box
-    std::vector<unsigned char> seen((size_t)tb, 0);
-    for (const auto* list : {&near_items, &tiles})
-      for (const int2& it : *list) {
-        const int b = lc::item_box(it.x), ng = lc::item_ng(it.x), cb = lc::item_cb(it.y), g0 = lc::item_g0(it.y);
-        if (b >= c->nbox) return fail(c, LC_EINVAL, "internal: bad marching work item");
-        const BoxDev& B = c->hb[b];
-        if (ng < 1 || cb >= B.ntx * B.nty || g0 + ng > B.ntz)
-          return fail(c, LC_EINVAL, "internal: bad marching work item");
-        for (int g = g0; g < g0 + ng; g++) {
-          unsigned char& s = seen[(size_t)B.tile_base + cb + (size_t)B.ntx * B.nty * g];
-          if (s++) return fail(c, LC_EINVAL, "internal: overlapping marching work items");
-        }
-      }
-    for (unsigned char s : seen)
-      if (!s) return fail(c, LC_EINVAL, "internal: marching work items leave a gap");
-  }
   c->ntile = (int)tb;
   c->ghost_total = gb;
   c->event_total = eb;
-  // Launch order: the near items (padded to a whole number of rounds over
-  // the dies), then the rest so that workgroup i, which runs on die i % 8,
-  // takes from the contiguous chunk (i % 8) of the spatial list (L2 locality).
-  const int nn = (int)((near_items.size() + kXcd - 1) / kXcd) * kXcd;
-  const int nt = (int)tiles.size();
-  const int per = (nt + kXcd - 1) / kXcd;
-  c->nblk = nn + per * kXcd;
-  std::vector<int2> order(c->nblk, make_int2(-1, 0));
-  for (int i = 0; i < (int)near_items.size(); i++) order[i] = near_items[i];
-  for (int i = 0; i < per * kXcd; i++) {
-    const int s = (i % kXcd) * per + i / kXcd;
-    if (s < nt) order[nn + i] = tiles[s];
+  std::vector<int2> order;
+  std::vector<int> offs;
+  if (T.kind == 1) {
+    int dev = 0, cus = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = std::max(1, lc::march_blocks_per_cu(c->tile));
+    const int slots = std::max(1, cus * per_cu / kXcd) * kXcd;
+    const int rc = march_schedule(c, T, slots, order, offs);
+    if (rc != LC_OK) return rc;
+    c->nblk = slots;
+  } else {
+    // One block per tile; workgroup i, which runs on die i % 8, takes the
+    // contiguous chunk (i % 8) of the spatial list (L2 locality).
+    const int nt = (int)tiles.size();
+    const int per = (nt + kXcd - 1) / kXcd;
+    c->nblk = per * kXcd;
+    order.assign(c->nblk, make_int2(-1, 0));
+    for (int i = 0; i < per * kXcd; i++) {
+      const int s = (i % kXcd) * per + i / kXcd;
+      if (s < nt) order[i] = tiles[s];
+    }
   }
   if (c->dtiles) hipFree(c->dtiles);
+  if (c->doffs) hipFree(c->doffs);
   if (c->dpart) hipFree(c->dpart);
   c->dtiles = nullptr;
+  c->doffs = nullptr;
   c->dpart = nullptr;
-  HIPCHK(c, hipMalloc(&c->dtiles, sizeof(int2) * c->nblk));
+  HIPCHK(c, hipMalloc(&c->dtiles, sizeof(int2) * order.size()));
+  if (!offs.empty()) {
+    HIPCHK(c, hipMalloc(&c->doffs, sizeof(int) * offs.size()));
+    HIPCHK(c, hipMemcpyAsync(c->doffs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice, c->stream));
+  }
   HIPCHK(c, hipMalloc(&c->dpart, sizeof(double) * 12 * std::max(1, c->ntile)));
   HIPCHK(c, hipMemsetAsync(c->dpart, 0, sizeof(double) * 12 * std::max(1, c->ntile), c->stream));
   if ((size_t)eblk * 6 > c->depart_cap) {
@@ -271,7 +354,7 @@ int layout(lc_ctx* c) {
     c->depart_cap = std::max<size_t>(6, (size_t)eblk * 6);
     HIPCHK(c, hipMalloc(&c->depart, sizeof(double) * c->depart_cap));
   }
-  HIPCHK(c, hipMemcpyAsync(c->dtiles, order.data(), sizeof(int2) * c->nblk, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dtiles, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->dbox, c->hb.data(), sizeof(BoxDev) * c->nbox, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   destroy_graph(c);
@@ -303,7 +386,7 @@ hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t
     if (e != hipSuccess) return e;
   }
   if (k0) hipEventRecord(k0, c->stream);
-  e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, a, c->stream);
+  e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, c->doffs, a, c->stream);
   if (e != hipSuccess) return e;
   if (k1) hipEventRecord(k1, c->stream);
   if (c->any_moving) {
@@ -528,7 +611,7 @@ void lc_destroy(lc_ctx* c) {
       if (c->Q[k]) hipFree(c->Q[k]);
       if (c->u[k]) hipFree(c->u[k]);
     }
-  void* bufs[] = {c->dbox, c->dtiles, c->dpart, c->depart, c->dforce, c->dhist, c->dcount, c->dflag, c->ddiag};
+  void* bufs[] = {c->dbox, c->dtiles, c->doffs, c->dpart, c->depart, c->dforce, c->dhist, c->dcount, c->dflag, c->ddiag};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
