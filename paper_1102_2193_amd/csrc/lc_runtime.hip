@@ -174,48 +174,101 @@ int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& 
       }
     }
   }
-  // segments of the group sequence under a cap: start index of each
-  auto cut = [&](double cap, std::vector<size_t>* starts) {
-    int n = 0;
-    double load = 0.0;
-    for (size_t i = 0; i < grp.size(); i++) {
-      const bool cont = n > 0 && grp[i].b == grp[i - 1].b && grp[i].cb == grp[i - 1].cb;
-      const double add = grp[i].cost + (cont ? 0.0 : kItemStart);
-      if (n == 0 || load + add > cap) {
-        n++;
-        load = grp[i].cost + kItemStart;
-        if (starts) starts->push_back(i);
-      } else {
-        load += add;
-      }
-    }
-    return n;
+  // Pieces: every column block's run of groups is cut on its own into n
+  // pieces of about equal cost (so the pieces of uniform column blocks start
+  // at the same planes and neighbouring blocks march side by side); the n
+  // are apportioned greedily, one more piece at a time to the column block
+  // with the most expensive pieces, until the blocks are used up.
+  struct Col {
+    size_t first, last;   // group index range [first, last)
+    double cost;          // sum of group costs
+    int n;
   };
-  double lo = kItemStart, hi = kItemStart;
-  for (const Grp& x : grp) {
-    lo = std::max(lo, x.cost + kItemStart);
-    hi += x.cost + kItemStart;
+  std::vector<Col> cols;
+  for (size_t i = 0; i < grp.size();) {
+    size_t j = i;
+    double cost = 0.0;
+    while (j < grp.size() && grp[j].b == grp[i].b && grp[j].cb == grp[i].cb) cost += grp[j++].cost;
+    cols.push_back({i, j, cost, 1});
+    i = j;
   }
-  for (int it = 0; it < 60 && hi - lo > 1e-6 * hi; it++) {
-    const double mid = 0.5 * (lo + hi);
-    if (cut(mid, nullptr) <= slots) hi = mid;
-    else lo = mid;
+  auto piece = [](const Col& k) { return k.cost / k.n + kItemStart; };
+  if ((int)cols.size() <= slots) {
+    typedef std::pair<double, int> P;   // (piece cost, column)
+    std::priority_queue<P> heap;
+    for (int q = 0; q < (int)cols.size(); q++) heap.push(P(piece(cols[q]), q));
+    for (int used = (int)cols.size(); used < slots && !heap.empty(); used++) {
+      const int q = heap.top().second;
+      heap.pop();
+      if (cols[q].n >= (int)(cols[q].last - cols[q].first)) continue;   // one group per piece already
+      cols[q].n++;
+      heap.push(P(piece(cols[q]), q));
+    }
   }
-  std::vector<size_t> starts;
-  const int nseg = cut(hi, &starts);
-  if (nseg > slots) return fail(c, LC_EINVAL, "internal: marching schedule does not fit");
-  starts.push_back(grp.size());
+  struct Piece {
+    size_t first, last;
+    double cost;
+  };
+  std::vector<Piece> pieces;
+  for (const Col& k : cols) {
+    double acc = 0.0;
+    int made = 0;
+    size_t start = k.first;
+    for (size_t g = k.first; g < k.last; g++) {
+      // a new piece starts where the cumulative cost first reaches made/n
+      if (g > k.first && made < k.n && acc >= k.cost * made / k.n - 1e-9) {
+        pieces.push_back({start, g, 0.0});
+        start = g;
+      }
+      if (g == k.first || g == start) made++;
+      acc += grp[g].cost;
+    }
+    pieces.push_back({start, k.last, 0.0});
+  }
+  for (Piece& pc : pieces) {
+    pc.cost = kItemStart;
+    for (size_t g = pc.first; g < pc.last; g++) pc.cost += grp[g].cost;
+  }
+  // Pieces ordered by (box, first plane, column block); the q-th goes to
+  // block (q / per_die) + 8 (q % per_die), so each die takes every column
+  // block of a slab of planes and the halo rows its blocks share with their
+  // x and y neighbours pass through the same L2.  With more pieces than
+  // blocks (very large boxes), the extra pieces go longest first to the
+  // least loaded block of the same die.
+  std::stable_sort(pieces.begin(), pieces.end(), [&](const Piece& u, const Piece& v) {
+    const Grp& a = grp[u.first];
+    const Grp& b = grp[v.first];
+    if (a.b != b.b) return a.b < b.b;
+    if (a.g != b.g) return a.g < b.g;
+    return a.cb < b.cb;
+  });
   const int per_die = slots / kXcd;
+  const int np = (int)pieces.size();
   std::vector<std::vector<int2>> bins(slots);
-  for (int r = 0; r < nseg; r++) {
-    std::vector<int2>& bn = bins[(r / per_die) + kXcd * (r % per_die)];
-    size_t i = starts[r];
-    while (i < starts[r + 1]) {
-      size_t j = i + 1;
-      while (j < starts[r + 1] && grp[j].b == grp[i].b && grp[j].cb == grp[i].cb) j++;
-      if (j - i > (size_t)(lc::kMaxGroups - 1)) j = i + (lc::kMaxGroups - 1);
-      bn.push_back(lc::march_item(grp[i].b, grp[i].cb, grp[i].g, (int)(j - i)));
-      i = j;
+  std::vector<double> load(slots, 0.0);
+  const int per_die_pieces = (np + kXcd - 1) / kXcd;
+  for (int d = 0; d < kXcd; d++) {
+    const int q0 = std::min(np, d * per_die_pieces), q1 = std::min(np, (d + 1) * per_die_pieces);
+    std::vector<int> idx;
+    for (int q = q0; q < q1; q++) idx.push_back(q);
+    if ((int)idx.size() > per_die)
+      std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) { return pieces[u].cost > pieces[v].cost; });
+    for (int t = 0; t < (int)idx.size(); t++) {
+      int j = t;
+      if (t >= per_die) {
+        j = 0;
+        for (int m = 1; m < per_die; m++)
+          if (load[d + kXcd * m] < load[d + kXcd * j]) j = m;
+      }
+      const int blk = d + kXcd * j;
+      const Piece& pc = pieces[idx[t]];
+      load[blk] += pc.cost;
+      size_t i = pc.first;
+      while (i < pc.last) {
+        size_t e = std::min(pc.last, i + (size_t)(lc::kMaxGroups - 1));
+        bins[blk].push_back(lc::march_item(grp[i].b, grp[i].cb, grp[i].g, (int)(e - i)));
+        i = e;
+      }
     }
   }
   // coverage: every (box, column block, group) exactly once
