@@ -81,25 +81,28 @@ __device__ inline void rigid_vel(const BoxDev& B, const double r[3], double ub[3
   ub[2] = B.vel[2] + (B.omega[0] * r[1] - B.omega[1] * r[0]);
 }
 
-// Conservative integer test: can any node of the block [lo, lo+ext) (per
-// axis) lie within two lattice spacings of the colloid surface?  Blocks for
-// which this is false have no solid node within reach of their stencils.
+// Conservative integer test, one axis: can the colloid (radius + 3 sites)
+// reach [lo, lo+ext) along axis a in some periodic image?
+__device__ inline bool axis_near(const BoxDev& B, const double R[3], int a, int lo, int ext) {
+  const int ra = (int)ceil(B.a0) + 3;
+  const int L = a == 0 ? B.nx : (a == 1 ? B.ny : B.nz);
+  const int c = (int)floor(R[a]);
+  int best = 1 << 30;
+  for (int k = -1; k <= 1; k++) {
+    const int cc = c + k * L;
+    const int d = cc < lo ? lo - cc : (cc > lo + ext - 1 ? cc - (lo + ext - 1) : 0);
+    best = d < best ? d : best;
+  }
+  return best <= ra;
+}
+
+// Can any node of the block [lo, lo+ext) (per axis) lie within two lattice
+// spacings of the colloid surface?  Blocks for which this is false have no
+// solid node within reach of their stencils.
 __device__ inline bool block_near(const BoxDev& B, const double R[3], int x0, int y0, int z0,
                                   int ex, int ey, int ez) {
   if (!B.present) return false;
-  const int ra = (int)ceil(B.a0) + 3;
-  const int lo[3] = {x0, y0, z0}, ext[3] = {ex, ey, ez}, L[3] = {B.nx, B.ny, B.nz};
-  for (int a = 0; a < 3; a++) {
-    int c = (int)floor(R[a]);
-    int best = 1 << 30;
-    for (int k = -1; k <= 1; k++) {
-      int cc = c + k * L[a];
-      int d = cc < lo[a] ? lo[a] - cc : (cc > lo[a] + ext[a] - 1 ? cc - (lo[a] + ext[a] - 1) : 0);
-      best = d < best ? d : best;
-    }
-    if (best > ra) return false;
-  }
-  return true;
+  return axis_near(B, R, 0, x0, ex) && axis_near(B, R, 1, y0, ey) && axis_near(B, R, 2, z0, ez);
 }
 
 // ---------------------------------------------------------------------

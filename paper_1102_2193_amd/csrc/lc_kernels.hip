@@ -34,21 +34,58 @@ __device__ inline R wave_sum(R v) {
   return v;
 }
 
-// Reduce n doubles per thread over the block into out[0..n) (thread 0).
-template <int NT, int NV>
-__device__ inline void block_sum(double (&v)[NV], double* sred, double* out) {
-  constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// Sums over the 64 lanes of a full wave of NV <= 16 doubles per lane, in a
+// fixed order.  The values are padded to P = 2^LOG; at exchange s the lanes
+// split on lane bit 5-s, each keeping one half of its values and adding the
+// partner's copy of that half, so P-1 shuffles reduce all of them at once;
+// the remaining lane bits are then summed.  Lane l returns the total of
+// value (l >> (6 - LOG)), repeated in 64 >> LOG consecutive lanes.
+template <int NV>
+struct WaveSums {
+  static constexpr int LOG = NV <= 1 ? 0 : NV <= 2 ? 1 : NV <= 4 ? 2 : NV <= 8 ? 3 : 4;
+  static constexpr int P = 1 << LOG;
+  static constexpr int REP = 64 >> LOG;   // lanes holding each total
+  __device__ static double run(const double (&v)[NV]) {
+    static_assert(NV <= 16, "at most 16 values");
+    double w[P];
 #pragma unroll
-  for (int k = 0; k < NV; k++) {
-    double s = wave_sum(v[k]);
-    if (lane == 0) sred[w * NV + k] = s;
+    for (int i = 0; i < P; i++) w[i] = i < NV ? v[i] : 0.0;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < LOG; s++) {
+      const int half = P >> (s + 1);
+      const bool hi = (lane >> (5 - s)) & 1;
+#pragma unroll
+      for (int j = 0; j < half; j++) {
+        const double send = hi ? w[j] : w[j + half];
+        const double keep = hi ? w[j + half] : w[j];
+        w[j] = keep + __shfl_xor(send, 32 >> s, 64);
+      }
+    }
+    double r = w[0];
+#pragma unroll
+    for (int o = REP >> 1; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+    return r;
+  }
+  __device__ static int index() { return (threadIdx.x & 63) >> (6 - LOG); }
+  __device__ static bool writer() { return ((threadIdx.x & 63) & (REP - 1)) == 0 && index() < NV; }
+};
+
+// Reduce n doubles per thread over the block into out[k * stride],
+// k = 0..n-1 (threads < n).
+template <int NT, int NV>
+__device__ inline void block_sum(double (&v)[NV], double* sred, double* out, long long stride = 1) {
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6;
+  {
+    const double s = WaveSums<NV>::run(v);
+    if (WaveSums<NV>::writer()) sred[w * NV + WaveSums<NV>::index()] = s;
   }
   __syncthreads();
   if (threadIdx.x < NV) {
     double s = 0.0;
     for (int i = 0; i < NW; i++) s += sred[i * NV + threadIdx.x];
-    out[threadIdx.x] = s;
+    out[threadIdx.x * stride] = s;
   }
 }
 
@@ -467,7 +504,9 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
     double red[12];
 #pragma unroll
     for (int k = 0; k < 12; k++) red[k] = part[k];
-    block_sum<NT, 12>(red, sred, a.part + 12LL * (B.tile_base + tt.y));
+    block_sum<NT, 12>(red, sred, a.part + (B.tile_base + tt.y), a.nslot);
+  } else if (tid < 12) {
+    a.part[tid * a.nslot + B.tile_base + tt.y] = 0.0;   // every slot written each step
   }
 }
 
@@ -695,7 +734,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
         t += r[w * 12 + tid];
         r[w * 12 + tid] = 0.0;
       }
-      a.part[12LL * (B.tile_base + cb + (long long)ncb * (g0 + g)) + tid] = t;
+      a.part[tid * a.nslot + B.tile_base + cb + (long long)ncb * (g0 + g)] = t;
     }
   };
 
@@ -968,11 +1007,8 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
 #pragma unroll
       for (int c = 0; c < 12; c++) any = any || part[c] != 0.0;
       if (__any(any)) {
-#pragma unroll
-        for (int c = 0; c < 12; c++) {
-          const double v = wave_sum(part[c]);
-          if (lane == 0) sm.red[gi & 1][wv * 12 + c] += v;
-        }
+        const double v = WaveSums<12>::run(part);
+        if (WaveSums<12>::writer()) sm.red[gi & 1][wv * 12 + WaveSums<12>::index()] += v;
       }
     }
 
@@ -999,6 +1035,11 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
 
   // the last plane's barrier has ordered every wave's sums of the last group
   flush((zend - 1 - z0) / kGroup);
+  // far from the colloid every group's sums are zero: write them, so that
+  // k_finalize can add all slots without repeating the geometry test
+  if (!near && tid < 12)
+    for (int g = 0; g < (zend - z0 + kGroup - 1) / kGroup; g++)
+      a.part[tid * a.nslot + B.tile_base + cb + (long long)ncb * (g0 + g)] = 0.0;
 }
 
 // ---------------------------------------------------------------------
@@ -1155,33 +1196,38 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------
 // finalize: fixed-order sums, force history, colloid position
 // ---------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-    k_finalize(int TX, int TY, int TZ, BoxDev* __restrict__ boxes, const double* __restrict__ part,
+__global__ void __launch_bounds__(1024)
+    k_finalize(int TX, int TY, int TZ, BoxDev* __restrict__ boxes, const double* __restrict__ part, long long nslot,
                const double* __restrict__ epart, double* __restrict__ force, double* __restrict__ hist, int cap,
                long long* __restrict__ count) {
-  __shared__ double sred[4 * 12];
+  __shared__ double sred[16 * 12];
   __shared__ double sres[12];
   const int b = blockIdx.x;
   BoxDev& B = boxes[b];
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
   if (B.present) {
+    // every tile (or column-block group) wrote its slot this step, zeros
+    // where the kernels' test found the colloid out of reach; only the
+    // others are read (the same integer test, z first)
+    const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
     const int nt = B.ntx * B.nty * B.ntz;
-    for (int k = threadIdx.x; k < nt; k += 256) {
+    for (int k = threadIdx.x; k < nt; k += 1024) {
       const int tix = k % B.ntx, tiy = (k / B.ntx) % B.nty, tiz = k / (B.ntx * B.nty);
-      if (!block_near(B, Rc, tix * TX - 2, tiy * TY - 2, tiz * TZ - 2, TX + 4, TY + 4, TZ + 4)) continue;
-      const double* p = part + 12LL * (B.tile_base + k);
-      for (int c = 0; c < 12; c++) v[c] += p[c];
+      if (!axis_near(B, Rc, 2, tiz * TZ - 2, TZ + 4) || !axis_near(B, Rc, 1, tiy * TY - 2, TY + 4) ||
+          !axis_near(B, Rc, 0, tix * TX - 2, TX + 4))
+        continue;
+      const double* p = part + B.tile_base + k;
+      for (int c = 0; c < 12; c++) v[c] += p[c * nslot];
     }
     if (B.motion == 1) {
-      for (int k = threadIdx.x; k < B.event_nblk; k += 256) {
+      for (int k = threadIdx.x; k < B.event_nblk; k += 1024) {
         const double* p = epart + 6LL * (B.event_blk0 + k);
         v[0] += p[0]; v[1] += p[1]; v[2] += p[2];
         v[6] += p[3]; v[7] += p[4]; v[8] += p[5];
       }
     }
   }
-  block_sum<256, 12>(v, sred, sres);
+  block_sum<1024, 12>(v, sred, sres);
   __syncthreads();
   if (threadIdx.x < 12) {
     const double val = B.present ? sres[threadIdx.x] : 0.0;
@@ -1392,10 +1438,10 @@ int march_blocks_per_cu(int tile) {
   return n;
 }
 
-hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part,
+hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part, long long nslot,
                            const double* epart, double* force, double* hist, int cap, long long* count,
                            hipStream_t s) {
-  k_finalize<<<nbox, 256, 0, s>>>(tx, ty, tz, boxes, part, epart, force, hist, cap, count);
+  k_finalize<<<nbox, 1024, 0, s>>>(tx, ty, tz, boxes, part, nslot, epart, force, hist, cap, count);
   return hipGetLastError();
 }
 

@@ -17,8 +17,9 @@ struct StepPtrs {
   const R* uin;
   R* uout;
   long long nsites;   // component stride (all boxes)
-  double* part;       // colloid partial sums, 12 doubles per 3D tile or per
-                      // (column block, z group) of the marching kernel
+  double* part;       // colloid partial sums, component-major: part[c * nslot + slot],
+                      // one slot per 3D tile or per (column block, z group)
+  long long nslot;
   int* flag;          // set to 1 on a non-finite value or |u| >= 0.3
 };
 
@@ -65,7 +66,7 @@ hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tile
 // shape is not a marching one).
 int march_blocks_per_cu(int tile);
 // tx, ty, tz: extents of one tile (3D tile or marching column chunk)
-hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part,
+hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part, long long nslot,
                            const double* epart, double* force, double* hist, int cap, long long* count,
                            hipStream_t s);
 template <typename R>

@@ -425,6 +425,7 @@ lc::StepPtrs<R> ptrs(lc_ctx* c, int from) {
   a.uout = (R*)c->u[1 - from];
   a.nsites = c->nsites;
   a.part = c->dpart;
+  a.nslot = std::max(1, c->ntile);
   a.flag = c->dflag;
   return a;
 }
@@ -447,7 +448,8 @@ hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t
     if (e != hipSuccess) return e;
   }
   const TileShape& T = tile_shape(c, c->tile);
-  return lc::launch_finalize(T.x, T.y, T.kind ? lc::kGroup : T.z, c->nbox, c->dbox, c->dpart, c->depart, c->dforce, c->dhist,
+  return lc::launch_finalize(T.x, T.y, T.kind ? lc::kGroup : T.z, c->nbox, c->dbox, c->dpart,
+                             std::max(1, c->ntile), c->depart, c->dforce, c->dhist,
                              kHistCap, c->dcount, c->stream);
 }
 
