@@ -129,6 +129,22 @@ def test_fp32_parity_nematic32_planar():
     check(r, 1e-5, 1e-5, tol_force=1e-3)
 
 
+def test_fp32_colloid_moving_past_the_planned_split():
+    # The marching kernel's work split is planned on the host from the
+    # colloid position at set-up (two sites of slack); the kernels test the
+    # live position, so a colloid that travels further still gets the
+    # solid-aware path wherever it reaches.
+    say("case: 32^3 fp32 cholesteric, colloid moving 4.8 sites in 60 steps")
+    L = 32
+    prm = dict(NEM, q0=2 * math.pi / 16)
+    Q0 = inputs.helix_q(L, L, L, 2 * math.pi / 16, inputs.Q_INIT)
+    col = dict(pos=(9.3, 16.2, 15.7), a0=4.0, anchoring="normal", W=0.02, S0=0.5, vel=(0.08, 0.01, -0.02),
+               motion=1)
+    r = run_pair((L, L, L), prm, 60, "fp32", colloid=col, Q0=Q0, hist=True)
+    check(r, 1e-5, 1e-5, tol_force=1e-3)
+    np.testing.assert_array_equal(np.array(r["ctx"].get_colloid(0).pos), np.array(r["ref"].get_colloid().pos))
+
+
 MODES = [(anch, motion, hydro) for anch in ("none", "normal", "planar") for motion in (0, 1) for hydro in (0, 1)]
 
 
