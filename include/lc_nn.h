@@ -62,8 +62,8 @@ int lc_nn_get_layer(lc_nn* nn, int layer, float* W, float* b);
  * them on the device). */
 int lc_nn_features(lc_nn* nn, const lc_nn_case* c, float* feat_out);
 
-/* Forward pass: dQ (5 x L^3, FP64 host).  Also leaves the activations for
- * lc_nn_train_step's backward pass. */
+/* Inference pass: dQ (5 x L^3, FP64 host).  (lc_nn_train_step runs its own
+ * forward pass, keeping the pre-activations for the backward pass.) */
 int lc_nn_predict(lc_nn* nn, const lc_nn_case* c, double* dQ_out);
 
 /* Write Q_helix + q_eq * dQ into box `box` of a context (whose box must be

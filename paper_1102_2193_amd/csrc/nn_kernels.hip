@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(256) k_features(int L, Case c, uint16_t* __res
 // x [V][CIN] bf16, w [27][COUT][CIN] bf16.  MODE 0: z = acc + b, store z
 // (FP32) and bf16(silu(z)); MODE 1: z = acc + b (FP32); MODE 2: acc times
 // silu'(zprev) stored as bf16 (data gradient through an activation);
-// MODE 3: acc stored as FP32 (plain data gradient).
+// MODE 3: acc stored as FP32 (plain data gradient); MODE 4: as MODE 0
+// without keeping z (inference).
 template <int CIN, int COUT, int MODE>
 __global__ void __launch_bounds__(256)
     k_conv(int L, const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias,
@@ -98,24 +99,36 @@ __global__ void __launch_bounds__(256)
   for (int m = 0; m < 4; m++)
 #pragma unroll
     for (int n = 0; n < COUT / 16; n++) acc[m][n] = f4{0.f, 0.f, 0.f, 0.f};
+  // weight fragments of tap t+1 are loaded while tap t runs on the matrix cores
+  constexpr int KC = CIN / 16, NN = COUT / 16;
+  s4 bcur[KC][NN], bnxt[KC][NN];
+  auto load_b = [&](int t, s4 (&bf)[KC][NN]) {
+#pragma unroll
+    for (int kc = 0; kc < KC; kc++)
+#pragma unroll
+      for (int n = 0; n < NN; n++)
+        bf[kc][n] = *(const s4*)(w + ((long long)(t * COUT + n * 16 + ri) * CIN + kc * 16 + 4 * kq));
+  };
+  load_b(0, bcur);
   for (int t = 0; t < 27; t++) {
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    if (t + 1 < 27) load_b(t + 1, bnxt);
 #pragma unroll
-    for (int kc = 0; kc < CIN / 16; kc++) {
-      s4 bf[COUT / 16];
-#pragma unroll
-      for (int n = 0; n < COUT / 16; n++)
-        bf[n] = *(const s4*)(w + ((long long)(t * COUT + n * 16 + ri) * CIN + kc * 16 + 4 * kq));
+    for (int kc = 0; kc < KC; kc++) {
 #pragma unroll
       for (int m = 0; m < 4; m++) {
         const int lx = ri & 7, ly = 2 * m + (ri >> 3);
         const int hv = (lx + 1 + dx) + HX * ((ly + 1 + dy) + HY * (wv + 1 + dz));
         const s4 af = *(const s4*)(sx + hv * CS + kc * 16 + 4 * kq);
 #pragma unroll
-        for (int n = 0; n < COUT / 16; n++)
-          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[n], acc[m][n], 0, 0, 0);
+        for (int n = 0; n < NN; n++)
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bcur[kc][n], acc[m][n], 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int kc = 0; kc < KC; kc++)
+#pragma unroll
+      for (int n = 0; n < NN; n++) bcur[kc][n] = bnxt[kc][n];
   }
 #pragma unroll
   for (int m = 0; m < 4; m++)
@@ -127,9 +140,9 @@ __global__ void __launch_bounds__(256)
         const int lx = i & 7, ly = 2 * m + (i >> 3);
         const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + wv));
         const float val = acc[m][n][e];
-        if (MODE == 0) {
+        if (MODE == 0 || MODE == 4) {
           const float z = val + bias[j];
-          zout[gv * COUT + j] = z;
+          if (MODE == 0) zout[gv * COUT + j] = z;
           aout[gv * COUT + j] = f2bf(z * sigmoidf_(z));
         } else if (MODE == 1) {
           zout[gv * COUT + j] = val + bias[j];
@@ -168,18 +181,27 @@ __global__ void __launch_bounds__(256)
   for (int tile = blockIdx.x * tpb; tile < (blockIdx.x + 1) * tpb && tile < ntile; tile++) {
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
     __syncthreads();
-    for (int e = tid; e < TV * COUT; e += 256) {
-      const int p = e / COUT, o = e - p * COUT;
+    // staged transposed ([channel][voxel]); four channels per 8-byte load
+    for (int e = tid; e < TV * (COUT / 4); e += 256) {
+      const int p = e / (COUT / 4), o = 4 * (e - p * (COUT / 4));
       const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
       const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + lz));
-      sd[o * PS + p] = dz[gv * COUT + o];
+      const uint2 u = *(const uint2*)(dz + gv * COUT + o);
+      sd[o * PS + p] = (uint16_t)(u.x & 0xffffu);
+      sd[(o + 1) * PS + p] = (uint16_t)(u.x >> 16);
+      sd[(o + 2) * PS + p] = (uint16_t)(u.y & 0xffffu);
+      sd[(o + 3) * PS + p] = (uint16_t)(u.y >> 16);
     }
-    for (int e = tid; e < HV * CIN; e += 256) {
-      const int v = e / CIN, c = e - v * CIN;
+    for (int e = tid; e < HV * (CIN / 4); e += 256) {
+      const int v = e / (CIN / 4), c = 4 * (e - v * (CIN / 4));
       const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
       const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
       const long long gv = gx + (long long)L * (gy + (long long)L * gz);
-      sx[c * XS + v] = x[gv * CIN + c];
+      const uint2 u = *(const uint2*)(x + gv * CIN + c);
+      sx[c * XS + v] = (uint16_t)(u.x & 0xffffu);
+      sx[(c + 1) * XS + v] = (uint16_t)(u.x >> 16);
+      sx[(c + 2) * XS + v] = (uint16_t)(u.y & 0xffffu);
+      sx[(c + 3) * XS + v] = (uint16_t)(u.y >> 16);
     }
     __syncthreads();
 #pragma unroll
@@ -267,10 +289,10 @@ __global__ void __launch_bounds__(256)
 
 // db[o] = sum of the bias partials; thread group g sums blocks g, g+ng, ...
 // and the group sums are added in group order.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
     k_bgrad_reduce(int nblk, int COUTP, int cout, const float* __restrict__ part, float* __restrict__ db) {
-  __shared__ float s[256];
-  const int o = threadIdx.x % COUTP, g = threadIdx.x / COUTP, ng = 256 / COUTP;
+  __shared__ float s[1024];
+  const int o = threadIdx.x % COUTP, g = threadIdx.x / COUTP, ng = 1024 / COUTP;
   float acc = 0.f;
   for (int k = g; k < nblk; k += ng) acc += part[k * COUTP + o];
   s[threadIdx.x] = acc;
@@ -406,6 +428,8 @@ hipError_t launch_conv(int cinp, int coutp, int mode, int L, const uint16_t* x, 
   }
   LCNN_CONV(16, 32, 0)
   LCNN_CONV(32, 32, 0)
+  LCNN_CONV(16, 32, 4)
+  LCNN_CONV(32, 32, 4)
   LCNN_CONV(32, 16, 1)
   LCNN_CONV(32, 32, 2)
   LCNN_CONV(16, 32, 2)
@@ -441,7 +465,7 @@ hipError_t launch_bgrad(long long V, int nblk, int coutp, int cout, const uint16
                         hipStream_t s) {
   const int chunk = (int)((V + nblk - 1) / nblk);
   k_bgrad<<<nblk, 256, 0, s>>>(V, chunk, coutp, dz, part);
-  k_bgrad_reduce<<<1, 256, 0, s>>>(nblk, coutp, cout, part, db);
+  k_bgrad_reduce<<<1, 1024, 0, s>>>(nblk, coutp, cout, part, db);
   return hipGetLastError();
 }
 

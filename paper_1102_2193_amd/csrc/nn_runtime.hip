@@ -93,12 +93,13 @@ int refresh_bf16(lc_nn* n, int l) {
   return LC_OK;
 }
 
-int forward(lc_nn* n, const lcnn::Case& k) {
+// Forward pass; `keep` stores the pre-activations for a backward pass.
+int forward(lc_nn* n, const lcnn::Case& k, bool keep) {
   NNCHK(n, lcnn::launch_features(n->L, k, n->x0, nullptr, n->stream));
   const uint16_t* in = n->x0;
   for (int l = 0; l < NL - 1; l++) {
-    NNCHK(n, lcnn::launch_conv(CINP[l], COUTP[l], 0, n->L, in, n->wf[l], n->b[l], nullptr, n->z[l], n->a[l],
-                               n->stream));
+    NNCHK(n, lcnn::launch_conv(CINP[l], COUTP[l], keep ? 0 : 4, n->L, in, n->wf[l], n->b[l], nullptr, n->z[l],
+                               n->a[l], n->stream));
     in = n->a[l];
   }
   NNCHK(n, lcnn::launch_conv(CINP[3], COUTP[3], 1, n->L, in, n->wf[3], n->b[3], nullptr, n->out, nullptr, n->stream));
@@ -182,9 +183,9 @@ int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out) 
   }
   const long long V = n->V;
   const int ntile = (L / 8) * (L / 8) * (L / 4);
-  n->tpb = (ntile + 511) / 512;
+  n->tpb = (ntile + 255) / 256;
   n->wblk = (ntile + n->tpb - 1) / n->tpb;
-  n->bblk = 1024;
+  n->bblk = 512;
   n->lblk = (int)((V + 255) / 256);
   bool ok = true;
   auto dmalloc = [&](void** p, size_t sz) {
@@ -302,7 +303,7 @@ int lc_nn_predict(lc_nn* n, const lc_nn_case* c, double* dQ_out) {
   if (!n) return LC_EINVAL;
   int rc = check_case(n, c);
   if (rc) return rc;
-  if ((rc = forward(n, to_case(c))) != LC_OK) return rc;
+  if ((rc = forward(n, to_case(c), false)) != LC_OK) return rc;
   if (dQ_out) {
     std::vector<float> h((size_t)n->V * 16);
     NNCHK(n, hipMemcpyAsync(h.data(), n->out, sizeof(float) * h.size(), hipMemcpyDeviceToHost, n->stream));
@@ -323,7 +324,7 @@ int lc_nn_warm_start(lc_nn* n, const lc_nn_case* c, lc_ctx* ctx, int box) {
   if (q.nx != n->L || q.ny != n->L || q.nz != n->L) return nfail(n, LC_EINVAL, "box is not L^3");
   NNCHK(n, hipStreamSynchronize(q.stream));
   const lcnn::Case k = to_case(c);
-  if ((rc = forward(n, k)) != LC_OK) return rc;
+  if ((rc = forward(n, k, false)) != LC_OK) return rc;
   NNCHK(n, q.prec == LC_FP32 ? lcnn::launch_warm<float>(n->L, k, n->out, (float*)q.Q, q.nsites, q.off, n->stream)
                              : lcnn::launch_warm<double>(n->L, k, n->out, (double*)q.Q, q.nsites, q.off, n->stream));
   NNCHK(n, hipStreamSynchronize(n->stream));
@@ -339,7 +340,7 @@ int lc_nn_train_step(lc_nn* n, const lc_nn_case* c, const double* Q_target, cons
   double inv_nf;
   if ((rc = upload_targets(n, Q_target, fluid, &inv_nf)) != LC_OK) return rc;
   const lcnn::Case k = to_case(c);
-  if ((rc = forward(n, k)) != LC_OK) return rc;
+  if ((rc = forward(n, k, true)) != LC_OK) return rc;
   if ((rc = loss(n, k, inv_nf, loss_out)) != LC_OK) return rc;
   if ((rc = backward_and_update(n, lr)) != LC_OK) return rc;
   NNCHK(n, hipStreamSynchronize(n->stream));
@@ -398,10 +399,10 @@ int lc_nn_time(lc_nn* n, const lc_nn_case* c, const double* Q_target, const unsi
   NNCHK(n, hipEventCreate(&e2));
   NNCHK(n, hipEventRecord(e0, n->stream));
   for (int r = 0; r < reps; r++)
-    if ((rc = forward(n, k)) != LC_OK) return rc;
+    if ((rc = forward(n, k, false)) != LC_OK) return rc;
   NNCHK(n, hipEventRecord(e1, n->stream));
   for (int r = 0; r < reps; r++) {
-    if ((rc = forward(n, k)) != LC_OK) return rc;
+    if ((rc = forward(n, k, true)) != LC_OK) return rc;
     if ((rc = loss(n, k, inv_nf, nullptr)) != LC_OK) return rc;
     if ((rc = backward_and_update(n, 0.f)) != LC_OK) return rc;
   }
