@@ -1080,15 +1080,23 @@ __global__ void __launch_bounds__(256)
   const int z = wrapc((int)floor(Rc[2]) - h + (int)(l / ((long long)E * E)), B.nz);
   if (!inside(B, Rc, x, y, z)) return;
   const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-  double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  int nf = 0;
+  // all six neighbours are read at once (the loads overlap), then the fluid
+  // ones are added in neighbour order
+  double qn[6][3][3];
+  bool fl[6];
+#pragma unroll
   for (int k = 0; k < 6; k++) {
     const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
-    if (inside(B, Rc, xn, yn, zn)) continue;
-    double q[3][3];
-    load_full(Q, NS, B.off + xn + (long long)B.nx * (yn + (long long)B.ny * zn), q);
+    load_full(Q, NS, B.off + xn + (long long)B.nx * (yn + (long long)B.ny * zn), qn[k]);
+    fl[k] = !inside(B, Rc, xn, yn, zn);
+  }
+  double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  int nf = 0;
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+    if (!fl[k]) continue;
     for (int i = 0; i < 3; i++)
-      for (int j = 0; j < 3; j++) qbar[i][j] += q[i][j];
+      for (int j = 0; j < 3; j++) qbar[i][j] += qn[k][i][j];
     nf++;
   }
   if (nf == 0) return;  // interior solid node
@@ -1125,9 +1133,9 @@ __device__ inline void advanced_pos(const BoxDev& B, double Rn[3]) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kEventBlock)
     k_events(const BoxDev* __restrict__ boxes, int nbox, long long total, StepPtrs<R> a, double* epart) {
-  __shared__ double sred[4 * 6];
+  __shared__ double sred[(kEventBlock / 64) * 6];
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[6] = {0, 0, 0, 0, 0, 0};
   // every box's range is padded to whole blocks, so a block has one box
@@ -1190,7 +1198,7 @@ __global__ void __launch_bounds__(256)
       v[5] = r[0] * p[1] - r[1] * p[0];
     }
   }
-  block_sum<256, 6>(v, sred, epart + 6LL * blockIdx.x);
+  block_sum<kEventBlock, 6>(v, sred, epart + 6LL * blockIdx.x);
 }
 
 // ---------------------------------------------------------------------
@@ -1448,7 +1456,8 @@ hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, cons
 template <typename R>
 hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  k_ghost<R><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(boxes, nbox, total, Q, NS);
+  // small blocks: the few thousand boundary candidates spread over many CUs
+  k_ghost<R><<<(unsigned)((total + 63) / 64), 64, 0, s>>>(boxes, nbox, total, Q, NS);
   return hipGetLastError();
 }
 
@@ -1456,7 +1465,7 @@ template <typename R>
 hipError_t launch_events(const BoxDev* boxes, int nbox, long long total, const StepPtrs<R>& a, double* epart,
                          hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  k_events<R><<<(unsigned)(total / 256), 256, 0, s>>>(boxes, nbox, total, a, epart);
+  k_events<R><<<(unsigned)(total / kEventBlock), kEventBlock, 0, s>>>(boxes, nbox, total, a, epart);
   return hipGetLastError();
 }
 

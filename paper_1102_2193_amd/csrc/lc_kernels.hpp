@@ -47,6 +47,9 @@ struct StepPtrs {
 // block cb (x fastest) and first group g0.  Limits: box, cb < 2^16;
 // g0, ng < 2^15.  Padding items have x = -1.
 constexpr int kGroup = 1;
+// Threads per block of the moving-boundary kernel; every box's range of
+// candidate nodes is padded to whole blocks (one box per block).
+constexpr int kEventBlock = 64;
 constexpr int kMaxBoxes = 1 << 16, kMaxColBlocks = 1 << 16, kMaxGroups = 1 << 15;
 __host__ __device__ inline int2 march_item(int box, int cb, int g0, int ng) {
   return make_int2(box | (ng << 16), cb | (g0 << 16));

@@ -355,8 +355,8 @@ int layout(lc_ctx* c) {
     B.event_base = (int)eb;
     B.event_blk0 = eblk;
     const long long ne = (long long)B.event_ext * B.event_ext * B.event_ext;
-    B.event_nblk = (int)((ne + 255) / 256);
-    eb += 256LL * B.event_nblk;
+    B.event_nblk = (int)((ne + lc::kEventBlock - 1) / lc::kEventBlock);
+    eb += (long long)lc::kEventBlock * B.event_nblk;
     eblk += B.event_nblk;
     c->any_colloid |= (bool)k.present;
     c->any_moving |= moving;
