@@ -136,6 +136,30 @@ int lc_get_Q(lc_ctx* ctx, int box, double* Q5);
 int lc_get_f(lc_ctx* ctx, int box, double* f19);   /* pre-collision f^n */
 int lc_get_u(lc_ctx* ctx, int box, double* u3);    /* velocity of the last collision */
 
+/* Checkpoint and restart (the paper describes none; this is a plain save of
+ * the evolving state).  The state holds both buffers of f, Q and u bit for
+ * bit in the context's precision (a step leaves solid nodes untouched, so
+ * the second buffer is kept too), every box's colloid at its current
+ * position, the step count, the last-step forces and the force-history
+ * rings.  Material parameters are not part of it: a context takes its own
+ * lc_params.  A context created with the same lc_params (and precision)
+ * that is given the state continues exactly as the saved one would have:
+ * every later getter returns the same bits.
+ * The format is the library's own: a header (magic "LCSTATE1", version,
+ * precision, box count, sites, step count), one record per box (shape,
+ * history count, colloid), then raw arrays in native byte order.
+ *  lc_state_bytes: the size of this context's state in bytes.
+ *  lc_get_state:   writes the state into caller-owned host memory buf of
+ *                  `bytes` >= lc_state_bytes; synchronises the stream;
+ *                  LC_ENUMERIC if a step was flagged.
+ *  lc_set_state:   reads a state written by lc_get_state.  LC_EINVAL if buf
+ *                  is NULL or short, or its precision, box count, box shapes
+ *                  or colloids do not fit this context; the context is then
+ *                  unchanged.  Clears the numeric flag. */
+int lc_state_bytes(const lc_ctx* ctx, size_t* out);
+int lc_get_state(lc_ctx* ctx, void* buf, size_t bytes);
+int lc_set_state(lc_ctx* ctx, const void* buf, size_t bytes);
+
 /* Advance every box by nsteps steps.  Each step: ghost Q at boundary solid
  * nodes (anchoring), then one fused pass per site (molecular field H,
  * stress P, force = discrete divergence of P, Beris-Edwards update of Q,

@@ -58,6 +58,16 @@ const char* lc_nn_last_error(const lc_nn* nn);
 int lc_nn_set_layer(lc_nn* nn, int layer, const float* W, const float* b);
 int lc_nn_get_layer(lc_nn* nn, int layer, float* W, float* b);
 
+/* Weights to and from a file (the optimiser state is not saved; loading
+ * resets it, as lc_nn_set_layer does).  Format: magic "LCNNWTS1", int
+ * version 1, int layer count 4, then per layer int C_out, C_in, 27, 0 and
+ * the FP32 W [C_out][C_in][27] and b [C_out], native byte order.  The
+ * weights do not depend on L.  LC_EINVAL if the file cannot be opened or
+ * written, or is not a weight file of this network (the network is then
+ * unchanged). */
+int lc_nn_save(lc_nn* nn, const char* path);
+int lc_nn_load(lc_nn* nn, const char* path);
+
 /* Input features of a case: 12 x L^3 floats (may be NULL to only build
  * them on the device). */
 int lc_nn_features(lc_nn* nn, const lc_nn_case* c, float* feat_out);

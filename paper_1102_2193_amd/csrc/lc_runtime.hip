@@ -533,6 +533,30 @@ int get(lc_ctx* c, const void* dev, int box, int ncomp, double* dst, bool shift)
                             : get_field<double>(c, dev, box, ncomp, dst, shift ? 1.0 : 0.0);
 }
 
+// Validate a colloid for a box; v gets it with the centre wrapped into the box.
+int check_colloid(const lc_params& p, const lc_colloid& k, lc_colloid& v, std::string& why) {
+  v = k;
+  if (!v.present) return LC_OK;
+  const int Lmin = std::min(p.nx, std::min(p.ny, p.nz));
+  if (!(v.a0 > 1.0) || !(2.0 * v.a0 + 4.0 <= Lmin)) { why = "colloid radius does not fit the box"; return LC_EINVAL; }
+  if (v.anchoring < LC_ANCHOR_NONE || v.anchoring > LC_ANCHOR_PLANAR) { why = "bad anchoring"; return LC_EINVAL; }
+  if (v.motion != LC_FIXED && v.motion != LC_PRESCRIBED) { why = "bad motion"; return LC_EINVAL; }
+  if (!(v.W >= 0.0)) { why = "W must be >= 0"; return LC_EINVAL; }
+  if (v.anchoring != LC_ANCHOR_NONE && !(p.K + v.W > 0.0)) { why = "K + W must be positive"; return LC_EINVAL; }
+  for (int a = 0; a < 3; a++)
+    if (!isfinite(v.pos[a]) || !isfinite(v.vel[a]) || !isfinite(v.omega[a]) || fabs(v.vel[a]) >= 1.0) {
+      why = "colloid position/velocity must be finite, |v| < 1";
+      return LC_EINVAL;
+    }
+  const int L[3] = {p.nx, p.ny, p.nz};
+  for (int a = 0; a < 3; a++) {
+    double r = fmod(v.pos[a], (double)L[a]);
+    if (r < 0) r += L[a];
+    v.pos[a] = r;
+  }
+  return LC_OK;
+}
+
 int check_flag(lc_ctx* c) {
   int flag = 0;
   HIPCHK(c, hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -719,25 +743,9 @@ int lc_set_colloid(lc_ctx* c, int box, const lc_colloid* k) {
   int rc = check_box(c, box);
   if (rc) return rc;
   if (!k) return fail(c, LC_EINVAL, "colloid is NULL");
-  const lc_params& p = c->prm[box];
-  lc_colloid v = *k;
-  if (v.present) {
-    const int Lmin = std::min(p.nx, std::min(p.ny, p.nz));
-    if (!(v.a0 > 1.0) || !(2.0 * v.a0 + 4.0 <= Lmin)) return fail(c, LC_EINVAL, "colloid radius does not fit the box");
-    if (v.anchoring < LC_ANCHOR_NONE || v.anchoring > LC_ANCHOR_PLANAR) return fail(c, LC_EINVAL, "bad anchoring");
-    if (v.motion != LC_FIXED && v.motion != LC_PRESCRIBED) return fail(c, LC_EINVAL, "bad motion");
-    if (!(v.W >= 0.0)) return fail(c, LC_EINVAL, "W must be >= 0");
-    if (v.anchoring != LC_ANCHOR_NONE && !(p.K + v.W > 0.0)) return fail(c, LC_EINVAL, "K + W must be positive");
-    for (int a = 0; a < 3; a++)
-      if (!isfinite(v.pos[a]) || !isfinite(v.vel[a]) || !isfinite(v.omega[a]) || fabs(v.vel[a]) >= 1.0)
-        return fail(c, LC_EINVAL, "colloid position/velocity must be finite, |v| < 1");
-    const int L[3] = {p.nx, p.ny, p.nz};
-    for (int a = 0; a < 3; a++) {
-      double r = fmod(v.pos[a], (double)L[a]);
-      if (r < 0) r += L[a];
-      v.pos[a] = r;
-    }
-  }
+  lc_colloid v;
+  std::string why;
+  if (check_colloid(c->prm[box], *k, v, why) != LC_OK) return fail(c, LC_EINVAL, why);
   if ((rc = pull_boxes(c)) != LC_OK) return rc;
   c->col[box] = v;
   return layout(c);
@@ -790,6 +798,132 @@ int lc_get_u(lc_ctx* c, int box, double* u3) {
   if (!u3) return fail(c, LC_EINVAL, "u is NULL");
   if ((rc = check_flag(c)) != LC_OK) return rc;
   return get(c, c->u[c->cur], box, 3, u3, false);
+}
+
+// Checkpoint layout: header, one record per box, the last-step forces,
+// the force-history rings, then f, Q and u raw in the context's precision
+// (the buffer of time n first, then the other one), native byte order.
+struct StateHeader {
+  char magic[8];
+  int version, precision, nbox, hist_cap;
+  long long nsites, nstep;
+};
+struct StateBox {
+  int nx, ny, nz, pad_;
+  long long count;     // steps recorded in this box's history ring
+  lc_colloid col;
+};
+const char kStateMagic[8] = {'L', 'C', 'S', 'T', 'A', 'T', 'E', '1'};
+const int kStateVersion = 1;
+
+size_t state_bytes(const lc_ctx* c) {
+  size_t sz[3];
+  lc_buffer_bytes(c, sz);
+  return sizeof(StateHeader) + sizeof(StateBox) * c->nbox + sizeof(double) * 12 * c->nbox +
+         sizeof(double) * 12 * (size_t)kHistCap * c->nbox + 2 * (sz[0] + sz[1] + sz[2]);
+}
+
+int lc_state_bytes(const lc_ctx* c, size_t* out) {
+  if (!c || !out) return LC_EINVAL;
+  *out = state_bytes(c);
+  return LC_OK;
+}
+
+int lc_get_state(lc_ctx* c, void* buf, size_t bytes) {
+  if (!c) return LC_EINVAL;
+  if (!buf || bytes < state_bytes(c)) return fail(c, LC_EINVAL, "state buffer is NULL or smaller than lc_state_bytes");
+  int rc = check_flag(c);
+  if (rc) return rc;
+  if ((rc = pull_boxes(c)) != LC_OK) return rc;
+  char* p = (char*)buf;
+  StateHeader h;
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, kStateMagic, 8);
+  h.version = kStateVersion;
+  h.precision = c->prec;
+  h.nbox = c->nbox;
+  h.hist_cap = kHistCap;
+  h.nsites = c->nsites;
+  h.nstep = c->nstep;
+  memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  std::vector<long long> cnt(c->nbox);
+  HIPCHK(c, hipMemcpyAsync(cnt.data(), c->dcount, sizeof(long long) * c->nbox, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int b = 0; b < c->nbox; b++) {
+    StateBox r;
+    memset(&r, 0, sizeof(r));
+    r.nx = c->prm[b].nx; r.ny = c->prm[b].ny; r.nz = c->prm[b].nz;
+    r.count = cnt[b];
+    r.col = c->col[b];
+    memcpy(p, &r, sizeof(r));
+    p += sizeof(r);
+  }
+  size_t sz[3];
+  lc_buffer_bytes(c, sz);
+  const size_t nforce = sizeof(double) * 12 * c->nbox, nhist = sizeof(double) * 12 * (size_t)kHistCap * c->nbox;
+  HIPCHK(c, hipMemcpyAsync(p, c->dforce, nforce, hipMemcpyDeviceToHost, c->stream));
+  p += nforce;
+  HIPCHK(c, hipMemcpyAsync(p, c->dhist, nhist, hipMemcpyDeviceToHost, c->stream));
+  p += nhist;
+  void* const* fld[3] = {c->f, c->Q, c->u};
+  for (int k = 0; k < 3; k++)
+    for (int j = 0; j < 2; j++) {
+      HIPCHK(c, hipMemcpyAsync(p, fld[k][c->cur ^ j], sz[k], hipMemcpyDeviceToHost, c->stream));
+      p += sz[k];
+    }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LC_OK;
+}
+
+int lc_set_state(lc_ctx* c, const void* buf, size_t bytes) {
+  if (!c) return LC_EINVAL;
+  if (!buf || bytes < sizeof(StateHeader)) return fail(c, LC_EINVAL, "state buffer is NULL or too small");
+  const char* p = (const char*)buf;
+  StateHeader h;
+  memcpy(&h, p, sizeof(h));
+  p += sizeof(h);
+  if (memcmp(h.magic, kStateMagic, 8) != 0 || h.version != kStateVersion)
+    return fail(c, LC_EINVAL, "not a state written by lc_get_state (magic or version)");
+  if (h.precision != c->prec || h.nbox != c->nbox || h.nsites != c->nsites || h.hist_cap != kHistCap)
+    return fail(c, LC_EINVAL, "state precision, box count or size does not match the context");
+  if (bytes < state_bytes(c)) return fail(c, LC_EINVAL, "state buffer is smaller than lc_state_bytes");
+  if (h.nstep < 0) return fail(c, LC_EINVAL, "negative step count in the state");
+  // validate everything before changing the context
+  std::vector<long long> cnt(c->nbox);
+  std::vector<lc_colloid> col(c->nbox);
+  for (int b = 0; b < c->nbox; b++) {
+    StateBox r;
+    memcpy(&r, p, sizeof(r));
+    p += sizeof(r);
+    if (r.nx != c->prm[b].nx || r.ny != c->prm[b].ny || r.nz != c->prm[b].nz)
+      return fail(c, LC_EINVAL, "box " + std::to_string(b) + " of the state has another shape");
+    if (r.count < 0) return fail(c, LC_EINVAL, "negative history count in the state");
+    std::string why;
+    if (check_colloid(c->prm[b], r.col, col[b], why) != LC_OK)
+      return fail(c, LC_EINVAL, "box " + std::to_string(b) + " of the state: " + why);
+    cnt[b] = r.count;
+  }
+  size_t sz[3];
+  lc_buffer_bytes(c, sz);
+  const size_t nforce = sizeof(double) * 12 * c->nbox, nhist = sizeof(double) * 12 * (size_t)kHistCap * c->nbox;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dcount, cnt.data(), sizeof(long long) * c->nbox, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dforce, p, nforce, hipMemcpyHostToDevice, c->stream));
+  p += nforce;
+  HIPCHK(c, hipMemcpyAsync(c->dhist, p, nhist, hipMemcpyHostToDevice, c->stream));
+  p += nhist;
+  void* const* fld[3] = {c->f, c->Q, c->u};
+  for (int k = 0; k < 3; k++)
+    for (int j = 0; j < 2; j++) {
+      HIPCHK(c, hipMemcpyAsync(fld[k][c->cur ^ j], p, sz[k], hipMemcpyHostToDevice, c->stream));
+      p += sz[k];
+    }
+  HIPCHK(c, hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->col = col;
+  c->nstep = (long)h.nstep;
+  return layout(c);
 }
 
 int lc_step(lc_ctx* c, int nsteps) {

@@ -1,5 +1,6 @@
 // nn_runtime.hip -- host runtime of the warm-start network (include/lc_nn.h).
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <string>
@@ -284,6 +285,62 @@ int lc_nn_get_layer(lc_nn* n, int l, float* W, float* b) {
   NNCHK(n, hipMemcpyAsync(W, n->W[l], (size_t)COUT[l] * CIN[l] * 27 * 4, hipMemcpyDeviceToHost, n->stream));
   NNCHK(n, hipMemcpyAsync(b, n->b[l], COUT[l] * 4, hipMemcpyDeviceToHost, n->stream));
   NNCHK(n, hipStreamSynchronize(n->stream));
+  return LC_OK;
+}
+
+// Weight file: magic, version, layer count, then per layer its shape
+// (C_out, C_in, taps) and the FP32 W and b, native byte order.
+const char kWeightMagic[8] = {'L', 'C', 'N', 'N', 'W', 'T', 'S', '1'};
+
+int lc_nn_save(lc_nn* n, const char* path) {
+  if (!n) return LC_EINVAL;
+  if (!path) return nfail(n, LC_EINVAL, "path is NULL");
+  std::vector<std::vector<float>> W(NL), b(NL);
+  for (int l = 0; l < NL; l++) {
+    W[l].resize((size_t)COUT[l] * CIN[l] * 27);
+    b[l].resize(COUT[l]);
+    int rc = lc_nn_get_layer(n, l, W[l].data(), b[l].data());
+    if (rc) return rc;
+  }
+  FILE* fp = fopen(path, "wb");
+  if (!fp) return nfail(n, LC_EINVAL, std::string("cannot open ") + path + " for writing");
+  const int head[2] = {1, NL};
+  bool ok = fwrite(kWeightMagic, 1, 8, fp) == 8 && fwrite(head, sizeof(int), 2, fp) == 2;
+  for (int l = 0; l < NL && ok; l++) {
+    const int shape[4] = {COUT[l], CIN[l], 27, 0};
+    ok = fwrite(shape, sizeof(int), 4, fp) == 4 && fwrite(W[l].data(), 4, W[l].size(), fp) == W[l].size() &&
+         fwrite(b[l].data(), 4, b[l].size(), fp) == b[l].size();
+  }
+  ok = (fclose(fp) == 0) && ok;
+  if (!ok) return nfail(n, LC_EINVAL, std::string("writing ") + path + " failed");
+  return LC_OK;
+}
+
+int lc_nn_load(lc_nn* n, const char* path) {
+  if (!n) return LC_EINVAL;
+  if (!path) return nfail(n, LC_EINVAL, "path is NULL");
+  FILE* fp = fopen(path, "rb");
+  if (!fp) return nfail(n, LC_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  int head[2];
+  std::vector<std::vector<float>> W(NL), b(NL);
+  bool ok = fread(magic, 1, 8, fp) == 8 && memcmp(magic, kWeightMagic, 8) == 0 &&
+            fread(head, sizeof(int), 2, fp) == 2 && head[0] == 1 && head[1] == NL;
+  for (int l = 0; l < NL && ok; l++) {
+    int shape[4];
+    ok = fread(shape, sizeof(int), 4, fp) == 4 && shape[0] == COUT[l] && shape[1] == CIN[l] && shape[2] == 27;
+    if (!ok) break;
+    W[l].resize((size_t)COUT[l] * CIN[l] * 27);
+    b[l].resize(COUT[l]);
+    ok = fread(W[l].data(), 4, W[l].size(), fp) == W[l].size() && fread(b[l].data(), 4, b[l].size(), fp) == b[l].size();
+  }
+  ok = ok && fgetc(fp) == EOF;
+  fclose(fp);
+  if (!ok) return nfail(n, LC_EINVAL, std::string(path) + " is not a weight file of this network");
+  for (int l = 0; l < NL; l++) {
+    int rc = lc_nn_set_layer(n, l, W[l].data(), b[l].data());
+    if (rc) return rc;
+  }
   return LC_OK;
 }
 

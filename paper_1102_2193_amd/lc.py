@@ -24,7 +24,8 @@ STATUS = {0: "LC_OK", 1: "LC_EINVAL", 2: "LC_ENOMEM", 3: "LC_EDEVICE", 4: "LC_EN
 EXPORTS = [
     "lc_create", "lc_create_batch", "lc_destroy", "lc_last_error", "lc_buffer_bytes", "lc_bind_buffers",
     "lc_set_colloid", "lc_get_colloid", "lc_set_Q", "lc_set_f", "lc_set_u", "lc_get_Q", "lc_get_f",
-    "lc_get_u", "lc_step", "lc_sync", "lc_get_nstep", "lc_get_force", "lc_get_force_history",
+    "lc_get_u", "lc_state_bytes", "lc_get_state", "lc_set_state", "lc_step", "lc_sync", "lc_get_nstep",
+    "lc_get_force", "lc_get_force_history",
     "lc_history_capacity", "lc_get_diag", "lc_defects", "lc_num_tiles", "lc_tile_shape", "lc_set_tile",
     "lc_get_tile", "lc_use_graph", "lc_launch_info", "lc_time_kernel",
 ]
@@ -81,6 +82,9 @@ def load():
     L.lc_get_colloid.argtypes = [vp, ip, ctypes.POINTER(Colloid)]
     for n in ("lc_set_Q", "lc_set_f", "lc_set_u", "lc_get_Q", "lc_get_f", "lc_get_u", "lc_get_force"):
         getattr(L, n).argtypes = [vp, ip, dp]
+    L.lc_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.lc_get_state.argtypes = [vp, vp, ctypes.c_size_t]
+    L.lc_set_state.argtypes = [vp, vp, ctypes.c_size_t]
     L.lc_step.argtypes = [vp, ip]
     L.lc_sync.argtypes = [vp]
     L.lc_get_nstep.argtypes = [vp]
@@ -219,6 +223,25 @@ class Context:
 
     def get_u(self, box=0):
         return self._get("lc_get_u", box, 3)
+
+    # ---- checkpoint ------------------------------------------------------
+    def get_state(self):
+        """The whole evolving state as a uint8 array (lc_get_state)."""
+        n = ctypes.c_size_t()
+        self._chk(self._L.lc_state_bytes(self._h, ctypes.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._chk(self._L.lc_get_state(self._h, ctypes.c_void_p(buf.ctypes.data), buf.nbytes))
+        return buf
+
+    def set_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._chk(self._L.lc_set_state(self._h, ctypes.c_void_p(buf.ctypes.data), buf.nbytes))
+
+    def save(self, path):
+        self.get_state().tofile(path)
+
+    def load(self, path):
+        self.set_state(np.fromfile(path, dtype=np.uint8))
 
     # ---- stepping --------------------------------------------------------
     def step(self, n=1):

@@ -4,12 +4,14 @@ Argument marshalling only; the network runs in the library's HIP kernels
 (BF16 matrix-core convolutions).  Raises if the library or the GPU is absent.
 """
 import ctypes
+import os
 
 import numpy as np
 
 from . import lc
 
 EXPORTS = ["lc_nn_create", "lc_nn_destroy", "lc_nn_last_error", "lc_nn_set_layer", "lc_nn_get_layer",
+           "lc_nn_save", "lc_nn_load",
            "lc_nn_features", "lc_nn_predict", "lc_nn_warm_start", "lc_nn_train_step", "lc_nn_layer_forward",
            "lc_nn_layer_backward", "lc_nn_time"]
 CIN = (12, 32, 32, 32)
@@ -48,6 +50,8 @@ def _lib():
         L.lc_nn_last_error.restype = ctypes.c_char_p
         L.lc_nn_set_layer.argtypes = [vp, ctypes.c_int, fp, fp]
         L.lc_nn_get_layer.argtypes = [vp, ctypes.c_int, fp, fp]
+        L.lc_nn_save.argtypes = [vp, ctypes.c_char_p]
+        L.lc_nn_load.argtypes = [vp, ctypes.c_char_p]
         L.lc_nn_features.argtypes = [vp, cp, fp]
         L.lc_nn_predict.argtypes = [vp, cp, dp]
         L.lc_nn_warm_start.argtypes = [vp, cp, vp, ctypes.c_int]
@@ -113,6 +117,12 @@ class Net:
         b = np.zeros(COUT[l], np.float32)
         self._chk(self._L.lc_nn_get_layer(self._h, l, _f(W), _f(b)))
         return W, b
+
+    def save(self, path):
+        self._chk(self._L.lc_nn_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        self._chk(self._L.lc_nn_load(self._h, os.fsencode(path)))
 
     def features(self, case):
         out = np.zeros((12,) + self.shape, np.float32)

@@ -57,7 +57,7 @@ BAND = 1e-4
 EVERY = 100
 TRAIN_SEED0 = 5000
 HELD_SEED0 = 9000
-WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_net.npz")
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_net.lcnn")
 
 
 def log(*a):
@@ -173,17 +173,12 @@ def q_error(Q, Qstar, fluid):
 
 
 def save_weights(net, path):
-    arrs = {}
-    for l in range(4):
-        W, b = net.get_layer(l)
-        arrs["W%d" % l], arrs["b%d" % l] = W, b
-    np.savez(path, **arrs)
+    """Weights in the library's file format (lc_nn_save)."""
+    net.save(path)
 
 
 def load_weights(net, path):
-    with np.load(path) as z:
-        for l in range(4):
-            net.set_layer(l, z["W%d" % l], z["b%d" % l])
+    net.load(path)
 
 
 def relaxed_states(cases, L, cap, batch, hydro, tile, label):
@@ -321,7 +316,7 @@ def main(argv=None):
         info["history"] = train(net, data, L, args.epochs, args.lr0, args.lr1, args.seed0,
                                 [d for d in held if d["conv"] is not None])
         info["train_seconds"] = time.time() - t0
-        save_weights(net, os.path.join(args.out, "weights.npz"))
+        save_weights(net, os.path.join(args.out, "weights.lcnn"))
         info["nn_time_ms"] = net.time(nn_case(data[0], L), data[0]["Q"], fluid_mask(data[0], L), n=20)
         info["cases"] = [{k: d[k] for k in ("seed", "a", "pitch", "anchoring", "conv")} for d in data]
         log("trained in %.0f s; %s" % (info["train_seconds"], info["nn_time_ms"]))

@@ -1,0 +1,175 @@
+"""Checkpoint and restart through the C ABI (lc_get_state / lc_set_state,
+lc_nn_save / lc_nn_load).
+
+A context given a saved state continues exactly as the saved context would
+have: every getter returns the same bits afterwards.  States that do not fit
+a context are rejected and leave it unchanged.  Every case prints its name
+before touching the GPU.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1102_2193_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+NEM = inputs.NEMATIC
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def snapshot(ctx, nbox, nhist):
+    out = []
+    for b in range(nbox):
+        out.append(dict(Q=ctx.get_Q(b), f=ctx.get_f(b), u=ctx.get_u(b), F=ctx.force(b),
+                        H=ctx.force_history(b, nhist), pos=np.array(list(ctx.get_colloid(b).pos)),
+                        diag=ctx.diag(b)))
+    return out
+
+
+def assert_same(a, b):
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        for k in ("Q", "f", "u", "F", "H", "pos"):
+            np.testing.assert_array_equal(x[k], y[k], err_msg=k)
+        for k in ("free_energy", "mass", "umax"):
+            assert x["diag"][k] == y["diag"][k], k
+        np.testing.assert_array_equal(x["diag"]["momentum"], y["diag"]["momentum"])
+
+
+def test_fp32_moving_colloid_continues_bit_for_bit():
+    from paper_1102_2193_amd import lc
+    say("case: checkpoint 32^3 fp32 cholesteric, moving colloid, save at step 23, continue 41")
+    L = 32
+    prm = dict(NEM, q0=2 * math.pi / 16)
+    box = [dict(nx=L, precision="fp32", **prm)]
+    a = lc.Context(box)
+    a.set_colloid(0, (9.3, 16.2, 15.7), 4.0, anchoring="normal", W=0.02, vel=(0.05, 0.01, -0.02),
+                  motion=lc.PRESCRIBED)
+    a.set_Q(0, inputs.helix_q(L, L, L, 2 * math.pi / 16, inputs.Q_INIT))
+    a.step(23)              # a graph of 16 steps and 7 eager ones: the time-n buffer is the second
+    state = a.get_state()
+    assert a.nstep == 23
+    a.step(41)
+    ref = snapshot(a, 1, 64)
+    # a fresh context with the same parameters and no set-up of its own
+    b = lc.Context(box)
+    b.set_state(state)
+    assert b.nstep == 23
+    b.step(41)
+    assert b.nstep == 64
+    assert_same(snapshot(b, 1, 64), ref)
+    # rewinding the original context gives the same run again
+    a.set_state(state)
+    a.step(41)
+    assert_same(snapshot(a, 1, 64), ref)
+    a.close()
+    b.close()
+
+
+def test_fp64_batch_continues_bit_for_bit(tmp_path):
+    from paper_1102_2193_amd import lc
+    say("case: checkpoint fp64 batch (16^3 with a fixed colloid, 20x16x24 without), file round trip")
+    boxes = [dict(nx=16, precision="fp64", **NEM), dict(nx=20, ny=16, nz=24, precision="fp64", **NEM)]
+    a = lc.Context(boxes)
+    a.set_colloid(0, (8.2, 7.9, 8.4), 3.5, anchoring="planar", W=0.01)
+    a.set_Q(0, inputs.noisy_nematic_q(16, 16, 16, inputs.Q_INIT, seed=4))
+    a.set_Q(1, inputs.noisy_nematic_q(20, 16, 24, inputs.Q_INIT, seed=5))
+    a.step(5)
+    path = str(tmp_path / "ctx.state")
+    a.save(path)
+    a.step(20)
+    ref = snapshot(a, 2, 25)
+    b = lc.Context(boxes)
+    b.load(path)
+    b.step(20)
+    assert_same(snapshot(b, 2, 25), ref)
+    a.close()
+    b.close()
+
+
+def test_states_that_do_not_fit_are_rejected():
+    from paper_1102_2193_amd import lc
+    say("case: checkpoint mismatches (precision, shape, box count, truncation, magic)")
+    L = 16
+    a = lc.Context([dict(nx=L, precision="fp32", **NEM)])
+    a.set_Q(0, inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=2))
+    a.step(3)
+    state = a.get_state()
+    targets = {
+        "precision": lc.Context([dict(nx=L, precision="fp64", **NEM)]),
+        "shape": lc.Context([dict(nx=L, ny=L, nz=L + 8, precision="fp32", **NEM)]),
+        "box count": lc.Context([dict(nx=L, precision="fp32", **NEM)] * 2),
+    }
+    # same number of sites, other shape
+    s2 = lc.Context([dict(nx=L, ny=L, nz=L + 8, precision="fp32", **NEM)])
+    s2.step(1)
+    state2 = s2.get_state()
+    s2.close()
+    t = lc.Context([dict(nx=L + 8, ny=L, nz=L, precision="fp32", **NEM)])
+    with pytest.raises(lc.LCError) as e:
+        t.set_state(state2)
+    assert e.value.code == 1 and t.nstep == 0
+    t.close()
+    for name, ctx in targets.items():
+        before = ctx.get_Q(0)
+        with pytest.raises(lc.LCError) as e:
+            ctx.set_state(state)
+        assert e.value.code == 1, name
+        np.testing.assert_array_equal(ctx.get_Q(0), before)
+        assert ctx.nstep == 0
+        ctx.close()
+    c = lc.Context([dict(nx=L, precision="fp32", **NEM)])
+    before = c.get_Q(0)
+    bad = state.copy()
+    bad[0] ^= 0xFF
+    for buf in (state[:-1], bad, state[:16]):
+        with pytest.raises(lc.LCError) as e:
+            c.set_state(buf)
+        assert e.value.code == 1
+    np.testing.assert_array_equal(c.get_Q(0), before)
+    assert c.nstep == 0
+    c.set_state(state)
+    np.testing.assert_array_equal(c.get_Q(0), a.get_Q(0))
+    assert c.nstep == 3
+    a.close()
+    c.close()
+
+
+def test_network_weight_file_round_trip(tmp_path):
+    from paper_1102_2193_amd import lc, nn
+    say("case: network weights saved and loaded (16^3 grid)")
+    L = 16
+    rng = np.random.default_rng(8)
+    a = nn.Net(L, seed=3)
+    for l in range(4):
+        a.set_layer(l, rng.normal(size=(nn.COUT[l], nn.CIN[l], 27)).astype(np.float32) * 0.05,
+                    rng.normal(size=nn.COUT[l]).astype(np.float32) * 0.05)
+    path = str(tmp_path / "w.lcnn")
+    a.save(path)
+    b = nn.Net(L, seed=11)
+    b.load(path)
+    for l in range(4):
+        for x, y in zip(a.get_layer(l), b.get_layer(l)):
+            np.testing.assert_array_equal(x, y)
+    c = nn.make_case((8.0, 8.0, 8.0), 3.5, 16.0, "normal", 0.495, 0.5)
+    np.testing.assert_array_equal(a.predict(c), b.predict(c))
+    # a truncated file and a file of something else are refused; b keeps its weights
+    raw = open(path, "rb").read()
+    bad = tmp_path / "bad.lcnn"
+    for content in (raw[:-4], b"not a weight file", raw + b"\0"):
+        bad.write_bytes(content)
+        with pytest.raises(lc.LCError) as e:
+            b.load(str(bad))
+        assert e.value.code == 1
+    np.testing.assert_array_equal(a.predict(c), b.predict(c))
+    with pytest.raises(lc.LCError):
+        b.load(str(tmp_path / "missing.lcnn"))
+    a.close()
+    b.close()

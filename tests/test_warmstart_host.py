@@ -90,10 +90,28 @@ def test_summary_charges_fallbacks():
     assert s["warm_faster"] == 1 and s["warm_slower"] == 1
 
 
+def read_weight_file(path):
+    """Parse the weight file format documented for lc_nn_save."""
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"LCNNWTS1"
+    version, nl = np.frombuffer(raw, np.int32, 2, 8)
+    assert version == 1 and nl == 4
+    off, layers = 16, []
+    for _ in range(nl):
+        cout, cin, taps, pad = np.frombuffer(raw, np.int32, 4, off)
+        off += 16
+        W = np.frombuffer(raw, np.float32, cout * cin * taps, off).reshape(cout, cin, taps)
+        off += W.nbytes
+        b = np.frombuffer(raw, np.float32, cout, off)
+        off += b.nbytes
+        layers.append((W, b))
+    assert off == len(raw)
+    return layers
+
+
 def test_committed_weights_have_the_network_shapes():
     from paper_1102_2193_amd import nn
-    with np.load(ws.WEIGHTS) as z:
-        for l in range(4):
-            assert z["W%d" % l].shape == (nn.COUT[l], nn.CIN[l], 27)
-            assert z["b%d" % l].shape == (nn.COUT[l],)
-            assert np.all(np.isfinite(z["W%d" % l]))
+    for l, (W, b) in enumerate(read_weight_file(ws.WEIGHTS)):
+        assert W.shape == (nn.COUT[l], nn.CIN[l], 27)
+        assert b.shape == (nn.COUT[l],)
+        assert np.all(np.isfinite(W)) and np.all(np.isfinite(b))
