@@ -12,14 +12,14 @@
 namespace lc {
 
 // One box of the batch.  Host and device share this layout; the colloid
-// position is advanced on the device by the finalize kernel.
+// position is advanced on the device by the post-step kernel.
 struct BoxDev {
   int nx, ny, nz, hydro;
   long long off;            // first site of the box in the concatenated arrays
   int tile_base, ntx, nty, ntz;          // fused-kernel tiles of this box
   int ghost_base, ghost_ext;             // ghost launch: thread range, bbox edge
-  int event_base, event_ext;             // event launch: thread range, bbox edge
-  int event_blk0, event_nblk;            // event partial-sum blocks of this box
+  int event_ext, pad1_;                  // bbox edge of the moving-boundary events
+  int post_blk0, post_nblk;              // blocks of the post-step kernel for this box
   double tau, rho0, A0, gamma, K, q0, xi, Gamma;
   double itau, fsrc;                     // 1/tau and 1 - 1/(2 tau)
   double body[3];

@@ -6,8 +6,10 @@
 //               Beris-Edwards update of Q, BGK collision with Guo forcing,
 //               push streaming with bounce-back on links, colloid force and
 //               torque partial sums (Sec. 2.1-2.2)
-//   k_events    moving-boundary events of a colloid with prescribed motion
-//   k_finalize  fixed-order sum of the partials, force history, R += v
+//   k_post      after each step: moving-boundary events of a colloid with
+//               prescribed motion, the next step's ghost Q, block sums of
+//               the colloid force and torque
+//   k_finish    fixed-order sum of the block sums, force history, R += v
 //   k_diag      free energy, mass, momentum, max|u| partials
 //   k_defects   (3/2) lambda_max(Q) below a threshold
 //
@@ -103,6 +105,34 @@ template <typename T>
 __device__ inline T* at32(T* base, unsigned idx) {
   return (T*)((char*)base + idx * (unsigned)sizeof(T));
 }
+
+// FP32 field array [component][site] addressed through one buffer resource:
+// component c of site s is at byte s*4 (per lane) + c*stride (scalar
+// offset).  One 128-bit resource per array replaces a 64-bit base address
+// per component, which the marching kernel cannot keep in scalar registers.
+// The range is the whole array (ncomp x ns floats), so no access is
+// clamped.
+struct FieldBuf {
+  __amdgpu_buffer_rsrc_t r;
+  unsigned cs;   // bytes between components
+  __device__ FieldBuf(const float* p, long long ns, int ncomp)
+      : r(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)((unsigned)ncomp * (unsigned)ns * 4u),
+                                            0x00020000)),
+        cs((unsigned)ns * 4u) {}
+  // aux 2 = non-temporal (streamed once)
+  __device__ float ld(int c, unsigned s) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, s * 4u, (unsigned)c * cs, 0));
+  }
+  __device__ float ld_nt(int c, unsigned s) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, s * 4u, (unsigned)c * cs, 2));
+  }
+  __device__ void st(int c, unsigned s, float v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, s * 4u, (unsigned)c * cs, 0);
+  }
+  __device__ void st_nt(int c, unsigned s, float v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, s * 4u, (unsigned)c * cs, 2);
+  }
+};
 
 
 // Block = one TX x TY x TZ tile, one thread per node.  LDS holds Q with a
@@ -573,8 +603,11 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   const int zend = z0 + ng * kGroup < nz ? z0 + ng * kGroup : nz;
   const unsigned off = (unsigned)B.off;
   const long long NS = a.nsites;
+  static_assert(std::is_same<R, float>::value, "the marching kernel is FP32 only");
+  const FieldBuf bfin(a.fin, NS, 19), bfout(a.fout, NS, 19), bqin(a.Qin, NS, 5), bqout(a.Qout, NS, 5),
+      buin(a.uin, NS, 3), buout(a.uout, NS, 3);
   const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
-  // nominal extent (whole groups): every group's own test (in k_finalize)
+  // nominal extent (whole groups): every group's own test (in k_post)
   // covers a subset of this range, so a group counted there was written here
   const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, ng * kGroup + 4);
   const Mat<R> mp(B);
@@ -604,23 +637,23 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     uo[m] = wrapn(x0 - 1 + ex, nx) + nx * wrapn(y0 - 1 + ey, ny);
   }
   R rq[MQ][5], ru[MU][3];
-  auto fetch_q = [&](int z) {
+  auto fetch_q = [&](R (&dst)[MQ][5], int z) {
     const unsigned zo = off + (unsigned)(nxy * wrapn(z, nz));
 #pragma unroll
     for (int m = 0; m < MQ; m++)
       if (m < MQ - 1 || tid + m * NT < QP)
 #pragma unroll
-        for (int c = 0; c < 5; c++) rq[m][c] = *at32(a.Qin + c * NS, zo + (unsigned)qo[m]);
+        for (int c = 0; c < 5; c++) dst[m][c] = bqin.ld(c, zo + (unsigned)qo[m]);
   };
-  auto fetch_u = [&](int z) {
+  auto fetch_u = [&](R (&dst)[MU][3], int z) {
     const unsigned zo = off + (unsigned)(nxy * wrapn(z, nz));
 #pragma unroll
     for (int m = 0; m < MU; m++)
       if (m < MU - 1 || tid + m * NT < UP)
 #pragma unroll
-        for (int c = 0; c < 3; c++) ru[m][c] = *at32(a.uin + c * NS, zo + (unsigned)uo[m]);
+        for (int c = 0; c < 3; c++) dst[m][c] = buin.ld(c, zo + (unsigned)uo[m]);
   };
-  auto store_q = [&](int slot, int z) {
+  auto store_q = [&](const R (&rq)[MQ][5], int slot, int z) {
     const int wz = wrapn(z, nz);
 #pragma unroll
     for (int m = 0; m < MQ; m++) {
@@ -632,7 +665,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
       }
     }
   };
-  auto store_u = [&](int slot) {
+  auto store_u = [&](const R (&ru)[MU][3], int slot) {
 #pragma unroll
     for (int m = 0; m < MU; m++) {
       const int e = tid + m * NT;
@@ -738,17 +771,32 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     }
   };
 
-  // prologue: Q planes z0-2 .. z0+2 in slots 0..4, u planes z0-1 .. z0+1
-  // in slots 0..2
-  for (int k = 0; k < 5; k++) {
-    fetch_q(z0 - 2 + k);
-    store_q(k, z0 - 2 + k);
-  }
-  if (hydro) {
-    for (int k = 0; k < 3; k++) {
-      fetch_u(z0 - 1 + k);
-      store_u(k);
+  // populations of the own column, one plane ahead of their use
+  R f[19];
+  const unsigned gcol = off + (unsigned)(gx + nx * gy);
+  auto fetch_f = [&](int z) {
+    if (hydro && incol) {
+      const unsigned gf = gcol + (unsigned)(nxy * z);
+#pragma unroll
+      for (int i = 0; i < 19; i++) f[i] = bfin.ld_nt(i, gf);
     }
+  };
+  fetch_f(z0);
+
+  // prologue: Q planes z0-2 .. z0+2 in slots 0..4, u planes z0-1 .. z0+1
+  // in slots 0..2, all requested before the first is stored
+  {
+    R pq[5][MQ][5], pu[3][MU][3];
+#pragma unroll
+    for (int k = 0; k < 5; k++) fetch_q(pq[k], z0 - 2 + k);
+    if (hydro)
+#pragma unroll
+      for (int k = 0; k < 3; k++) fetch_u(pu[k], z0 - 1 + k);
+#pragma unroll
+    for (int k = 0; k < 5; k++) store_q(pq[k], k, z0 - 2 + k);
+    if (hydro)
+#pragma unroll
+      for (int k = 0; k < 3; k++) store_u(pu[k], k);
   }
   lds_sync();
   if (hydro)
@@ -767,18 +815,6 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   int ps_0 = 0;
   const int lane = tid & 63, wv = tid >> 6;
 
-  // populations of the own column, one plane ahead of their use
-  R f[19];
-  const unsigned gcol = off + (unsigned)(gx + nx * gy);
-  auto fetch_f = [&](int z) {
-    if (hydro && incol) {
-      const unsigned gf = gcol + (unsigned)(nxy * z);
-#pragma unroll
-      for (int i = 0; i < 19; i++) f[i] = __builtin_nontemporal_load(at32(a.fin + i * NS, gf));
-    }
-  };
-  fetch_f(z0);
-
   for (int k = z0; k < zend; k++) {
     const int gi = (k - z0) / kGroup;
     if (k > z0 && k - z0 == gi * kGroup) flush(gi - 1);
@@ -789,8 +825,8 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     const unsigned g = gcol + (unsigned)(nxy * gz);
     const bool more = k + 1 < zend;
     if (more) {
-      fetch_q(k + 3);
-      if (hydro) fetch_u(k + 2);
+      fetch_q(rq, k + 3);
+      if (hydro) fetch_u(ru, k + 2);
     }
     // stress of plane k+1
     plane_stress(qs_0, qs_p1, qs_p2, ps_0 ^ 1, true, h_nxt, pz_n);
@@ -907,7 +943,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
 #pragma unroll
       for (int c = 0; c < 5; c++) {
         const R v = q5[c] + dQ[c];
-        __builtin_nontemporal_store(v, at32(a.Qout + c * NS, g));
+        bqout.st_nt(c, g, v);
         qn2 += v * v;
       }
       bool bad = !(qn2 < (R)100);
@@ -964,14 +1000,14 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
         for (int i = 0; i < 19; i++) {
           if (!NEAR || !sn[i]) {
             const unsigned gn = g + (unsigned)(dxs[cx(i) + 1] + dys[cy(i) + 1] + dzs[cz(i) + 1]);
-            *at32(a.fout + i * NS, gn) = fs[i];
+            bfout.st(i, gn, fs[i]);
           } else {
             // link bounce-back with the moving-wall term; the link passes
             // (2 f_i - corr) c_i to the colloid at r_site + c_i/2, whose
             // torque about the centre is r_site x dp (c_i x c_i = 0)
             const R cub = (R)cx(i) * ubs[0] + (R)cy(i) * ubs[1] + (R)cz(i) * ubs[2];
             const R corr = (R)(6.0 * wgt(i)) * (R)B.rho0 * cub;
-            __builtin_nontemporal_store(fs[i] - corr, at32(a.fout + opp(i) * NS, g));
+            bfout.st_nt(opp(i), g, fs[i] - corr);
             const double m = 2.0 * ((double)fs[i] + wgt(i)) - (double)corr;
             if (cx(i)) bbp[0] += cx(i) > 0 ? m : -m;
             if (cy(i)) bbp[1] += cy(i) > 0 ? m : -m;
@@ -979,7 +1015,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
           }
         }
 #pragma unroll
-        for (int c = 0; c < 3; c++) __builtin_nontemporal_store(u[c], at32(a.uout + c * NS, g));
+        for (int c = 0; c < 3; c++) buout.st_nt(c, g, u[c]);
       }
       if (NEAR && anys) {
         double r[3];
@@ -1014,8 +1050,8 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
 
     // rotate: planes k+3 (Q) and k+2 (u) enter the free slots
     if (more) {
-      store_q(qs_free, k + 3);
-      if (hydro) store_u(us_free);
+      store_q(rq, qs_free, k + 3);
+      if (hydro) store_u(ru, us_free);
     }
     lds_sync();
     if (more && hydro) {
@@ -1036,7 +1072,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   // the last plane's barrier has ordered every wave's sums of the last group
   flush((zend - 1 - z0) / kGroup);
   // far from the colloid every group's sums are zero: write them, so that
-  // k_finalize can add all slots without repeating the geometry test
+  // k_post can add all slots without repeating the geometry test
   if (!near && tid < 12)
     for (int g = 0; g < (zend - z0 + kGroup - 1) / kGroup; g++)
       a.part[tid * a.nslot + B.tile_base + cb + (long long)ncb * (g0 + g)] = 0.0;
@@ -1045,15 +1081,6 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
 // ---------------------------------------------------------------------
 // ghost Q at boundary solid nodes
 // ---------------------------------------------------------------------
-__device__ inline int find_box(const BoxDev* boxes, int nbox, long long t, int which) {
-  int b = 0;
-  for (int k = 1; k < nbox; k++) {
-    const int base = which == 0 ? boxes[k].ghost_base : boxes[k].event_base;
-    if (t >= base) b = k;
-  }
-  return b;
-}
-
 template <typename R>
 __device__ inline void load_full(const R* Q, long long NS, long long g, double q[3][3]) {
   const double xx = Q[g], xy = Q[NS + g], xz = Q[2 * NS + g], yy = Q[3 * NS + g], yz = Q[4 * NS + g];
@@ -1062,22 +1089,37 @@ __device__ inline void load_full(const R* Q, long long NS, long long g, double q
   q[2][0] = xz; q[2][1] = yz; q[2][2] = -xx - yy;
 }
 
+__device__ inline long long site_of(const BoxDev& B, int x, int y, int z) {
+  return B.off + x + (long long)B.nx * (y + (long long)B.ny * z);
+}
+
+// Q given to a node that the move Rold -> Rnew uncovers: the mean over its
+// face neighbours that are fluid before and after the move, rounded to the
+// storage precision.
 template <typename R>
-__global__ void __launch_bounds__(256)
-    k_ghost(const BoxDev* __restrict__ boxes, int nbox, long long total, R* __restrict__ Q, long long NS) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int b = find_box(boxes, nbox, t, 0);
-  const BoxDev& B = boxes[b];
-  if (!B.present) return;
-  const int E = B.ghost_ext;
-  const long long l = t - B.ghost_base;
-  if (l >= (long long)E * E * E) return;
-  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
-  const int h = (E - 1) / 2;
-  const int x = wrapc((int)floor(Rc[0]) - h + (int)(l % E), B.nx);
-  const int y = wrapc((int)floor(Rc[1]) - h + (int)((l / E) % E), B.ny);
-  const int z = wrapc((int)floor(Rc[2]) - h + (int)(l / ((long long)E * E)), B.nz);
+__device__ inline void exposed_q(const BoxDev& B, const double Rold[3], const double Rnew[3], int x, int y, int z,
+                                 const R* Q, long long NS, double q5[5]) {
+  const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+  double qm[5] = {0, 0, 0, 0, 0};
+  int nf = 0;
+  for (int k = 0; k < 6; k++) {
+    const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
+    if (inside(B, Rold, xn, yn, zn) || inside(B, Rnew, xn, yn, zn)) continue;
+    const long long gn = site_of(B, xn, yn, zn);
+    for (int c = 0; c < 5; c++) qm[c] += (double)Q[c * NS + gn];
+    nf++;
+  }
+  for (int c = 0; c < 5; c++) q5[c] = (double)(R)(nf ? qm[c] / nf : 0.0);
+}
+
+// Anchoring at node (x, y, z) for the colloid at Rc: if the node is solid
+// with at least one fluid face neighbour, Q there becomes Q^0 (or its blend
+// with the neighbours' mean for finite W).  When the colloid has just moved
+// from Rold, neighbours it uncovered get their Q in this same pass, so their
+// value is formed here by the same rule instead of being read.
+template <typename R>
+__device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const double Rc[3], bool moved, int x,
+                                  int y, int z, R* __restrict__ Q, long long NS) {
   if (!inside(B, Rc, x, y, z)) return;
   const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
   // all six neighbours are read at once (the loads overlap), then the fluid
@@ -1087,8 +1129,20 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int k = 0; k < 6; k++) {
     const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
-    load_full(Q, NS, B.off + xn + (long long)B.nx * (yn + (long long)B.ny * zn), qn[k]);
+    load_full(Q, NS, site_of(B, xn, yn, zn), qn[k]);
     fl[k] = !inside(B, Rc, xn, yn, zn);
+  }
+  if (moved) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
+      if (!fl[k] || !inside(B, Rold, xn, yn, zn)) continue;
+      double q5[5];
+      exposed_q<R>(B, Rold, Rc, xn, yn, zn, Q, NS, q5);
+      qn[k][0][0] = q5[0]; qn[k][0][1] = q5[1]; qn[k][0][2] = q5[2];
+      qn[k][1][0] = q5[1]; qn[k][1][1] = q5[3]; qn[k][1][2] = q5[4];
+      qn[k][2][0] = q5[2]; qn[k][2][1] = q5[4]; qn[k][2][2] = -q5[0] - q5[3];
+    }
   }
   double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   int nf = 0;
@@ -1114,9 +1168,38 @@ __global__ void __launch_bounds__(256)
       for (int j = 0; j < 3; j++)
         qs[i][j] = fixed ? q0[i][j] : (B.K * qbar[i][j] + B.W * q0[i][j]) / (B.K + B.W);
   }
-  const long long g = B.off + x + (long long)B.nx * (y + (long long)B.ny * z);
+  const long long g = site_of(B, x, y, z);
   Q[g] = (R)qs[0][0]; Q[NS + g] = (R)qs[0][1]; Q[2 * NS + g] = (R)qs[0][2];
   Q[3 * NS + g] = (R)qs[1][1]; Q[4 * NS + g] = (R)qs[1][2];
+}
+
+// Node l of the cube of edge E centred on floor(R), wrapped into the box.
+__device__ inline void cube_site(const BoxDev& B, const double R[3], int E, long long l, int& x, int& y, int& z) {
+  const int h = (E - 1) / 2;
+  x = wrapc((int)floor(R[0]) - h + (int)(l % E), B.nx);
+  y = wrapc((int)floor(R[1]) - h + (int)((l / E) % E), B.ny);
+  z = wrapc((int)floor(R[2]) - h + (int)(l / ((long long)E * E)), B.nz);
+}
+
+// Stand-alone anchoring pass over one Q buffer (colloids at their current
+// positions).
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_ghost(const BoxDev* __restrict__ boxes, int nbox, long long total, R* __restrict__ Q, long long NS) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  int b = 0;
+  for (int k = 1; k < nbox; k++)
+    if (t >= boxes[k].ghost_base) b = k;
+  const BoxDev& B = boxes[b];
+  if (!B.present) return;
+  const int E = B.ghost_ext;
+  const long long l = t - B.ghost_base;
+  if (l >= (long long)E * E * E) return;
+  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  int x, y, z;
+  cube_site(B, Rc, E, l, x, y, z);
+  ghost_site<R>(B, Rc, Rc, false, x, y, z, Q, NS);
 }
 
 // ---------------------------------------------------------------------
@@ -1132,110 +1215,122 @@ __device__ inline void advanced_pos(const BoxDev& B, double Rn[3]) {
   }
 }
 
+// Node (x, y, z) when the colloid moves Rc -> Rn: a node it uncovers gets
+// fluid at rest in the wall frame and Q from its face neighbours; a node it
+// covers gives its fluid momentum to the colloid.  p and the torque about
+// Rn go to v[0..2] and v[6..8].
 template <typename R>
-__global__ void __launch_bounds__(kEventBlock)
-    k_events(const BoxDev* __restrict__ boxes, int nbox, long long total, StepPtrs<R> a, double* epart) {
-  __shared__ double sred[(kEventBlock / 64) * 6];
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  // every box's range is padded to whole blocks, so a block has one box
-  const int b = find_box(boxes, nbox, (long long)blockIdx.x * blockDim.x, 1);
-  const BoxDev& B = boxes[b];
+__device__ inline void event_site(const BoxDev& B, const double Rc[3], const double Rn[3], int x, int y, int z,
+                                  const StepPtrs<R>& a, double v[12]) {
+  const bool was = inside(B, Rc, x, y, z), now = inside(B, Rn, x, y, z);
+  if (was == now) return;
   const long long NS = a.nsites;
-  const long long l = t - B.event_base;
-  const int E = B.event_ext;
-  if (B.present && B.motion == 1 && t < total && l < (long long)E * E * E) {
-    const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
-    double Rn[3];
-    advanced_pos(B, Rn);
-    const int h = (E - 1) / 2;
-    const int x = wrapc((int)floor(Rc[0]) - h + (int)(l % E), B.nx);
-    const int y = wrapc((int)floor(Rc[1]) - h + (int)((l / E) % E), B.ny);
-    const int z = wrapc((int)floor(Rc[2]) - h + (int)(l / ((long long)E * E)), B.nz);
-    const bool was = inside(B, Rc, x, y, z), now = inside(B, Rn, x, y, z);
-    if (was != now) {
-      const long long g = B.off + x + (long long)B.nx * (y + (long long)B.ny * z);
-      double r[3], p[3] = {0, 0, 0};
-      rel_pos(B, Rn, (double)x, (double)y, (double)z, r);
-      if (was) {
-        // newly exposed node: fluid at rest in the wall frame, Q from the
-        // face neighbours that are fluid before and after the move
-        double ub[3];
-        rigid_vel(B, r, ub);
-        if (B.hydro) {
-          const double usq = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+  const long long g = site_of(B, x, y, z);
+  double r[3], p[3] = {0, 0, 0};
+  rel_pos(B, Rn, (double)x, (double)y, (double)z, r);
+  if (was) {
+    double ub[3];
+    rigid_vel(B, r, ub);
+    if (B.hydro) {
+      const double usq = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
 #pragma unroll
-          for (int i = 0; i < 19; i++) {
-            const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
-            const double feq = wgt(i) * B.rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-            a.fout[i * NS + g] = (R)(feq - wgt(i));
-            p[0] -= feq * cx(i); p[1] -= feq * cy(i); p[2] -= feq * cz(i);
-          }
-          for (int c = 0; c < 3; c++) a.uout[c * NS + g] = (R)ub[c];
-        }
-        const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-        double qm[5] = {0, 0, 0, 0, 0};
-        int nf = 0;
-        for (int k = 0; k < 6; k++) {
-          const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
-          if (inside(B, Rc, xn, yn, zn) || inside(B, Rn, xn, yn, zn)) continue;
-          const long long gn = B.off + xn + (long long)B.nx * (yn + (long long)B.ny * zn);
-          for (int c = 0; c < 5; c++) qm[c] += (double)a.Qout[c * NS + gn];
-          nf++;
-        }
-        for (int c = 0; c < 5; c++) a.Qout[c * NS + g] = (R)(nf ? qm[c] / nf : 0.0);
-      } else if (B.hydro) {
-        // newly covered node: its fluid momentum goes to the colloid
-#pragma unroll
-        for (int i = 0; i < 19; i++) {
-          const double fi = (double)a.fout[i * NS + g] + wgt(i);
-          p[0] += fi * cx(i); p[1] += fi * cy(i); p[2] += fi * cz(i);
-        }
+      for (int i = 0; i < 19; i++) {
+        const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
+        const double feq = wgt(i) * B.rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        a.fout[i * NS + g] = (R)(feq - wgt(i));
+        p[0] -= feq * cx(i); p[1] -= feq * cy(i); p[2] -= feq * cz(i);
       }
-      v[0] = p[0]; v[1] = p[1]; v[2] = p[2];
-      v[3] = r[1] * p[2] - r[2] * p[1];
-      v[4] = r[2] * p[0] - r[0] * p[2];
-      v[5] = r[0] * p[1] - r[1] * p[0];
+      for (int c = 0; c < 3; c++) a.uout[c * NS + g] = (R)ub[c];
+    }
+    double q5[5];
+    exposed_q<R>(B, Rc, Rn, x, y, z, a.Qout, NS, q5);
+    for (int c = 0; c < 5; c++) a.Qout[c * NS + g] = (R)q5[c];
+  } else if (B.hydro) {
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+      const double fi = (double)a.fout[i * NS + g] + wgt(i);
+      p[0] += fi * cx(i); p[1] += fi * cy(i); p[2] += fi * cz(i);
     }
   }
-  block_sum<kEventBlock, 6>(v, sred, epart + 6LL * blockIdx.x);
+  v[0] += p[0]; v[1] += p[1]; v[2] += p[2];
+  v[6] += r[1] * p[2] - r[2] * p[1];
+  v[7] += r[2] * p[0] - r[0] * p[2];
+  v[8] += r[0] * p[1] - r[1] * p[0];
 }
 
 // ---------------------------------------------------------------------
-// finalize: fixed-order sums, force history, colloid position
+// post-step: events, next step's ghost Q, colloid sums, history, R += v
 // ---------------------------------------------------------------------
-__global__ void __launch_bounds__(1024)
-    k_finalize(int TX, int TY, int TZ, BoxDev* __restrict__ boxes, const double* __restrict__ part, long long nslot,
-               const double* __restrict__ epart, double* __restrict__ force, double* __restrict__ hist, int cap,
-               long long* __restrict__ count) {
-  __shared__ double sred[16 * 12];
-  __shared__ double sres[12];
-  const int b = blockIdx.x;
-  BoxDev& B = boxes[b];
+// Threads of box b, in three ranges: fused-kernel slot sums (kPostSlots
+// consecutive slots each; every slot was written this step, zeros where the
+// colloid is out of reach, so all are added), then one thread per event
+// candidate, then one per ghost candidate.  Each thread has one role, so
+// the roles' memory latencies overlap.  Each block adds its threads'
+// 12-vectors (slot sums and event momenta) in thread order into bpart;
+// k_finish adds the block vectors of each box in block order.
+template <typename R>
+__global__ void __launch_bounds__(kPostBlock)
+    k_post(const BoxDev* __restrict__ boxes, int nbox, StepPtrs<R> a, double* __restrict__ bpart) {
+  __shared__ double sred[(kPostBlock / 64) * 12];
+  int b = 0;
+  for (int k = 1; k < nbox; k++)
+    if ((int)blockIdx.x >= boxes[k].post_blk0) b = k;
+  const BoxDev& B = boxes[b];
+  long long l = (long long)((int)blockIdx.x - B.post_blk0) * kPostBlock + threadIdx.x;
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (B.present) {
-    // every tile (or column-block group) wrote its slot this step, zeros
-    // where the kernels' test found the colloid out of reach; only the
-    // others are read (the same integer test, z first)
-    const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
-    const int nt = B.ntx * B.nty * B.ntz;
-    for (int k = threadIdx.x; k < nt; k += 1024) {
-      const int tix = k % B.ntx, tiy = (k / B.ntx) % B.nty, tiz = k / (B.ntx * B.nty);
-      if (!axis_near(B, Rc, 2, tiz * TZ - 2, TZ + 4) || !axis_near(B, Rc, 1, tiy * TY - 2, TY + 4) ||
-          !axis_near(B, Rc, 0, tix * TX - 2, TX + 4))
-        continue;
-      const double* p = part + B.tile_base + k;
-      for (int c = 0; c < 12; c++) v[c] += p[c * nslot];
-    }
-    if (B.motion == 1) {
-      for (int k = threadIdx.x; k < B.event_nblk; k += 1024) {
-        const double* p = epart + 6LL * (B.event_blk0 + k);
-        v[0] += p[0]; v[1] += p[1]; v[2] += p[2];
-        v[6] += p[3]; v[7] += p[4]; v[8] += p[5];
+    const long long nt = (long long)B.ntx * B.nty * B.ntz;
+    const long long nst = (nt + kPostSlots - 1) / kPostSlots;
+    const long long ne = B.motion == 1 ? (long long)B.event_ext * B.event_ext * B.event_ext : 0;
+    const long long ng = (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
+    if (l < nst) {
+      const long long k0 = l * kPostSlots;
+      double t[kPostSlots][12];
+#pragma unroll
+      for (int j = 0; j < kPostSlots; j++) {
+        const bool ok = k0 + j < nt;
+        const double* p = a.part + B.tile_base + (ok ? k0 + j : 0);
+#pragma unroll
+        for (int c = 0; c < 12; c++) t[j][c] = ok ? p[c * a.nslot] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < kPostSlots; j++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) v[c] += t[j][c];
+    } else {
+      const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+      const bool moving = B.motion == 1;
+      double Rn[3] = {Rc[0], Rc[1], Rc[2]};
+      if (moving) advanced_pos(B, Rn);
+      l -= nst;
+      int x, y, z;
+      if (l < ne) {
+        cube_site(B, Rc, B.event_ext, l, x, y, z);
+        event_site<R>(B, Rc, Rn, x, y, z, a, v);
+      } else if (l - ne < ng) {
+        cube_site(B, Rn, B.ghost_ext, l - ne, x, y, z);
+        ghost_site<R>(B, Rc, Rn, moving, x, y, z, a.Qout, a.nsites);
       }
     }
   }
-  block_sum<1024, 12>(v, sred, sres);
+  block_sum<kPostBlock, 12>(v, sred, bpart + 12LL * blockIdx.x);
+}
+
+// One block per box: the colloid's force and torque (block vectors in
+// block order), the force history and R += v.
+__global__ void __launch_bounds__(kFinishBlock)
+    k_finish(BoxDev* __restrict__ boxes, const double* __restrict__ bpart, double* __restrict__ force,
+             double* __restrict__ hist, int cap, long long* __restrict__ count) {
+  __shared__ double sred[(kFinishBlock / 64) * 12];
+  __shared__ double sres[12];
+  const int b = blockIdx.x;
+  BoxDev& B = boxes[b];
+  double w[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < B.post_nblk; k += kFinishBlock) {
+    const double* p = bpart + 12LL * (B.post_blk0 + k);
+    for (int c = 0; c < 12; c++) w[c] += p[c];
+  }
+  block_sum<kFinishBlock, 12>(w, sred, sres);
   __syncthreads();
   if (threadIdx.x < 12) {
     const double val = B.present ? sres[threadIdx.x] : 0.0;
@@ -1446,13 +1541,6 @@ int march_blocks_per_cu(int tile) {
   return n;
 }
 
-hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part, long long nslot,
-                           const double* epart, double* force, double* hist, int cap, long long* count,
-                           hipStream_t s) {
-  k_finalize<<<nbox, 1024, 0, s>>>(tx, ty, tz, boxes, part, nslot, epart, force, hist, cap, count);
-  return hipGetLastError();
-}
-
 template <typename R>
 hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, hipStream_t s) {
   if (total <= 0) return hipSuccess;
@@ -1462,10 +1550,12 @@ hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, lo
 }
 
 template <typename R>
-hipError_t launch_events(const BoxDev* boxes, int nbox, long long total, const StepPtrs<R>& a, double* epart,
-                         hipStream_t s) {
-  if (total <= 0) return hipSuccess;
-  k_events<R><<<(unsigned)(total / kEventBlock), kEventBlock, 0, s>>>(boxes, nbox, total, a, epart);
+hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, double* force,
+                       double* hist, int cap, long long* count, hipStream_t s) {
+  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, nbox, a, bpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_finish<<<(unsigned)nbox, kFinishBlock, 0, s>>>(boxes, bpart, force, hist, cap, count);
   return hipGetLastError();
 }
 
@@ -1493,8 +1583,8 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
   template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const int*, const StepPtrs<R>&,               \
                                      hipStream_t);                                                          \
   template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, hipStream_t);           \
-  template hipError_t launch_events<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*,          \
-                                       hipStream_t);                                                        \
+  template hipError_t launch_post<R>(int, int, BoxDev*, const StepPtrs<R>&, double*, double*, double*, int,   \
+                                     long long*, hipStream_t);                                                \
   template hipError_t launch_diag<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*, hipStream_t); \
   template hipError_t launch_defects<R>(const BoxDev*, int, long long, const R*, long long, double,         \
                                         unsigned char*, unsigned long long*, hipStream_t);                  \

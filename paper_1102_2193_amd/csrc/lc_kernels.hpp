@@ -47,9 +47,13 @@ struct StepPtrs {
 // block cb (x fastest) and first group g0.  Limits: box, cb < 2^16;
 // g0, ng < 2^15.  Padding items have x = -1.
 constexpr int kGroup = 1;
-// Threads per block of the moving-boundary kernel; every box's range of
-// candidate nodes is padded to whole blocks (one box per block).
-constexpr int kEventBlock = 64;
+// Threads per block of the post-step kernel; every box has its own whole
+// blocks (one box per block).
+constexpr int kPostBlock = 64;
+// Colloid slots added by one post-step thread; threads of the per-box
+// finishing kernel.
+constexpr int kPostSlots = 4;
+constexpr int kFinishBlock = 1024;
 constexpr int kMaxBoxes = 1 << 16, kMaxColBlocks = 1 << 16, kMaxGroups = 1 << 15;
 __host__ __device__ inline int2 march_item(int box, int cb, int g0, int ng) {
   return make_int2(box | (ng << 16), cb | (g0 << 16));
@@ -68,15 +72,17 @@ hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tile
 // Resident blocks per compute unit of FP32 marching shape `tile` (0 if the
 // shape is not a marching one).
 int march_blocks_per_cu(int tile);
-// tx, ty, tz: extents of one tile (3D tile or marching column chunk)
-hipError_t launch_finalize(int tx, int ty, int tz, int nbox, BoxDev* boxes, const double* part, long long nslot,
-                           const double* epart, double* force, double* hist, int cap, long long* count,
-                           hipStream_t s);
+// Anchoring pass: ghost Q at the boundary solid nodes of the Q buffer
+// (before the first step and after any change made from the host).
 template <typename R>
 hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, hipStream_t s);
+// After the fused kernel: moving-boundary events, the next step's ghost Q
+// and per-block sums of the fused kernel's colloid slots and the event
+// momenta (nblk blocks), then one block per box adding them in block order:
+// force, force history, R += v.
 template <typename R>
-hipError_t launch_events(const BoxDev* boxes, int nbox, long long total, const StepPtrs<R>& a, double* epart,
-                         hipStream_t s);
+hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, double* force,
+                       double* hist, int cap, long long* count, hipStream_t s);
 template <typename R>
 hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const StepPtrs<R>& a, double* out,
                        hipStream_t s);

@@ -60,9 +60,11 @@ struct lc_ctx {
   int2* dtiles = nullptr;
   int* doffs = nullptr;         // marching shapes: item range of each persistent block
   double* dpart = nullptr;      // 12 per tile
-  long long ghost_total = 0, event_total = 0;
-  double* depart = nullptr;     // 6 per event block
-  size_t depart_cap = 0;
+  long long ghost_total = 0;
+  int npost = 0;                // blocks of the post-step kernel
+  double* dbpart = nullptr;     // 12 per post-step block
+  size_t dbpart_cap = 0;
+  bool ghost_fresh = false;     // ghost Q of buffer cur matches the colloids
   double* dforce = nullptr;     // 12 per box
   double* dhist = nullptr;      // nbox * kHistCap * 12
   long long* dcount = nullptr;  // steps per box on the device
@@ -308,13 +310,20 @@ int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& 
 // as much per plane).  Those short items go first in the launch, spread over
 // the dies, so that the hardware's in-order dispatch starts them at once and
 // fills the remaining time with the long items.
+// The marching kernel addresses each population array through one buffer
+// resource with 32-bit component offsets: 19 x sites x 4 bytes must stay
+// below 4 GiB.
+bool march_fits(const lc_ctx* c) { return 19.0 * 4.0 * (double)c->nsites < 4294967296.0; }
+
 int layout(lc_ctx* c) {
   const TileShape& T = tile_shape(c, c->tile);
-  long long tb = 0, gb = 0, eb = 0;
-  int eblk = 0;
+  long long tb = 0, gb = 0;
+  int pblk = 0;
   c->any_colloid = c->any_moving = false;
   std::vector<int2> tiles;
   if (T.kind == 1 && c->nbox > lc::kMaxBoxes) return fail(c, LC_EINVAL, "too many boxes for the marching kernel");
+  if (T.kind == 1 && !march_fits(c))
+    return fail(c, LC_EINVAL, "context too large for the marching kernel (19 x sites x 4 bytes >= 4 GiB); use a 3D tile");
   for (int b = 0; b < c->nbox; b++) {
     BoxDev& B = c->hb[b];
     const lc_params& p = c->prm[b];
@@ -352,19 +361,24 @@ int layout(lc_ctx* c) {
     gb += (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
     const bool moving = k.present && k.motion == LC_PRESCRIBED;
     B.event_ext = moving ? 2 * ca + 5 : 0;
-    B.event_base = (int)eb;
-    B.event_blk0 = eblk;
+    // post-step threads: slot sums (kPostSlots slots each), one per event
+    // candidate, one per ghost candidate; at least one block per box
+    const long long nt = (long long)B.ntx * B.nty * B.ntz;
+    const long long nst = k.present ? (nt + lc::kPostSlots - 1) / lc::kPostSlots : 0;
     const long long ne = (long long)B.event_ext * B.event_ext * B.event_ext;
-    B.event_nblk = (int)((ne + lc::kEventBlock - 1) / lc::kEventBlock);
-    eb += (long long)lc::kEventBlock * B.event_nblk;
-    eblk += B.event_nblk;
+    const long long ng = (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
+    B.post_blk0 = pblk;
+    B.post_nblk = (int)std::max(1LL, (nst + ne + ng + lc::kPostBlock - 1) / lc::kPostBlock);
+    if ((long long)pblk + B.post_nblk > (1LL << 30)) return fail(c, LC_EINVAL, "too many post-step blocks");
+    pblk += B.post_nblk;
     c->any_colloid |= (bool)k.present;
     c->any_moving |= moving;
   }
   if (tb > (1LL << 30)) return fail(c, LC_EINVAL, "too many tiles");
   c->ntile = (int)tb;
   c->ghost_total = gb;
-  c->event_total = eb;
+  c->npost = pblk;
+  c->ghost_fresh = false;
   std::vector<int2> order;
   std::vector<int> offs;
   if (T.kind == 1) {
@@ -401,11 +415,11 @@ int layout(lc_ctx* c) {
   }
   HIPCHK(c, hipMalloc(&c->dpart, sizeof(double) * 12 * std::max(1, c->ntile)));
   HIPCHK(c, hipMemsetAsync(c->dpart, 0, sizeof(double) * 12 * std::max(1, c->ntile), c->stream));
-  if ((size_t)eblk * 6 > c->depart_cap) {
-    if (c->depart) hipFree(c->depart);
-    c->depart = nullptr;
-    c->depart_cap = std::max<size_t>(6, (size_t)eblk * 6);
-    HIPCHK(c, hipMalloc(&c->depart, sizeof(double) * c->depart_cap));
+  if ((size_t)pblk * 12 > c->dbpart_cap) {
+    if (c->dbpart) hipFree(c->dbpart);
+    c->dbpart = nullptr;
+    c->dbpart_cap = std::max<size_t>(12, (size_t)pblk * 12);
+    HIPCHK(c, hipMalloc(&c->dbpart, sizeof(double) * c->dbpart_cap));
   }
   HIPCHK(c, hipMemcpyAsync(c->dtiles, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->dbox, c->hb.data(), sizeof(BoxDev) * c->nbox, hipMemcpyHostToDevice, c->stream));
@@ -430,31 +444,39 @@ lc::StepPtrs<R> ptrs(lc_ctx* c, int from) {
   return a;
 }
 
-// Queue one step reading buffer set `from`.
+// One step from buffer `from`: the fused kernel, then the post-step kernel
+// (events, the ghost Q of the new buffer, colloid sums, R += v).  The ghost
+// Q of `from` must be current (ghost_pass).
 template <typename R>
 hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t k1 = nullptr) {
   hipError_t e;
   lc::StepPtrs<R> a = ptrs<R>(c, from);
-  if (c->any_colloid) {
-    e = lc::launch_ghost<R>(c->dbox, c->nbox, c->ghost_total, (R*)c->Q[from], c->nsites, c->stream);
-    if (e != hipSuccess) return e;
-  }
   if (k0) hipEventRecord(k0, c->stream);
   e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, c->doffs, a, c->stream);
   if (e != hipSuccess) return e;
   if (k1) hipEventRecord(k1, c->stream);
-  if (c->any_moving) {
-    e = lc::launch_events<R>(c->dbox, c->nbox, c->event_total, a, c->depart, c->stream);
-    if (e != hipSuccess) return e;
-  }
-  const TileShape& T = tile_shape(c, c->tile);
-  return lc::launch_finalize(T.x, T.y, T.kind ? lc::kGroup : T.z, c->nbox, c->dbox, c->dpart,
-                             std::max(1, c->ntile), c->depart, c->dforce, c->dhist,
-                             kHistCap, c->dcount, c->stream);
+  return lc::launch_post<R>(c->npost, c->nbox, c->dbox, a, c->dbpart, c->dforce, c->dhist, kHistCap, c->dcount,
+                            c->stream);
 }
 
 hipError_t enqueue(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t k1 = nullptr) {
   return c->prec == LC_FP32 ? enqueue_step<float>(c, from, k0, k1) : enqueue_step<double>(c, from, k0, k1);
+}
+
+// Anchoring pass over buffer cur, needed once after anything changed Q or
+// a colloid from the host; every step then leaves the new buffer current.
+int ghost_pass(lc_ctx* c) {
+  if (c->ghost_fresh) return LC_OK;
+  if (c->any_colloid) {
+    hipError_t e = c->prec == LC_FP32
+                       ? lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites,
+                                                 c->stream)
+                       : lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites,
+                                                  c->stream);
+    HIPCHK(c, e);
+  }
+  c->ghost_fresh = true;
+  return LC_OK;
 }
 
 int build_graph(lc_ctx* c) {
@@ -525,6 +547,7 @@ int get_field(lc_ctx* c, const void* dev, int box, int ncomp, double* dst, doubl
 }
 
 int put(lc_ctx* c, void* dev, int box, int ncomp, const double* src, bool shift) {
+  c->ghost_fresh = false;
   return c->prec == LC_FP32 ? put_field<float>(c, dev, box, ncomp, src, shift ? 1.0 : 0.0)
                             : put_field<double>(c, dev, box, ncomp, src, shift ? 1.0 : 0.0);
 }
@@ -571,6 +594,7 @@ int lc_internal_q_view(lc_ctx* c, int box, LcQView* out) {
   int rc = check_box(c, box);
   if (rc) return rc;
   out->Q = c->Q[c->cur];
+  c->ghost_fresh = false;   // the caller writes Q
   out->nsites = c->nsites;
   out->off = c->hb[box].off;
   out->prec = c->prec;
@@ -665,6 +689,12 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
                                       : lc::launch_fill<double>((double*)c->f[k], c->nsites, p[0].rho0, c->stream);
     if (e != hipSuccess) return bail(LC_EDEVICE, std::string("init: ") + hipGetErrorString(e));
   }
+  if (!march_fits(c))   // default to the first 3D-tile shape
+    for (int t = 0; t < num_tiles(c); t++)
+      if (tile_shape(c, t).kind == 0) {
+        c->tile = t;
+        break;
+      }
   rc = layout(c);
   if (rc != LC_OK) return bail(rc, c->err);
   for (int b = 0; b < nbox; b++) {
@@ -690,7 +720,8 @@ void lc_destroy(lc_ctx* c) {
       if (c->Q[k]) hipFree(c->Q[k]);
       if (c->u[k]) hipFree(c->u[k]);
     }
-  void* bufs[] = {c->dbox, c->dtiles, c->doffs, c->dpart, c->depart, c->dforce, c->dhist, c->dcount, c->dflag, c->ddiag};
+  void* bufs[] = {c->dbox,  c->dtiles, c->doffs, c->dpart, c->dbpart,
+                  c->dforce, c->dhist,  c->dcount, c->dflag, c->ddiag};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -929,6 +960,10 @@ int lc_set_state(lc_ctx* c, const void* buf, size_t bytes) {
 int lc_step(lc_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return LC_EINVAL;
   int left = nsteps;
+  if (nsteps > 0) {
+    int rc = ghost_pass(c);
+    if (rc != LC_OK) return rc;
+  }
   auto eager = [&]() -> int {
     hipError_t e = enqueue(c, c->cur);
     if (e != hipSuccess) return fail(c, LC_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
@@ -1095,6 +1130,8 @@ int lc_launch_info(const lc_ctx* c, long out[2]) {
 
 int lc_time_kernel(lc_ctx* c, int nsteps, double out[3]) {
   if (!c || !out || nsteps < 1) return LC_EINVAL;
+  int rc = ghost_pass(c);
+  if (rc != LC_OK) return rc;
   std::vector<hipEvent_t> ev(2 * nsteps + 2);
   for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
   HIPCHK(c, hipEventRecord(ev[2 * nsteps], c->stream));
