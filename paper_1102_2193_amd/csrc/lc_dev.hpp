@@ -40,6 +40,24 @@ __host__ __device__ constexpr int cz(int i) {
   return i == 5 || i == 11 || i == 14 || i == 15 || i == 18 ? 1
        : i == 6 || i == 12 || i == 13 || i == 16 || i == 17 ? -1 : 0;
 }
+// c_i . v for direction i with the zero components left out: a product
+// with a zero component is not folded away in IEEE arithmetic and would
+// cost an instruction.  The nonzero terms are added in x, y, z order, as
+// the full dot product adds them.
+template <typename R>
+__device__ __forceinline__ R cdot(int i, const R v[3]) {
+  const int c[3] = {cx(i), cy(i), cz(i)};
+  R s = (R)0;
+  bool first = true;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    if (c[k] == 0) continue;
+    const R t = c[k] > 0 ? v[k] : -v[k];
+    s = first ? t : s + t;
+    first = false;
+  }
+  return s;
+}
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 __host__ __device__ constexpr double wgt(int i) {
   return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);

@@ -465,8 +465,8 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
       for (int i = 1; i < 19; i += 2) {
         // the pair (i, i+1) has opposite velocities: shared even parts
         const R w = (R)wgt(i);
-        const R cu = (R)cx(i) * u[0] + (R)cy(i) * u[1] + (R)cz(i) * u[2];
-        const R cF = (R)cx(i) * F[0] + (R)cy(i) * F[1] + (R)cz(i) * F[2];
+        const R cu = cdot(i, u);
+        const R cF = cdot(i, F);
         const R even = w * rm1 + w * rho * ((R)4.5 * cu * cu - (R)1.5 * usq);
         const R odd = w * rho * (R)3 * cu;
         const R seven = w * ((R)9 * cu * cF - (R)3 * uF);
@@ -498,7 +498,7 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
           // bounce-back on the link with the moving-wall correction; the
           // link passes (2 f_i - corr) c_i to the colloid at r_site + c_i/2,
           // whose torque about the centre is r_site x dp (c_i x c_i = 0)
-          const R cub = (R)cx(i) * ubs[0] + (R)cy(i) * ubs[1] + (R)cz(i) * ubs[2];
+          const R cub = cdot(i, ubs);
           const R corr = (R)(6.0 * wgt(i)) * (R)B.rho0 * cub;
           __builtin_nontemporal_store(fs[i] - corr, at32(a.fout + opp(i) * NS, g));
           const double m = 2.0 * ((double)fs[i] + wgt(i)) - (double)corr;
@@ -973,8 +973,8 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
 #pragma unroll
         for (int i = 1; i < 19; i += 2) {
           const R w = (R)wgt(i);
-          const R cu = (R)cx(i) * u[0] + (R)cy(i) * u[1] + (R)cz(i) * u[2];
-          const R cF = (R)cx(i) * F[0] + (R)cy(i) * F[1] + (R)cz(i) * F[2];
+          const R cu = cdot(i, u);
+          const R cF = cdot(i, F);
           const R even = w * rm1 + w * rho * ((R)4.5 * cu * cu - (R)1.5 * usq);
           const R odd = w * rho * (R)3 * cu;
           const R seven = w * ((R)9 * cu * cF - (R)3 * uF);
@@ -982,6 +982,9 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
           fs[i] = f[i] - (f[i] - (even + odd)) * itau + fsrc * (seven + sodd);
           fs[i + 1] = f[i + 1] - (f[i + 1] - (even - odd)) * itau + fsrc * (seven - sodd);
         }
+        // the next plane's populations are requested before this plane's
+        // stores (f is dead once fs is formed)
+        if (more) fetch_f(k + 1);
         const int dxp = gx + 1 == nx ? 1 - nx : 1, dxm = gx == 0 ? nx - 1 : -1;
         const int dyp = gy + 1 == ny ? nx * (1 - ny) : nx, dym = gy == 0 ? nx * (ny - 1) : -nx;
         const int dzp = gz + 1 == nz ? nxy * (1 - nz) : nxy, dzm = gz == 0 ? nxy * (nz - 1) : -nxy;
@@ -1005,7 +1008,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
             // link bounce-back with the moving-wall term; the link passes
             // (2 f_i - corr) c_i to the colloid at r_site + c_i/2, whose
             // torque about the centre is r_site x dp (c_i x c_i = 0)
-            const R cub = (R)cx(i) * ubs[0] + (R)cy(i) * ubs[1] + (R)cz(i) * ubs[2];
+            const R cub = cdot(i, ubs);
             const R corr = (R)(6.0 * wgt(i)) * (R)B.rho0 * cub;
             bfout.st_nt(opp(i), g, fs[i] - corr);
             const double m = 2.0 * ((double)fs[i] + wgt(i)) - (double)corr;
@@ -1035,7 +1038,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
       if (pnear) update(std::true_type{});
       else update(std::false_type{});
     }
-    if (more) fetch_f(k + 1);
+    if (more && !(incol && fluid)) fetch_f(k + 1);
     if (pnear) {
       // wave sums in plane order into the wave's own slots (no barrier);
       // waves without a solid link this plane skip the reduction
