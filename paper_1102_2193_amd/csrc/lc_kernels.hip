@@ -643,7 +643,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     for (int m = 0; m < MQ; m++)
       if (m < MQ - 1 || tid + m * NT < QP)
 #pragma unroll
-        for (int c = 0; c < 5; c++) dst[m][c] = bqin.ld(c, zo + (unsigned)qo[m]);
+        for (int c = 0; c < 5; c++) dst[m][c] = bqin.ld_nt(c, zo + (unsigned)qo[m]);
   };
   auto fetch_u = [&](R (&dst)[MU][3], int z) {
     const unsigned zo = off + (unsigned)(nxy * wrapn(z, nz));
@@ -651,7 +651,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     for (int m = 0; m < MU; m++)
       if (m < MU - 1 || tid + m * NT < UP)
 #pragma unroll
-        for (int c = 0; c < 3; c++) dst[m][c] = buin.ld(c, zo + (unsigned)uo[m]);
+        for (int c = 0; c < 3; c++) dst[m][c] = buin.ld_nt(c, zo + (unsigned)uo[m]);
   };
   auto store_q = [&](const R (&rq)[MQ][5], int slot, int z) {
     const int wz = wrapn(z, nz);
