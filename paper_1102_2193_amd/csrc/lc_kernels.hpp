@@ -34,7 +34,8 @@ struct StepPtrs {
   X(4, 16, 16, 16, 1)    \
   X(5, 32, 16, 8, 1)     \
   X(6, 16, 8, 2, 0)      \
-  X(7, 32, 16, 16, 1)
+  X(7, 32, 16, 16, 1)    \
+  X(8, 64, 8, 8, 1)
 // FP64 (the verification precision) uses the 3D-tile form only.
 #define LC_TILES_F64(X)  \
   X(0, 8, 4, 4, 0)       \
