@@ -160,13 +160,14 @@ int lc_state_bytes(const lc_ctx* ctx, size_t* out);
 int lc_get_state(lc_ctx* ctx, void* buf, size_t bytes);
 int lc_set_state(lc_ctx* ctx, const void* buf, size_t bytes);
 
-/* Advance every box by nsteps steps.  Each step: ghost Q at boundary solid
- * nodes (anchoring), then one fused pass per site (molecular field H,
- * stress P, force = discrete divergence of P, Beris-Edwards update of Q,
- * LB collision with that force, push streaming with bounce-back on links
- * and the colloid's force/torque sums), then moving-boundary events and
- * the colloid update.  Asynchronous; replays a captured HIP graph when
- * graphs are enabled. */
+/* Advance every box by nsteps steps.  Each step: one fused pass per site
+ * (molecular field H, stress P, force = discrete divergence of P,
+ * Beris-Edwards update of Q, LB collision with that force, push streaming
+ * with bounce-back on links and the colloid's force/torque sums), then the
+ * moving-boundary events, the ghost Q at boundary solid nodes (anchoring)
+ * of the new Q for the next step, and the colloid update.  Before the first
+ * step after a change from the host the ghost Q are formed once.
+ * Asynchronous; replays a captured HIP graph when graphs are enabled. */
 int lc_step(lc_ctx* ctx, int nsteps);
 int lc_sync(lc_ctx* ctx);       /* wait for the stream; LC_ENUMERIC if flagged */
 long lc_get_nstep(lc_ctx* ctx); /* steps taken (host count) */
@@ -202,10 +203,11 @@ int lc_use_graph(lc_ctx* ctx, int enable);
  * step and threads per block. */
 int lc_launch_info(const lc_ctx* ctx, long out[2]);
 
-/* Run nsteps steps without graphs, with HIP events recorded on the
- * context's stream around every fused-kernel launch and around the whole
- * run: out[0] = mean fused-kernel time per launch (ms), out[1] = mean time
- * per step (ms), out[2] = total (ms).  Synchronises the stream. */
+/* Run nsteps steps without graphs, with start/stop HIP events carried by
+ * every fused-kernel dispatch (hipExtLaunchKernel: no separate event
+ * commands between the kernels) and events on the context's stream around
+ * the whole run: out[0] = mean fused-kernel time per launch (ms), out[1] =
+ * mean time per step (ms), out[2] = total (ms).  Synchronises the stream. */
 int lc_time_kernel(lc_ctx* ctx, int nsteps, double out[3]);
 
 #ifdef __cplusplus

@@ -16,6 +16,8 @@
 // Populations are stored shifted, f~ = f - w_i, which keeps FP32 rounding
 // relative to the small deviations from rest.  Every array is
 // structure-of-arrays [component][site] over the concatenation of all boxes.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "lc_kernels.hpp"
@@ -1506,13 +1508,21 @@ __global__ void __launch_bounds__(256) k_fill_f(R* f, long long NS, const double
 // ---------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------
+// Launch with start/stop events carried by the dispatch itself when given
+// (no separate event commands between the kernels of a step).
+template <typename K, typename... Args>
+void launch_ev(K kernel, unsigned nblk, unsigned nthr, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0 || e1) hipExtLaunchKernelGGL(kernel, dim3(nblk), dim3(nthr), 0, s, e0, e1, 0, args...);
+  else hipLaunchKernelGGL(kernel, dim3(nblk), dim3(nthr), 0, s, args...);
+}
+
 template <typename R>
 hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const int* offs,
-                       const StepPtrs<R>& a, hipStream_t s) {
-#define LC_TILE_CASE(ID, X, Y, Z, KIND)                                               \
-  case ID:                                                                             \
-    if constexpr (KIND == 0) k_step<R, X, Y, Z><<<nblk, X * Y * Z, 0, s>>>(boxes, tiles, a); \
-    else k_march<R, X, Y, Z><<<nblk, X * Y, 0, s>>>(boxes, tiles, offs, a);                 \
+                       const StepPtrs<R>& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+#define LC_TILE_CASE(ID, X, Y, Z, KIND)                                                             \
+  case ID:                                                                                           \
+    if constexpr (KIND == 0) launch_ev(k_step<R, X, Y, Z>, nblk, X * Y * Z, s, e0, e1, boxes, tiles, a); \
+    else launch_ev(k_march<R, X, Y, Z>, nblk, X * Y, s, e0, e1, boxes, tiles, offs, a);                 \
     break;
   if constexpr (sizeof(R) == 4) {
     switch (tile) {
@@ -1583,8 +1593,8 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
 }
 
 #define LC_INST(R)                                                                                        \
-  template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const int*, const StepPtrs<R>&,               \
-                                     hipStream_t);                                                          \
+  template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const int*, const StepPtrs<R>&,   \
+                                     hipStream_t, hipEvent_t, hipEvent_t);                                  \
   template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, hipStream_t);           \
   template hipError_t launch_post<R>(int, int, BoxDev*, const StepPtrs<R>&, double*, double*, double*, int,   \
                                      long long*, hipStream_t);                                                \

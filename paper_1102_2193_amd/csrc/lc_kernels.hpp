@@ -66,10 +66,11 @@ __host__ __device__ inline int item_g0(int y) { return y >> 16; }
 
 // One launch of the fused kernel.  3D tiles: one block per entry of
 // `tiles`.  Marching shapes: `nblk` persistent blocks, block b taking the
-// work items tiles[offs[b]] .. tiles[offs[b+1]-1] in order.
+// work items tiles[offs[b]] .. tiles[offs[b+1]-1] in order.  e0/e1 (may be
+// null): events recorded when the kernel starts and ends.
 template <typename R>
 hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tiles, const int* offs,
-                       const StepPtrs<R>& a, hipStream_t s);
+                       const StepPtrs<R>& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Resident blocks per compute unit of FP32 marching shape `tile` (0 if the
 // shape is not a marching one).
 int march_blocks_per_cu(int tile);

@@ -451,10 +451,8 @@ template <typename R>
 hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t k1 = nullptr) {
   hipError_t e;
   lc::StepPtrs<R> a = ptrs<R>(c, from);
-  if (k0) hipEventRecord(k0, c->stream);
-  e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, c->doffs, a, c->stream);
+  e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, c->doffs, a, c->stream, k0, k1);
   if (e != hipSuccess) return e;
-  if (k1) hipEventRecord(k1, c->stream);
   return lc::launch_post<R>(c->npost, c->nbox, c->dbox, a, c->dbpart, c->dforce, c->dhist, kHistCap, c->dcount,
                             c->stream);
 }
