@@ -4,19 +4,24 @@
 // A 3x3x3 periodic convolution is an implicit GEMM: M = voxels of an
 // 8x8x4 tile, N = output channels, K = 27 taps x input channels.  Each
 // wave owns one z-layer of the tile (64 voxels = four 16-row M tiles) and
-// multiplies BF16 fragments on the matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation).  Fragment layout of that
-// instruction for a wave of 64 lanes: A[i][k] -> lane i + 16*(k/4),
-// element k%4; B[k][j] -> lane j + 16*(k/4), element k%4; D[i][j] -> lane
-// j + 16*(i/4), element i%4.
+// multiplies BF16 fragments on the matrix cores (v_mfma_f32_16x16x32_bf16
+// for 32-channel inputs, v_mfma_f32_16x16x16_bf16 for 16, FP32
+// accumulation).  Fragment layout for a wave of 64 lanes: A[i][k] -> lane
+// i + 16*(k/KB), element k%KB; B[k][j] -> lane j + 16*(k/KB), element
+// k%KB (KB = K/4 consecutive k per lane); D[i][j] -> lane j + 16*(i/4),
+// element i%4.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "nn_kernels.hpp"
 
 namespace lcnn {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline uint16_t f2bf(float x) {
@@ -77,19 +82,45 @@ template <int CIN, int COUT, int MODE>
 __global__ void __launch_bounds__(256)
     k_conv(int L, const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias,
            const float* __restrict__ zprev, float* __restrict__ zout, uint16_t* __restrict__ aout) {
-  constexpr int CS = CIN + 4;   // LDS voxel stride (bank spread)
-  __shared__ uint16_t sx[HV * CS];
+  // K of one matrix-core instruction: 32 input channels at once
+  // (v_mfma_f32_16x16x32_bf16) where the input has a multiple of 32, else
+  // 16.  Each lane's A and B fragments hold the same KI/4 consecutive
+  // channels, so the products pair up whatever order the instruction
+  // assigns to them within a K block.
+  constexpr int KI = CIN % 32 == 0 ? 32 : 16;
+  // LDS voxel stride (spread over the banks; 16-byte aligned fragments for
+  // K = 32) and staging chunk (elements)
+  constexpr int CS = CIN + (KI == 32 ? 8 : 4), SB = KI == 32 ? 8 : 4;
+  using Chunk = typename std::conditional<SB == 8, u4, uint2>::type;
+  __shared__ __align__(16) uint16_t sx[HV * CS];
   const int tid = threadIdx.x;
   const int ntx = L / TX, nty = L / TY;
   const int b = blockIdx.x;
   const int x0 = (b % ntx) * TX, y0 = ((b / ntx) % nty) * TY, z0 = (b / (ntx * nty)) * TZ;
-  constexpr int CH = CIN / 4;   // 8-byte chunks per voxel
-  for (int e = tid; e < HV * CH; e += 256) {
-    const int v = e / CH, c = e - v * CH;
-    const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
-    const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
-    const long long gv = gx + (long long)L * (gy + (long long)L * gz);
-    *(uint2*)(sx + v * CS + 4 * c) = *(const uint2*)(x + gv * CIN + 4 * c);
+  // halo staging: every load is issued before the first store to LDS, so
+  // their latencies overlap
+  constexpr int CH = CIN / SB, NIT = (HV * CH + 255) / 256;
+  {
+    Chunk tmp[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+      const int e = tid + it * 256;
+      if (e < HV * CH) {
+        const int v = e / CH, c = e - v * CH;
+        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+        const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
+        const long long gv = gx + (long long)L * (gy + (long long)L * gz);
+        tmp[it] = *(const Chunk*)(x + gv * CIN + SB * c);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+      const int e = tid + it * 256;
+      if (e < HV * CH) {
+        const int v = e / CH, c = e - v * CH;
+        *(Chunk*)(sx + v * CS + SB * c) = tmp[it];
+      }
+    }
   }
   __syncthreads();
   const int wv = tid >> 6, lane = tid & 63;
@@ -99,36 +130,42 @@ __global__ void __launch_bounds__(256)
   for (int m = 0; m < 4; m++)
 #pragma unroll
     for (int n = 0; n < COUT / 16; n++) acc[m][n] = f4{0.f, 0.f, 0.f, 0.f};
-  // weight fragments of tap t+1 are loaded while tap t runs on the matrix cores
-  constexpr int KC = CIN / 16, NN = COUT / 16;
-  s4 bcur[KC][NN], bnxt[KC][NN];
-  auto load_b = [&](int t, s4 (&bf)[KC][NN]) {
+  // weight fragments of taps t+1 .. t+PF-1 are in flight while tap t runs
+  // on the matrix cores
+  constexpr int KC = CIN / KI, NN = COUT / 16, PF = 4;
+  using Frag = typename std::conditional<KI == 32, u4, s4>::type;
+  Frag bq[PF][KC][NN];
+  auto load_b = [&](int t, Frag (&bf)[KC][NN]) {
 #pragma unroll
     for (int kc = 0; kc < KC; kc++)
 #pragma unroll
       for (int n = 0; n < NN; n++)
-        bf[kc][n] = *(const s4*)(w + ((long long)(t * COUT + n * 16 + ri) * CIN + kc * 16 + 4 * kq));
+        bf[kc][n] = *(const Frag*)(w + ((long long)(t * COUT + n * 16 + ri) * CIN + kc * KI + (KI / 4) * kq));
   };
-  load_b(0, bcur);
+#pragma unroll
+  for (int t = 0; t < PF; t++) load_b(t, bq[t]);
+#pragma unroll
   for (int t = 0; t < 27; t++) {
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-    if (t + 1 < 27) load_b(t + 1, bnxt);
 #pragma unroll
     for (int kc = 0; kc < KC; kc++) {
 #pragma unroll
       for (int m = 0; m < 4; m++) {
         const int lx = ri & 7, ly = 2 * m + (ri >> 3);
         const int hv = (lx + 1 + dx) + HX * ((ly + 1 + dy) + HY * (wv + 1 + dz));
-        const s4 af = *(const s4*)(sx + hv * CS + kc * 16 + 4 * kq);
+        const Frag af = *(const Frag*)(sx + hv * CS + kc * KI + (KI / 4) * kq);
 #pragma unroll
-        for (int n = 0; n < NN; n++)
-          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bcur[kc][n], acc[m][n], 0, 0, 0);
+        for (int n = 0; n < NN; n++) {
+          if constexpr (KI == 32)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, af),
+                                                                __builtin_bit_cast(bf8, bq[t % PF][kc][n]),
+                                                                acc[m][n], 0, 0, 0);
+          else
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bq[t % PF][kc][n], acc[m][n], 0, 0, 0);
+        }
       }
     }
-#pragma unroll
-    for (int kc = 0; kc < KC; kc++)
-#pragma unroll
-      for (int n = 0; n < NN; n++) bcur[kc][n] = bnxt[kc][n];
+    if (t + PF < 27) load_b(t + PF, bq[t % PF]);
   }
 #pragma unroll
   for (int m = 0; m < 4; m++)
@@ -180,28 +217,56 @@ __global__ void __launch_bounds__(256)
       for (int n = 0; n < CIN / 16; n++) acc[a][m][n] = f4{0.f, 0.f, 0.f, 0.f};
   for (int tile = blockIdx.x * tpb; tile < (blockIdx.x + 1) * tpb && tile < ntile; tile++) {
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-    __syncthreads();
-    // staged transposed ([channel][voxel]); four channels per 8-byte load
-    for (int e = tid; e < TV * (COUT / 4); e += 256) {
-      const int p = e / (COUT / 4), o = 4 * (e - p * (COUT / 4));
-      const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-      const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + lz));
-      const uint2 u = *(const uint2*)(dz + gv * COUT + o);
-      sd[o * PS + p] = (uint16_t)(u.x & 0xffffu);
-      sd[(o + 1) * PS + p] = (uint16_t)(u.x >> 16);
-      sd[(o + 2) * PS + p] = (uint16_t)(u.y & 0xffffu);
-      sd[(o + 3) * PS + p] = (uint16_t)(u.y >> 16);
+    // staged transposed ([channel][voxel]), eight channels per 16-byte
+    // load; every load of the tile is issued before the first LDS store
+    constexpr int DC = COUT / 8, XC = CIN / 8;
+    constexpr int NID = (TV * DC + 255) / 256, NIX = (HV * XC + 255) / 256;
+    u4 td[NID], tx[NIX];
+#pragma unroll
+    for (int it = 0; it < NID; it++) {
+      const int e = tid + it * 256;
+      if (e < TV * DC) {
+        const int p = e / DC, o = 8 * (e - p * DC);
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + lz));
+        td[it] = *(const u4*)(dz + gv * COUT + o);
+      }
     }
-    for (int e = tid; e < HV * (CIN / 4); e += 256) {
-      const int v = e / (CIN / 4), c = 4 * (e - v * (CIN / 4));
-      const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
-      const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
-      const long long gv = gx + (long long)L * (gy + (long long)L * gz);
-      const uint2 u = *(const uint2*)(x + gv * CIN + c);
-      sx[c * XS + v] = (uint16_t)(u.x & 0xffffu);
-      sx[(c + 1) * XS + v] = (uint16_t)(u.x >> 16);
-      sx[(c + 2) * XS + v] = (uint16_t)(u.y & 0xffffu);
-      sx[(c + 3) * XS + v] = (uint16_t)(u.y >> 16);
+#pragma unroll
+    for (int it = 0; it < NIX; it++) {
+      const int e = tid + it * 256;
+      if (e < HV * XC) {
+        const int v = e / XC, c = 8 * (e - v * XC);
+        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+        const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
+        const long long gv = gx + (long long)L * (gy + (long long)L * gz);
+        tx[it] = *(const u4*)(x + gv * CIN + c);
+      }
+    }
+    __syncthreads();   // the previous tile's LDS reads are done
+#pragma unroll
+    for (int it = 0; it < NID; it++) {
+      const int e = tid + it * 256;
+      if (e < TV * DC) {
+        const int p = e / DC, o = 8 * (e - p * DC);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          sd[(o + 2 * q) * PS + p] = (uint16_t)(td[it][q] & 0xffffu);
+          sd[(o + 2 * q + 1) * PS + p] = (uint16_t)(td[it][q] >> 16);
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NIX; it++) {
+      const int e = tid + it * 256;
+      if (e < HV * XC) {
+        const int v = e / XC, c = 8 * (e - v * XC);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          sx[(c + 2 * q) * XS + v] = (uint16_t)(tx[it][q] & 0xffffu);
+          sx[(c + 2 * q + 1) * XS + v] = (uint16_t)(tx[it][q] >> 16);
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
