@@ -24,7 +24,10 @@ struct BoxDev {
   double itau, fsrc;                     // 1/tau and 1 - 1/(2 tau)
   double body[3];
   int present, motion, anchoring, pad_;
-  double pos[3], a0, vel[3], omega[3], S0, W;
+  // colloid centre at the start of a step, by the step's buffer parity: the
+  // post-step kernel of a step writes the other slot
+  double pos[2][3];
+  double a0, vel[3], omega[3], S0, W;
 };
 
 // D3Q19: rest, 6 axis links, 12 diagonal links; opposite links adjacent.

@@ -8,8 +8,10 @@
 //               torque partial sums (Sec. 2.1-2.2)
 //   k_post      after each step: moving-boundary events of a colloid with
 //               prescribed motion, the next step's ghost Q, block sums of
-//               the colloid force and torque
-//   k_finish    fixed-order sum of the block sums, force history, R += v
+//               the colloid force and torque, R += v; its first block per
+//               box finishes the previous step (fixed-order sum of the block
+//               sums, force history)
+//   k_finish    the same finish, launched from the host for the last step
 //   k_diag      free energy, mass, momentum, max|u| partials
 //   k_defects   (3/2) lambda_max(Q) below a threshold
 //
@@ -200,7 +202,7 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
   const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
   const unsigned off = (unsigned)B.off;
   const long long NS = a.nsites;
-  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  const double Rc[3] = {B.pos[a.par][0], B.pos[a.par][1], B.pos[a.par][2]};
   const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, TZ + 4);
   // a single conditional correction wraps every halo coordinate
   const bool wide = nx >= TX + 2 && ny >= TY + 2 && nz >= TZ + 2;
@@ -608,7 +610,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   static_assert(std::is_same<R, float>::value, "the marching kernel is FP32 only");
   const FieldBuf bfin(a.fin, NS, 19), bfout(a.fout, NS, 19), bqin(a.Qin, NS, 5), bqout(a.Qout, NS, 5),
       buin(a.uin, NS, 3), buout(a.uout, NS, 3);
-  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  const double Rc[3] = {B.pos[a.par][0], B.pos[a.par][1], B.pos[a.par][2]};
   // nominal extent (whole groups): every group's own test (in k_post)
   // covers a subset of this range, so a group counted there was written here
   const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, ng * kGroup + 4);
@@ -1190,7 +1192,7 @@ __device__ inline void cube_site(const BoxDev& B, const double R[3], int E, long
 // positions).
 template <typename R>
 __global__ void __launch_bounds__(256)
-    k_ghost(const BoxDev* __restrict__ boxes, int nbox, long long total, R* __restrict__ Q, long long NS) {
+    k_ghost(const BoxDev* __restrict__ boxes, int nbox, long long total, R* __restrict__ Q, long long NS, int par) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   int b = 0;
@@ -1201,7 +1203,7 @@ __global__ void __launch_bounds__(256)
   const int E = B.ghost_ext;
   const long long l = t - B.ghost_base;
   if (l >= (long long)E * E * E) return;
-  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  const double Rc[3] = {B.pos[par][0], B.pos[par][1], B.pos[par][2]};
   int x, y, z;
   cube_site(B, Rc, E, l, x, y, z);
   ghost_site<R>(B, Rc, Rc, false, x, y, z, Q, NS);
@@ -1210,10 +1212,10 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------
 // moving-boundary events (prescribed motion)
 // ---------------------------------------------------------------------
-__device__ inline void advanced_pos(const BoxDev& B, double Rn[3]) {
+__device__ inline void advanced_pos(const BoxDev& B, int par, double Rn[3]) {
   const int L[3] = {B.nx, B.ny, B.nz};
   for (int c = 0; c < 3; c++) {
-    double r = __dadd_rn(B.pos[c], B.vel[c]);
+    double r = __dadd_rn(B.pos[par][c], B.vel[c]);
     if (r >= L[c]) r = __dsub_rn(r, (double)L[c]);
     if (r < 0.0) r = __dadd_rn(r, (double)L[c]);
     Rn[c] = r;
@@ -1266,27 +1268,67 @@ __device__ inline void event_site(const BoxDev& B, const double Rc[3], const dou
 // ---------------------------------------------------------------------
 // post-step: events, next step's ghost Q, colloid sums, history, R += v
 // ---------------------------------------------------------------------
+// Force, torque and history entry of one finished step of box b: the block
+// vectors of its post-step kernel added in block order (nt threads).
+template <int NT>
+__device__ inline void finish_box(const BoxDev& B, int b, const double* __restrict__ bpart, double* __restrict__ force,
+                                  double* __restrict__ hist, int cap, long long* __restrict__ count,
+                                  double* sred, double* sres) {
+  double w[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < B.post_nblk; k += NT) {
+    const double* p = bpart + 12LL * (B.post_blk0 + k);
+    for (int c = 0; c < 12; c++) w[c] += p[c];
+  }
+  block_sum<NT, 12>(w, sred, sres);
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    const double val = B.present ? sres[threadIdx.x] : 0.0;
+    const long long n = count[b];
+    force[12 * b + threadIdx.x] = val;
+    hist[((long long)b * cap + (n % cap)) * 12 + threadIdx.x] = val;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) count[b] += 1;
+}
+
 // Threads of box b, in three ranges: fused-kernel slot sums (kPostSlots
 // consecutive slots each; every slot was written this step, zeros where the
 // colloid is out of reach, so all are added), then one thread per event
 // candidate, then one per ghost candidate.  Each thread has one role, so
 // the roles' memory latencies overlap.  Each block adds its threads'
-// 12-vectors (slot sums and event momenta) in thread order into bpart;
-// k_finish adds the block vectors of each box in block order.
+// 12-vectors (slot sums and event momenta) in thread order into its slot of
+// this step's half of bpart.  The first block of a box also finishes the
+// previous step of the box if that is still pending (adding the previous
+// half's block vectors in block order), writes the next position and marks
+// this step pending; the post-step kernel of the next step (or k_finish,
+// from the host) finishes it.
 template <typename R>
 __global__ void __launch_bounds__(kPostBlock)
-    k_post(const BoxDev* __restrict__ boxes, int nbox, StepPtrs<R> a, double* __restrict__ bpart) {
+    k_post(BoxDev* __restrict__ boxes, int nbox, StepPtrs<R> a, double* __restrict__ bpart,
+           int* __restrict__ pending, double* __restrict__ force, double* __restrict__ hist, int cap,
+           long long* __restrict__ count, int nblk_all) {
   __shared__ double sred[(kPostBlock / 64) * 12];
+  __shared__ double sres[12];
   int b = 0;
   for (int k = 1; k < nbox; k++)
     if ((int)blockIdx.x >= boxes[k].post_blk0) b = k;
-  const BoxDev& B = boxes[b];
+  BoxDev& B = boxes[b];
+  const int par = a.par;
+  const bool first = (int)blockIdx.x == B.post_blk0;
+  if (first && pending[b]) {
+    finish_box<kPostBlock>(B, b, bpart + 12LL * nblk_all * (par ^ 1), force, hist, cap, count, sred, sres);
+    __syncthreads();
+  }
   long long l = (long long)((int)blockIdx.x - B.post_blk0) * kPostBlock + threadIdx.x;
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const double Rc[3] = {B.pos[par][0], B.pos[par][1], B.pos[par][2]};
+  const bool moving = B.present && B.motion == 1;
+  double Rn[3] = {Rc[0], Rc[1], Rc[2]};
+  if (moving) advanced_pos(B, par, Rn);
   if (B.present) {
     const long long nt = (long long)B.ntx * B.nty * B.ntz;
     const long long nst = (nt + kPostSlots - 1) / kPostSlots;
-    const long long ne = B.motion == 1 ? (long long)B.event_ext * B.event_ext * B.event_ext : 0;
+    const long long ne = moving ? (long long)B.event_ext * B.event_ext * B.event_ext : 0;
     const long long ng = (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
     if (l < nst) {
       const long long k0 = l * kPostSlots;
@@ -1303,10 +1345,6 @@ __global__ void __launch_bounds__(kPostBlock)
 #pragma unroll
         for (int c = 0; c < 12; c++) v[c] += t[j][c];
     } else {
-      const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
-      const bool moving = B.motion == 1;
-      double Rn[3] = {Rc[0], Rc[1], Rc[2]};
-      if (moving) advanced_pos(B, Rn);
       l -= nst;
       int x, y, z;
       if (l < ne) {
@@ -1318,40 +1356,24 @@ __global__ void __launch_bounds__(kPostBlock)
       }
     }
   }
-  block_sum<kPostBlock, 12>(v, sred, bpart + 12LL * blockIdx.x);
+  block_sum<kPostBlock, 12>(v, sred, bpart + 12LL * nblk_all * par + 12LL * blockIdx.x);
+  if (first && threadIdx.x == 0) {
+    B.pos[par ^ 1][0] = Rn[0]; B.pos[par ^ 1][1] = Rn[1]; B.pos[par ^ 1][2] = Rn[2];
+    pending[b] = 1;
+  }
 }
 
-// One block per box: the colloid's force and torque (block vectors in
-// block order), the force history and R += v.
+// One block per box: finishes the pending step of buffer parity par.
 __global__ void __launch_bounds__(kFinishBlock)
-    k_finish(BoxDev* __restrict__ boxes, const double* __restrict__ bpart, double* __restrict__ force,
-             double* __restrict__ hist, int cap, long long* __restrict__ count) {
+    k_finish(const BoxDev* __restrict__ boxes, int par, int nblk_all, const double* __restrict__ bpart,
+             int* __restrict__ pending, double* __restrict__ force, double* __restrict__ hist, int cap,
+             long long* __restrict__ count) {
   __shared__ double sred[(kFinishBlock / 64) * 12];
   __shared__ double sres[12];
   const int b = blockIdx.x;
-  BoxDev& B = boxes[b];
-  double w[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = threadIdx.x; k < B.post_nblk; k += kFinishBlock) {
-    const double* p = bpart + 12LL * (B.post_blk0 + k);
-    for (int c = 0; c < 12; c++) w[c] += p[c];
-  }
-  block_sum<kFinishBlock, 12>(w, sred, sres);
-  __syncthreads();
-  if (threadIdx.x < 12) {
-    const double val = B.present ? sres[threadIdx.x] : 0.0;
-    const long long n = count[b];
-    force[12 * b + threadIdx.x] = val;
-    hist[((long long)b * cap + (n % cap)) * 12 + threadIdx.x] = val;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (B.present && B.motion == 1) {
-      double Rn[3];
-      advanced_pos(B, Rn);
-      B.pos[0] = Rn[0]; B.pos[1] = Rn[1]; B.pos[2] = Rn[2];
-    }
-    count[b] += 1;
-  }
+  if (!pending[b]) return;
+  finish_box<kFinishBlock>(boxes[b], b, bpart + 12LL * nblk_all * par, force, hist, cap, count, sred, sres);
+  if (threadIdx.x == 0) pending[b] = 0;
 }
 
 // ---------------------------------------------------------------------
@@ -1368,7 +1390,7 @@ __global__ void __launch_bounds__(256)
   double v[6] = {0, 0, 0, 0, 0, 0};
   if (t < nsite) {
     const int x = (int)(t % B.nx), y = (int)((t / B.nx) % B.ny), z = (int)(t / ((long long)B.nx * B.ny));
-    const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+    const double Rc[3] = {B.pos[a.par][0], B.pos[a.par][1], B.pos[a.par][2]};
     auto solid = [&](int xx, int yy, int zz) {
       return B.present && inside(B, Rc, wrapc(xx, B.nx), wrapc(yy, B.ny), wrapc(zz, B.nz));
     };
@@ -1480,13 +1502,13 @@ __device__ inline double lambda_max(const double q[3][3]) {
 template <typename R>
 __global__ void __launch_bounds__(256)
     k_defects(const BoxDev* __restrict__ boxes, int box, const R* __restrict__ Q, long long NS, double thr,
-              unsigned char* __restrict__ mask, unsigned long long* __restrict__ count) {
+              unsigned char* __restrict__ mask, unsigned long long* __restrict__ count, int par) {
   const BoxDev& B = boxes[box];
   const long long nsite = (long long)B.nx * B.ny * B.nz;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nsite) return;
   const int x = (int)(t % B.nx), y = (int)((t / B.nx) % B.ny), z = (int)(t / ((long long)B.nx * B.ny));
-  const double Rc[3] = {B.pos[0], B.pos[1], B.pos[2]};
+  const double Rc[3] = {B.pos[par][0], B.pos[par][1], B.pos[par][2]};
   unsigned char m = 0;
   if (!(B.present && inside(B, Rc, x, y, z))) {
     double q[3][3];
@@ -1555,20 +1577,23 @@ int march_blocks_per_cu(int tile) {
 }
 
 template <typename R>
-hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, hipStream_t s) {
+hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, int par, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   // small blocks: the few thousand boundary candidates spread over many CUs
-  k_ghost<R><<<(unsigned)((total + 63) / 64), 64, 0, s>>>(boxes, nbox, total, Q, NS);
+  k_ghost<R><<<(unsigned)((total + 63) / 64), 64, 0, s>>>(boxes, nbox, total, Q, NS, par);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, double* force,
-                       double* hist, int cap, long long* count, hipStream_t s) {
-  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, nbox, a, bpart);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_finish<<<(unsigned)nbox, kFinishBlock, 0, s>>>(boxes, bpart, force, hist, cap, count);
+hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
+                       double* force, double* hist, int cap, long long* count, hipStream_t s) {
+  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, nbox, a, bpart, pending, force, hist, cap, count, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(int nbox, int nblk, const BoxDev* boxes, int par, const double* bpart, int* pending,
+                         double* force, double* hist, int cap, long long* count, hipStream_t s) {
+  k_finish<<<(unsigned)nbox, kFinishBlock, 0, s>>>(boxes, par, nblk, bpart, pending, force, hist, cap, count);
   return hipGetLastError();
 }
 
@@ -1581,8 +1606,8 @@ hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const Step
 
 template <typename R>
 hipError_t launch_defects(const BoxDev* boxes, int box, long long nsite, const R* Q, long long NS, double thr,
-                          unsigned char* mask, unsigned long long* count, hipStream_t s) {
-  k_defects<R><<<(unsigned)((nsite + 255) / 256), 256, 0, s>>>(boxes, box, Q, NS, thr, mask, count);
+                          unsigned char* mask, unsigned long long* count, int par, hipStream_t s) {
+  k_defects<R><<<(unsigned)((nsite + 255) / 256), 256, 0, s>>>(boxes, box, Q, NS, thr, mask, count, par);
   return hipGetLastError();
 }
 
@@ -1595,12 +1620,12 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
 #define LC_INST(R)                                                                                        \
   template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const int*, const StepPtrs<R>&,   \
                                      hipStream_t, hipEvent_t, hipEvent_t);                                  \
-  template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, hipStream_t);           \
-  template hipError_t launch_post<R>(int, int, BoxDev*, const StepPtrs<R>&, double*, double*, double*, int,   \
-                                     long long*, hipStream_t);                                                \
+  template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, int, hipStream_t);      \
+  template hipError_t launch_post<R>(int, int, BoxDev*, const StepPtrs<R>&, double*, int*, double*, double*,  \
+                                     int, long long*, hipStream_t);                                          \
   template hipError_t launch_diag<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*, hipStream_t); \
   template hipError_t launch_defects<R>(const BoxDev*, int, long long, const R*, long long, double,         \
-                                        unsigned char*, unsigned long long*, hipStream_t);                  \
+                                        unsigned char*, unsigned long long*, int, hipStream_t);             \
   template hipError_t launch_fill<R>(R*, long long, double, hipStream_t);
 LC_INST(float)
 LC_INST(double)

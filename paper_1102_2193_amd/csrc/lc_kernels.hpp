@@ -21,6 +21,7 @@ struct StepPtrs {
                       // one slot per 3D tile or per (column block, z group)
   long long nslot;
   int* flag;          // set to 1 on a non-finite value or |u| >= 0.3
+  int par;            // buffer parity of the step (slot of BoxDev::pos)
 };
 
 // Block shapes of the fused kernel, per precision: (id, TX, TY, TZ, kind).
@@ -75,22 +76,30 @@ hipError_t launch_step(int tile, int nblk, const BoxDev* boxes, const int2* tile
 // shape is not a marching one).
 int march_blocks_per_cu(int tile);
 // Anchoring pass: ghost Q at the boundary solid nodes of the Q buffer
-// (before the first step and after any change made from the host).
+// (before the first step and after any change made from the host), for the
+// colloids at pos[par].
 template <typename R>
-hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, hipStream_t s);
-// After the fused kernel: moving-boundary events, the next step's ghost Q
-// and per-block sums of the fused kernel's colloid slots and the event
-// momenta (nblk blocks), then one block per box adding them in block order:
-// force, force history, R += v.
+hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, int par, hipStream_t s);
+// After the fused kernel: moving-boundary events, the next step's ghost Q,
+// per-block sums of the fused kernel's colloid slots and the event momenta
+// (nblk blocks, 12 doubles each, into bpart + 12 * nblk * a.par) and the
+// next position pos[a.par ^ 1].  The first block of each box first finishes
+// the previous step if pending[box] is set (its block sums are in the other
+// half of bpart): force, force history, count; then marks this step
+// pending.
 template <typename R>
-hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, double* force,
-                       double* hist, int cap, long long* count, hipStream_t s);
+hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
+                       double* force, double* hist, int cap, long long* count, hipStream_t s);
+// Finish a pending step of buffer parity par from the host (one block per
+// box; boxes with pending[box] == 0 are left alone).
+hipError_t launch_finish(int nbox, int nblk, const BoxDev* boxes, int par, const double* bpart, int* pending,
+                         double* force, double* hist, int cap, long long* count, hipStream_t s);
 template <typename R>
 hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const StepPtrs<R>& a, double* out,
                        hipStream_t s);
 template <typename R>
 hipError_t launch_defects(const BoxDev* boxes, int box, long long nsite, const R* Q, long long NS, double thr,
-                          unsigned char* mask, unsigned long long* count, hipStream_t s);
+                          unsigned char* mask, unsigned long long* count, int par, hipStream_t s);
 template <typename R>
 hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s);
 

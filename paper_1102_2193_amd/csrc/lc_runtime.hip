@@ -62,8 +62,10 @@ struct lc_ctx {
   double* dpart = nullptr;      // 12 per tile
   long long ghost_total = 0;
   int npost = 0;                // blocks of the post-step kernel
-  double* dbpart = nullptr;     // 12 per post-step block
+  double* dbpart = nullptr;     // 12 per post-step block, one half per buffer parity
   size_t dbpart_cap = 0;
+  int* dpending = nullptr;      // per box: a step whose force sums are not yet added
+  bool maybe_pending = false;   // a step ran since the last finish from the host
   bool ghost_fresh = false;     // ghost Q of buffer cur matches the colloids
   double* dforce = nullptr;     // 12 per box
   double* dhist = nullptr;      // nbox * kHistCap * 12
@@ -116,7 +118,7 @@ int pull_boxes(lc_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->hb.data(), c->dbox, sizeof(BoxDev) * c->nbox, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int b = 0; b < c->nbox; b++)
-    for (int a = 0; a < 3; a++) c->col[b].pos[a] = c->hb[b].pos[a];
+    for (int a = 0; a < 3; a++) c->col[b].pos[a] = c->hb[b].pos[c->cur][a];
   return LC_OK;
 }
 
@@ -310,12 +312,26 @@ int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& 
 // as much per plane).  Those short items go first in the launch, spread over
 // the dies, so that the hardware's in-order dispatch starts them at once and
 // fills the remaining time with the long items.
+// Finish the last step from the host if its colloid sums are still pending
+// (the next step's post-step kernel would otherwise do it).
+int flush(lc_ctx* c) {
+  if (!c->maybe_pending) return LC_OK;
+  HIPCHK(c, lc::launch_finish(c->nbox, c->npost, c->dbox, c->cur ^ 1, c->dbpart, c->dpending, c->dforce, c->dhist,
+                              kHistCap, c->dcount, c->stream));
+  c->maybe_pending = false;
+  return LC_OK;
+}
+
 // The marching kernel addresses each population array through one buffer
 // resource with 32-bit component offsets: 19 x sites x 4 bytes must stay
 // below 4 GiB.
 bool march_fits(const lc_ctx* c) { return 19.0 * 4.0 * (double)c->nsites < 4294967296.0; }
 
 int layout(lc_ctx* c) {
+  {
+    int rc = flush(c);   // the block sums of a pending step follow the old layout
+    if (rc != LC_OK) return rc;
+  }
   const TileShape& T = tile_shape(c, c->tile);
   long long tb = 0, gb = 0;
   int pblk = 0;
@@ -348,7 +364,7 @@ int layout(lc_ctx* c) {
     B.motion = k.motion;
     B.anchoring = k.anchoring;
     for (int a = 0; a < 3; a++) {
-      B.pos[a] = k.pos[a];
+      B.pos[0][a] = B.pos[1][a] = k.pos[a];
       B.vel[a] = k.vel[a];
       B.omega[a] = k.omega[a];
     }
@@ -415,10 +431,10 @@ int layout(lc_ctx* c) {
   }
   HIPCHK(c, hipMalloc(&c->dpart, sizeof(double) * 12 * std::max(1, c->ntile)));
   HIPCHK(c, hipMemsetAsync(c->dpart, 0, sizeof(double) * 12 * std::max(1, c->ntile), c->stream));
-  if ((size_t)pblk * 12 > c->dbpart_cap) {
+  if ((size_t)pblk * 24 > c->dbpart_cap) {
     if (c->dbpart) hipFree(c->dbpart);
     c->dbpart = nullptr;
-    c->dbpart_cap = std::max<size_t>(12, (size_t)pblk * 12);
+    c->dbpart_cap = std::max<size_t>(24, (size_t)pblk * 24);
     HIPCHK(c, hipMalloc(&c->dbpart, sizeof(double) * c->dbpart_cap));
   }
   HIPCHK(c, hipMemcpyAsync(c->dtiles, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice, c->stream));
@@ -441,6 +457,7 @@ lc::StepPtrs<R> ptrs(lc_ctx* c, int from) {
   a.part = c->dpart;
   a.nslot = std::max(1, c->ntile);
   a.flag = c->dflag;
+  a.par = from;
   return a;
 }
 
@@ -453,8 +470,9 @@ hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t
   lc::StepPtrs<R> a = ptrs<R>(c, from);
   e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, c->doffs, a, c->stream, k0, k1);
   if (e != hipSuccess) return e;
-  return lc::launch_post<R>(c->npost, c->nbox, c->dbox, a, c->dbpart, c->dforce, c->dhist, kHistCap, c->dcount,
-                            c->stream);
+  c->maybe_pending = true;
+  return lc::launch_post<R>(c->npost, c->nbox, c->dbox, a, c->dbpart, c->dpending, c->dforce, c->dhist, kHistCap,
+                            c->dcount, c->stream);
 }
 
 hipError_t enqueue(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t k1 = nullptr) {
@@ -468,9 +486,9 @@ int ghost_pass(lc_ctx* c) {
   if (c->any_colloid) {
     hipError_t e = c->prec == LC_FP32
                        ? lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites,
-                                                 c->stream)
+                                                 c->cur, c->stream)
                        : lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites,
-                                                  c->stream);
+                                                  c->cur, c->stream);
     HIPCHK(c, e);
   }
   c->ghost_fresh = true;
@@ -670,11 +688,13 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
       hipMalloc(&c->dforce, sizeof(double) * 12 * nbox) != hipSuccess ||
       hipMalloc(&c->dhist, sizeof(double) * 12 * (size_t)kHistCap * nbox) != hipSuccess ||
       hipMalloc(&c->dcount, sizeof(long long) * nbox) != hipSuccess ||
+      hipMalloc(&c->dpending, sizeof(int) * nbox) != hipSuccess ||
       hipMalloc(&c->dflag, sizeof(int)) != hipSuccess)
     return bail(LC_ENOMEM, "device allocation failed");
   hipMemsetAsync(c->dforce, 0, sizeof(double) * 12 * nbox, c->stream);
   hipMemsetAsync(c->dhist, 0, sizeof(double) * 12 * (size_t)kHistCap * nbox, c->stream);
   hipMemsetAsync(c->dcount, 0, sizeof(long long) * nbox, c->stream);
+  hipMemsetAsync(c->dpending, 0, sizeof(int) * nbox, c->stream);
   hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream);
   for (int k = 0; k < 2; k++) {
     hipMemsetAsync(c->Q[k], 0, nq, c->stream);
@@ -718,8 +738,8 @@ void lc_destroy(lc_ctx* c) {
       if (c->Q[k]) hipFree(c->Q[k]);
       if (c->u[k]) hipFree(c->u[k]);
     }
-  void* bufs[] = {c->dbox,  c->dtiles, c->doffs, c->dpart, c->dbpart,
-                  c->dforce, c->dhist,  c->dcount, c->dflag, c->ddiag};
+  void* bufs[] = {c->dbox,  c->dtiles, c->doffs, c->dpart,  c->dbpart, c->dpending,
+                  c->dforce, c->dhist,  c->dcount, c->dflag,  c->ddiag};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -863,6 +883,7 @@ int lc_get_state(lc_ctx* c, void* buf, size_t bytes) {
   if (!buf || bytes < state_bytes(c)) return fail(c, LC_EINVAL, "state buffer is NULL or smaller than lc_state_bytes");
   int rc = check_flag(c);
   if (rc) return rc;
+  if ((rc = flush(c)) != LC_OK) return rc;
   if ((rc = pull_boxes(c)) != LC_OK) return rc;
   char* p = (char*)buf;
   StateHeader h;
@@ -936,7 +957,10 @@ int lc_set_state(lc_ctx* c, const void* buf, size_t bytes) {
   size_t sz[3];
   lc_buffer_bytes(c, sz);
   const size_t nforce = sizeof(double) * 12 * c->nbox, nhist = sizeof(double) * 12 * (size_t)kHistCap * c->nbox;
+  int frc = flush(c);   // a pending step of this context must not land in the restored history
+  if (frc != LC_OK) return frc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemsetAsync(c->dpending, 0, sizeof(int) * c->nbox, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->dcount, cnt.data(), sizeof(long long) * c->nbox, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->dforce, p, nforce, hipMemcpyHostToDevice, c->stream));
   p += nforce;
@@ -996,6 +1020,7 @@ int lc_get_force(lc_ctx* c, int box, double out[12]) {
   int rc = check_box(c, box);
   if (rc) return rc;
   if (!out) return fail(c, LC_EINVAL, "out is NULL");
+  if ((rc = flush(c)) != LC_OK) return rc;
   HIPCHK(c, hipMemcpyAsync(out, c->dforce + 12 * box, sizeof(double) * 12, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LC_OK;
@@ -1008,6 +1033,7 @@ int lc_get_force_history(lc_ctx* c, int box, int nsteps, double* out) {
   if (rc) return rc;
   if (!out || nsteps < 0 || nsteps > kHistCap || nsteps > c->nstep)
     return fail(c, LC_EINVAL, "nsteps exceeds the steps taken or the history capacity");
+  if ((rc = flush(c)) != LC_OK) return rc;
   long long cnt = 0;
   HIPCHK(c, hipMemcpyAsync(&cnt, c->dcount + box, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
   std::vector<double> h((size_t)kHistCap * 12);
@@ -1037,11 +1063,13 @@ int lc_get_diag(lc_ctx* c, int box, lc_diag* out) {
   hipError_t e;
   if (c->prec == LC_FP32) {
     lc::StepPtrs<float> a = ptrs<float>(c, c->cur);
-    if (c->any_colloid) lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->stream);
+    if (c->any_colloid)
+      lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->cur, c->stream);
     e = lc::launch_diag<float>(c->dbox, box, n, a, c->ddiag, c->stream);
   } else {
     lc::StepPtrs<double> a = ptrs<double>(c, c->cur);
-    if (c->any_colloid) lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->stream);
+    if (c->any_colloid)
+      lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->cur, c->stream);
     e = lc::launch_diag<double>(c->dbox, box, n, a, c->ddiag, c->stream);
   }
   HIPCHK(c, e);
@@ -1073,9 +1101,9 @@ int lc_defects(lc_ctx* c, int box, double threshold, unsigned char* mask, long* 
   hipMemsetAsync(dc, 0, sizeof(unsigned long long), c->stream);
   hipError_t e = c->prec == LC_FP32
                      ? lc::launch_defects<float>(c->dbox, box, n, (const float*)c->Q[c->cur] + 0, c->nsites,
-                                                 threshold, dm + 0, dc, c->stream)
+                                                 threshold, dm + 0, dc, c->cur, c->stream)
                      : lc::launch_defects<double>(c->dbox, box, n, (const double*)c->Q[c->cur], c->nsites,
-                                                  threshold, dm, dc, c->stream);
+                                                  threshold, dm, dc, c->cur, c->stream);
   unsigned long long cnt = 0;
   if (e == hipSuccess) {
     if (mask) e = hipMemcpyAsync(mask, dm, n, hipMemcpyDeviceToHost, c->stream);
