@@ -1297,11 +1297,11 @@ __device__ inline void finish_box(const BoxDev& B, int b, const double* __restri
 // candidate, then one per ghost candidate.  Each thread has one role, so
 // the roles' memory latencies overlap.  Each block adds its threads'
 // 12-vectors (slot sums and event momenta) in thread order into its slot of
-// this step's half of bpart.  The first block of a box also finishes the
-// previous step of the box if that is still pending (adding the previous
-// half's block vectors in block order), writes the next position and marks
-// this step pending; the post-step kernel of the next step (or k_finish,
-// from the host) finishes it.
+// this step's half of bpart.  The last block of a box has no such role: it
+// finishes the previous step of the box if that is still pending (adding
+// the previous half's block vectors in block order) while the others work,
+// writes the next position and marks this step pending; the post-step
+// kernel of the next step (or k_finish, from the host) finishes it.
 template <typename R>
 __global__ void __launch_bounds__(kPostBlock)
     k_post(BoxDev* __restrict__ boxes, int nbox, StepPtrs<R> a, double* __restrict__ bpart,
@@ -1314,8 +1314,8 @@ __global__ void __launch_bounds__(kPostBlock)
     if ((int)blockIdx.x >= boxes[k].post_blk0) b = k;
   BoxDev& B = boxes[b];
   const int par = a.par;
-  const bool first = (int)blockIdx.x == B.post_blk0;
-  if (first && pending[b]) {
+  const bool finisher = (int)blockIdx.x == B.post_blk0 + B.post_nblk - 1;
+  if (finisher && pending[b]) {
     finish_box<kPostBlock>(B, b, bpart + 12LL * nblk_all * (par ^ 1), force, hist, cap, count, sred, sres);
     __syncthreads();
   }
@@ -1357,7 +1357,7 @@ __global__ void __launch_bounds__(kPostBlock)
     }
   }
   block_sum<kPostBlock, 12>(v, sred, bpart + 12LL * nblk_all * par + 12LL * blockIdx.x);
-  if (first && threadIdx.x == 0) {
+  if (finisher && threadIdx.x == 0) {
     B.pos[par ^ 1][0] = Rn[0]; B.pos[par ^ 1][1] = Rn[1]; B.pos[par ^ 1][2] = Rn[2];
     pending[b] = 1;
   }

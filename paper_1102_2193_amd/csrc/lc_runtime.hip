@@ -378,13 +378,14 @@ int layout(lc_ctx* c) {
     const bool moving = k.present && k.motion == LC_PRESCRIBED;
     B.event_ext = moving ? 2 * ca + 5 : 0;
     // post-step threads: slot sums (kPostSlots slots each), one per event
-    // candidate, one per ghost candidate; at least one block per box
+    // candidate, one per ghost candidate, then one more block that only
+    // finishes the previous step
     const long long nt = (long long)B.ntx * B.nty * B.ntz;
     const long long nst = k.present ? (nt + lc::kPostSlots - 1) / lc::kPostSlots : 0;
     const long long ne = (long long)B.event_ext * B.event_ext * B.event_ext;
     const long long ng = (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
     B.post_blk0 = pblk;
-    B.post_nblk = (int)std::max(1LL, (nst + ne + ng + lc::kPostBlock - 1) / lc::kPostBlock);
+    B.post_nblk = (int)((nst + ne + ng + lc::kPostBlock - 1) / lc::kPostBlock) + 1;
     if ((long long)pblk + B.post_nblk > (1LL << 30)) return fail(c, LC_EINVAL, "too many post-step blocks");
     pblk += B.post_nblk;
     c->any_colloid |= (bool)k.present;

@@ -173,3 +173,28 @@ def test_network_weight_file_round_trip(tmp_path):
         b.load(str(tmp_path / "missing.lcnn"))
     a.close()
     b.close()
+
+
+def test_reading_forces_between_steps_changes_nothing():
+    # The colloid sums of a step are added by the next step's post-step
+    # kernel, or from the host when a getter needs them; either way every
+    # later value is the same.
+    from paper_1102_2193_amd import lc
+    say("case: force read between steps vs none, 24^3 fp32, moving colloid, 7 + 25 steps")
+    L = 24
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=12)
+    out = []
+    for read in (False, True):
+        ctx = lc.Context([dict(nx=L, precision="fp32", **NEM)])
+        ctx.set_colloid(0, (11.6, 12.2, 12.9), 4.0, anchoring="normal", W=0.01, vel=(0.03, -0.01, 0.02),
+                        motion=lc.PRESCRIBED)
+        ctx.set_Q(0, Q0)
+        ctx.step(7)
+        if read:
+            F7 = ctx.force(0)
+            np.testing.assert_array_equal(F7, ctx.force_history(0, 7)[-1])
+            ctx.force(0)   # a second read adds nothing
+        ctx.step(25)
+        out.append(snapshot(ctx, 1, 32))
+        ctx.close()
+    assert_same(out[0], out[1])
