@@ -103,6 +103,28 @@ def profiled_traffic(workload, tile):
     return None, None
 
 
+def copy_ceiling(nbytes, stream, reps=10):
+    """Same-box stream-copy ceiling: GB/s of a device-to-device copy that
+    reads and writes nbytes in all (half each), timed with events."""
+    import torch
+    half = int(nbytes) // 2
+    with torch.cuda.stream(stream):
+        src = torch.ones(half, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        t1.record(stream)
+    torch.cuda.synchronize()
+    gbps = 2 * half * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def cpu_baseline(wl, target_s):
     """FP64 oracle on the first steps of the same workload (box 0)."""
     from oracle import lco
@@ -237,6 +259,7 @@ def main():
     bpl = BYTES_PER_LU[wl["prec"]]
     achieved = bpl * sites / (tk["kernel_ms"] * 1e-3) / 1e9
     traffic, traffic_src = profiled_traffic(wl["config"]["workload"], tile)
+    copy_gbps = copy_ceiling(bpl * sites, ctx.stream)
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
@@ -247,7 +270,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic), "traffic_source": traffic_src,
                      "kernel": "fused step kernel", "kernel_ms": round(tk["kernel_ms"], 5),
-                     "bytes_per_launch": bpl * sites},
+                     "bytes_per_launch": bpl * sites,
+                     "copy_ceiling_gbps": round(copy_gbps, 1)},
         "wall_s": round(wall, 3),
     }
     if args.graph:
