@@ -18,8 +18,10 @@
  *   5. LB collision with the force, push streaming, bounce-back on links
  *      with the moving-wall correction; link momentum to the colloid
  *      (Sec. 2.2, BBL)
- *   6. moving-boundary events for a colloid with prescribed velocity
- *      (Sec. 2.2, last paragraph)
+ *   6. for a freely moving colloid: velocity and position from the summed
+ *      force (molecular-dynamics-like step, Sec. 2.2; reading in lco.h)
+ *   7. moving-boundary events for a moving colloid (Sec. 2.2, last
+ *      paragraph)
  */
 #include "lco.h"
 
@@ -346,7 +348,7 @@ int lco_set_colloid(lco_sim* s, const lco_colloid* c) {
     if (s->p.nz < Lmin) Lmin = s->p.nz;
     if (!(c->a0 > 1.0) || !(2.0 * c->a0 + 4.0 <= Lmin)) return LCO_EINVAL;
     if (c->anchoring < LCO_ANCHOR_NONE || c->anchoring > LCO_ANCHOR_PLANAR) return LCO_EINVAL;
-    if (c->motion != LCO_FIXED && c->motion != LCO_PRESCRIBED) return LCO_EINVAL;
+    if (c->motion != LCO_FIXED && c->motion != LCO_PRESCRIBED && c->motion != LCO_FREE) return LCO_EINVAL;
     if (!(c->W >= 0.0)) return LCO_EINVAL;
     if (c->anchoring != LCO_ANCHOR_NONE && !(s->p.K + c->W > 0.0)) return LCO_EINVAL;
   }
@@ -841,8 +843,9 @@ static void lb_stream(lco_sim* s, double Fb[3], double Tb[3]) {
   }
 }
 
-/* Moving-boundary events for a colloid with prescribed velocity (Sec. 2.2):
- * the centre advances by v, nodes are reclassified, a node that becomes
+/* Moving-boundary events for a moving colloid (Sec. 2.2): the centre
+ * advances by v (prescribed, or the velocity just updated), nodes are
+ * reclassified, a node that becomes
  * fluid receives equilibrium populations at rho0 and the local rigid-body
  * velocity and, for Q, the mean over its face neighbours that held fluid
  * both before and after the move (zero if there is none); a node that
@@ -850,7 +853,7 @@ static void lb_stream(lco_sim* s, double Fb[3], double Tb[3]) {
  * to the colloid (added to Fe, Te). */
 static void events(lco_sim* s, double* Qn, double Fe[3], double Te[3]) {
   for (int a = 0; a < 3; a++) Fe[a] = Te[a] = 0.0;
-  if (!s->c.present || s->c.motion != LCO_PRESCRIBED) return;
+  if (!s->c.present || s->c.motion == LCO_FIXED) return;
   long N = s->N;
   int L[3] = {s->p.nx, s->p.ny, s->p.nz};
   double Rn[3];
@@ -931,7 +934,24 @@ static void step_once(lco_sim* s) {
     lb_collide(s);
     lb_stream(s, Fb, Tb);
   }
+  const int free_motion = s->c.present && s->c.motion == LCO_FREE;
+  double M = 0.0, I = 0.0;
+  if (free_motion) {
+    const double rc = s->c.rho_c > 0.0 ? s->c.rho_c : s->p.rho0;
+    const double a = s->c.a0;
+    M = 4.0 / 3.0 * acos(-1.0) * a * a * a * rc;
+    I = 0.4 * M * a * a;
+    for (int k = 0; k < 3; k++) {
+      s->c.vel[k] += (Fb[k] + Fs[k] + s->c.fext[k]) / M;
+      s->c.omega[k] += (Tb[k] + Ts[k]) / I;
+    }
+  }
   events(s, s->Qn, Fe, Te);
+  if (free_motion)
+    for (int k = 0; k < 3; k++) {
+      s->c.vel[k] += Fe[k] / M;
+      s->c.omega[k] += Te[k] / I;
+    }
   double* t = s->Q; s->Q = s->Qn; s->Qn = t;
   if (s->p.hydro) { t = s->f; s->f = s->fn; s->fn = t; }
   for (int a = 0; a < 3; a++) {

@@ -31,7 +31,7 @@ extern "C" {
 
 enum { LCO_OK = 0, LCO_EINVAL = 1, LCO_ENOMEM = 2, LCO_ESTATE = 5 };
 enum { LCO_ANCHOR_NONE = 0, LCO_ANCHOR_NORMAL = 1, LCO_ANCHOR_PLANAR = 2 };
-enum { LCO_FIXED = 0, LCO_PRESCRIBED = 1 };
+enum { LCO_FIXED = 0, LCO_PRESCRIBED = 1, LCO_FREE = 2 };
 
 typedef struct lco_params {
   int nx, ny, nz;
@@ -44,7 +44,8 @@ typedef struct lco_params {
 
 typedef struct lco_colloid {
   int present;            /* 0: no colloid in the box */
-  int motion;             /* LCO_FIXED or LCO_PRESCRIBED (R += v every step) */
+  int motion;             /* LCO_FIXED, LCO_PRESCRIBED (R += v every step) or
+                             LCO_FREE (v and omega follow the force, below) */
   int anchoring;          /* LCO_ANCHOR_NONE / NORMAL / PLANAR (Sec. 2.2) */
   int pad_;
   double pos[3];          /* centre R */
@@ -53,6 +54,16 @@ typedef struct lco_colloid {
   double omega[3];        /* angular velocity */
   double S0;              /* surface order of Eq. for Q^0 (Sec. 2.2) */
   double W;               /* anchoring strength; +inf = fixed Q^0 */
+  /* LCO_FREE only.  The paper updates the particle velocity from the summed
+   * link and stress force, and the position from the velocity, in a
+   * molecular-dynamics-like step without giving it; the reading taken is
+   * explicit Euler at the end of each step:
+   *   V += (F + fext)/M, omega += T/I with M = 4/3 pi a0^3 rho_c and
+   *   I = 2/5 M a0^2, then R += V (the new V), then the moving-boundary
+   *   events of the move (with the new V, omega), whose momentum is added
+   *   to V and omega as well (F, T: the step's link and stress sums). */
+  double fext[3];         /* constant external force on the colloid */
+  double rho_c;           /* colloid density; <= 0 means rho0 */
 } lco_colloid;
 
 typedef struct lco_sim lco_sim;

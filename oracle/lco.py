@@ -15,7 +15,7 @@ import numpy as np
 from . import build as _build
 
 ANCHOR_NONE, ANCHOR_NORMAL, ANCHOR_PLANAR = 0, 1, 2
-FIXED, PRESCRIBED = 0, 1
+FIXED, PRESCRIBED, FREE = 0, 1, 2
 
 _lib = None
 
@@ -34,7 +34,8 @@ class Colloid(ctypes.Structure):
                 ("anchoring", ctypes.c_int), ("pad_", ctypes.c_int),
                 ("pos", ctypes.c_double * 3), ("a0", ctypes.c_double),
                 ("vel", ctypes.c_double * 3), ("omega", ctypes.c_double * 3),
-                ("S0", ctypes.c_double), ("W", ctypes.c_double)]
+                ("S0", ctypes.c_double), ("W", ctypes.c_double),
+                ("fext", ctypes.c_double * 3), ("rho_c", ctypes.c_double)]
 
 
 def lib():
@@ -87,12 +88,12 @@ def make_params(nx, ny, nz, hydro=1, tau=1.0, rho0=1.0, A0=0.01, gamma=3.0, K=0.
 
 
 def make_colloid(pos, a0, anchoring=ANCHOR_NORMAL, W=math.inf, S0=0.5, vel=(0, 0, 0),
-                 omega=(0, 0, 0), motion=FIXED, present=1):
+                 omega=(0, 0, 0), motion=FIXED, present=1, fext=(0, 0, 0), rho_c=0.0):
     c = Colloid()
     c.present, c.motion, c.anchoring = present, motion, anchoring
     for a in range(3):
-        c.pos[a], c.vel[a], c.omega[a] = pos[a], vel[a], omega[a]
-    c.a0, c.S0, c.W = a0, S0, W
+        c.pos[a], c.vel[a], c.omega[a], c.fext[a] = pos[a], vel[a], omega[a], fext[a]
+    c.a0, c.S0, c.W, c.rho_c = a0, S0, W, rho_c
     return c
 
 

@@ -477,6 +477,53 @@ def test_prescribed_motion_momentum_and_events(oracle):
     assert np.all(np.isfinite(s.get_Q()))
 
 
+def test_free_motion_closed_form_without_fluid(oracle):
+    # Fluid off, Q = 0, no anchoring: no hydrodynamic force, so the free
+    # update gives V^n = V^0 + n F/M and R^n = R^0 + n V^0 + F/M n(n+1)/2
+    # (R moves with the velocity just updated), M = 4/3 pi a^3 rho_c.
+    L, a, rho_c, n = 16, 3.0, 1.5, 40
+    fext = np.array([2e-3, -1e-3, 5e-4])
+    v0 = np.array([1e-3, 0.0, -2e-3])
+    s = oracle.Sim(L, **dict(NEM, hydro=0))
+    s.set_colloid((8.2, 7.9, 8.4), a, anchoring=oracle.ANCHOR_NONE, motion=oracle.FREE, vel=tuple(v0),
+                  fext=tuple(fext), rho_c=rho_c)
+    s.set_Q(np.zeros((5, L, L, L)))
+    acc = fext / (4.0 / 3.0 * math.pi * a ** 3 * rho_c)
+    for k in range(1, n + 1):
+        s.step(1)
+        c = s.get_colloid()
+        np.testing.assert_allclose(np.array(c.vel), v0 + k * acc, rtol=1e-12, atol=1e-17)
+        R = (np.array([8.2, 7.9, 8.4]) + k * v0 + acc * k * (k + 1) / 2) % L
+        np.testing.assert_allclose(np.array(c.pos), R, atol=1e-12)
+        assert np.all(np.array(c.omega) == 0.0)
+        assert np.all(s.force() == 0.0)
+    assert np.all(s.get_Q() == 0.0)
+
+
+def test_free_motion_conserves_total_momentum(oracle):
+    # Fluid on, no external or body force: fluid momentum (pre-collision
+    # populations) plus M V is constant; link, stress-face and event
+    # exchanges all balance.
+    L, a = 16, 3.5
+    s = oracle.Sim(L, **NEM)
+    s.set_colloid((8.3, 7.6, 8.1), a, anchoring=oracle.ANCHOR_PLANAR, W=0.01, motion=oracle.FREE,
+                  vel=(0.06, 0.0, -0.03))
+    s.set_Q(inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, 21, noise=0.02))
+    M = 4.0 / 3.0 * math.pi * a ** 3 * NEM.get("rho0", 1.0)
+    def total():
+        return s.diag()["momentum"] + M * np.array(s.get_colloid().vel)
+    p0 = total()
+    solid0, moved = s.solid(), 0
+    for _ in range(20):
+        s.step(1)
+        np.testing.assert_allclose(total(), p0, atol=1e-11)
+        sol = s.solid()
+        moved += int(np.sum(sol != solid0))
+        solid0 = sol
+    assert moved > 0                                        # events happened
+    assert np.linalg.norm(np.array(s.get_colloid().vel) - [0.06, 0.0, -0.03]) > 1e-4   # and the fluid acted
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("L,a", [(16, 3.0), (20, 4.5)])
 def test_stokes_drag_isotropic_limit(oracle, L, a):
