@@ -51,7 +51,7 @@ typedef enum lc_status {
 
 enum { LC_FP32 = 0, LC_FP64 = 1 };
 enum { LC_ANCHOR_NONE = 0, LC_ANCHOR_NORMAL = 1, LC_ANCHOR_PLANAR = 2 };
-enum { LC_FIXED = 0, LC_PRESCRIBED = 1 };
+enum { LC_FIXED = 0, LC_PRESCRIBED = 1, LC_FREE = 2 };
 
 /* Per-box parameters.  Material constants follow Eq. (1), Eq. (2) and
  * Eq. (4): A0, gamma (bulk), K (one elastic constant), q0 = 2 pi / pitch,
@@ -72,7 +72,13 @@ typedef struct lc_params {
 
 /* One spherical colloid (Sec. 2.2): nodes with |x - R|^2 < a0^2 are solid.
  * motion LC_FIXED keeps R; LC_PRESCRIBED advances R by vel every step with
- * the moving-boundary events of Sec. 2.2.  Anchoring sets Q at boundary
+ * the moving-boundary events of Sec. 2.2; LC_FREE lets vel and omega follow
+ * the force (the paper's molecular-dynamics-like step, which it does not
+ * spell out; the reading taken is explicit Euler at the end of each step:
+ * vel += (F_bbl + F_stress + fext)/M, omega += (T_bbl + T_stress)/I with
+ * M = 4/3 pi a0^3 rho_c and I = 2/5 M a0^2, then R += vel (the new vel),
+ * then the events of that move, whose momentum is added to vel and omega
+ * too).  Anchoring sets Q at boundary
  * solid nodes to Q^0 = S0 (n0 n0 - I/3) with n0 the surface normal (NORMAL)
  * or the projection of the neighbouring director on the tangent plane
  * (PLANAR); W = +INFINITY is the paper's fixed value, a finite W blends
@@ -89,6 +95,8 @@ typedef struct lc_colloid {
   double omega[3];
   double S0;
   double W;
+  double fext[3];         /* LC_FREE: constant external force on the colloid */
+  double rho_c;           /* LC_FREE: colloid density (<= 0: the fluid's rho0) */
 } lc_colloid;
 
 /* Diagnostics of one box: discrete free energy (bulk + chiral terms at

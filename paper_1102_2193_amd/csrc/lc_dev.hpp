@@ -28,6 +28,7 @@ struct BoxDev {
   // post-step kernel of a step writes the other slot
   double pos[2][3];
   double a0, vel[3], omega[3], S0, W;
+  double fext[3], mass, inertia;          // free motion (motion == 2)
 };
 
 // D3Q19: rest, 6 axis links, 12 diagonal links; opposite links adjacent.

@@ -1271,9 +1271,9 @@ __device__ inline void event_site(const BoxDev& B, const double Rc[3], const dou
 // Force, torque and history entry of one finished step of box b: the block
 // vectors of its post-step kernel added in block order (nt threads).
 template <int NT>
-__device__ inline void finish_box(const BoxDev& B, int b, const double* __restrict__ bpart, double* __restrict__ force,
-                                  double* __restrict__ hist, int cap, long long* __restrict__ count,
-                                  double* sred, double* sres) {
+__device__ inline void finish_box(BoxDev& B, int b, const double* __restrict__ bpart, const double* __restrict__ fsum,
+                                  double* __restrict__ force, double* __restrict__ hist, int cap,
+                                  long long* __restrict__ count, double* sred, double* sres) {
   double w[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int k = threadIdx.x; k < B.post_nblk; k += NT) {
     const double* p = bpart + 12LL * (B.post_blk0 + k);
@@ -1281,14 +1281,57 @@ __device__ inline void finish_box(const BoxDev& B, int b, const double* __restri
   }
   block_sum<NT, 12>(w, sred, sres);
   __syncthreads();
+  // a free colloid: the link and stress sums were added before the move
+  // (k_free); the block vectors hold the events' momentum, which also goes
+  // to its velocity
+  const bool free_motion = B.present && B.motion == 2;
   if (threadIdx.x < 12) {
-    const double val = B.present ? sres[threadIdx.x] : 0.0;
+    const double val = !B.present ? 0.0 : (free_motion ? fsum[12 * b + threadIdx.x] + sres[threadIdx.x] : sres[threadIdx.x]);
     const long long n = count[b];
     force[12 * b + threadIdx.x] = val;
     hist[((long long)b * cap + (n % cap)) * 12 + threadIdx.x] = val;
   }
   __syncthreads();
-  if (threadIdx.x == 0) count[b] += 1;
+  if (threadIdx.x == 0) {
+    if (free_motion)
+      for (int k = 0; k < 3; k++) {
+        B.vel[k] += sres[k] / B.mass;
+        B.omega[k] += sres[6 + k] / B.inertia;
+      }
+    count[b] += 1;
+  }
+}
+
+// Free colloids, one block per box, after the fused kernel: the step's link
+// and stress sums (all slots, fixed order) into fsum, then
+// vel += (F_bbl + F_stress + fext)/M, omega += (T_bbl + T_stress)/I and the
+// next position pos[par ^ 1] = pos[par] + vel.
+__global__ void __launch_bounds__(kFinishBlock)
+    k_free(BoxDev* __restrict__ boxes, const double* __restrict__ part, long long nslot, int par,
+           double* __restrict__ fsum) {
+  __shared__ double sred[(kFinishBlock / 64) * 12];
+  __shared__ double sres[12];
+  const int b = blockIdx.x;
+  BoxDev& B = boxes[b];
+  if (!(B.present && B.motion == 2)) return;
+  const long long nt = (long long)B.ntx * B.nty * B.ntz;
+  double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long k = threadIdx.x; k < nt; k += kFinishBlock) {
+    const double* p = part + B.tile_base + k;
+    for (int c = 0; c < 12; c++) v[c] += p[c * nslot];
+  }
+  block_sum<kFinishBlock, 12>(v, sred, sres);
+  __syncthreads();
+  if (threadIdx.x < 12) fsum[12 * b + threadIdx.x] = sres[threadIdx.x];
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; k++) {
+      B.vel[k] += (sres[k] + sres[3 + k] + B.fext[k]) / B.mass;
+      B.omega[k] += (sres[6 + k] + sres[9 + k]) / B.inertia;
+    }
+    double Rn[3];
+    advanced_pos(B, par, Rn);
+    B.pos[par ^ 1][0] = Rn[0]; B.pos[par ^ 1][1] = Rn[1]; B.pos[par ^ 1][2] = Rn[2];
+  }
 }
 
 // Threads of box b, in three ranges: fused-kernel slot sums (kPostSlots
@@ -1305,8 +1348,8 @@ __device__ inline void finish_box(const BoxDev& B, int b, const double* __restri
 template <typename R>
 __global__ void __launch_bounds__(kPostBlock)
     k_post(BoxDev* __restrict__ boxes, int nbox, StepPtrs<R> a, double* __restrict__ bpart,
-           int* __restrict__ pending, double* __restrict__ force, double* __restrict__ hist, int cap,
-           long long* __restrict__ count, int nblk_all) {
+           int* __restrict__ pending, const double* __restrict__ fsum, double* __restrict__ force,
+           double* __restrict__ hist, int cap, long long* __restrict__ count, int nblk_all) {
   __shared__ double sred[(kPostBlock / 64) * 12];
   __shared__ double sres[12];
   int b = 0;
@@ -1316,18 +1359,24 @@ __global__ void __launch_bounds__(kPostBlock)
   const int par = a.par;
   const bool finisher = (int)blockIdx.x == B.post_blk0 + B.post_nblk - 1;
   if (finisher && pending[b]) {
-    finish_box<kPostBlock>(B, b, bpart + 12LL * nblk_all * (par ^ 1), force, hist, cap, count, sred, sres);
+    finish_box<kPostBlock>(B, b, bpart + 12LL * nblk_all * (par ^ 1), fsum, force, hist, cap, count, sred, sres);
     __syncthreads();
   }
   long long l = (long long)((int)blockIdx.x - B.post_blk0) * kPostBlock + threadIdx.x;
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const double Rc[3] = {B.pos[par][0], B.pos[par][1], B.pos[par][2]};
-  const bool moving = B.present && B.motion == 1;
+  const bool free_motion = B.present && B.motion == 2;
+  const bool moving = B.present && B.motion != 0;
   double Rn[3] = {Rc[0], Rc[1], Rc[2]};
-  if (moving) advanced_pos(B, par, Rn);
+  if (free_motion) {
+    // k_free has moved it already
+    Rn[0] = B.pos[par ^ 1][0]; Rn[1] = B.pos[par ^ 1][1]; Rn[2] = B.pos[par ^ 1][2];
+  } else if (moving) {
+    advanced_pos(B, par, Rn);
+  }
   if (B.present) {
     const long long nt = (long long)B.ntx * B.nty * B.ntz;
-    const long long nst = (nt + kPostSlots - 1) / kPostSlots;
+    const long long nst = free_motion ? 0 : (nt + kPostSlots - 1) / kPostSlots;
     const long long ne = moving ? (long long)B.event_ext * B.event_ext * B.event_ext : 0;
     const long long ng = (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
     if (l < nst) {
@@ -1365,14 +1414,14 @@ __global__ void __launch_bounds__(kPostBlock)
 
 // One block per box: finishes the pending step of buffer parity par.
 __global__ void __launch_bounds__(kFinishBlock)
-    k_finish(const BoxDev* __restrict__ boxes, int par, int nblk_all, const double* __restrict__ bpart,
-             int* __restrict__ pending, double* __restrict__ force, double* __restrict__ hist, int cap,
-             long long* __restrict__ count) {
+    k_finish(BoxDev* __restrict__ boxes, int par, int nblk_all, const double* __restrict__ bpart,
+             int* __restrict__ pending, const double* __restrict__ fsum, double* __restrict__ force,
+             double* __restrict__ hist, int cap, long long* __restrict__ count) {
   __shared__ double sred[(kFinishBlock / 64) * 12];
   __shared__ double sres[12];
   const int b = blockIdx.x;
   if (!pending[b]) return;
-  finish_box<kFinishBlock>(boxes[b], b, bpart + 12LL * nblk_all * par, force, hist, cap, count, sred, sres);
+  finish_box<kFinishBlock>(boxes[b], b, bpart + 12LL * nblk_all * par, fsum, force, hist, cap, count, sred, sres);
   if (threadIdx.x == 0) pending[b] = 0;
 }
 
@@ -1586,14 +1635,21 @@ hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, lo
 
 template <typename R>
 hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
-                       double* force, double* hist, int cap, long long* count, hipStream_t s) {
-  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, nbox, a, bpart, pending, force, hist, cap, count, nblk);
+                       const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s) {
+  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, nbox, a, bpart, pending, fsum, force, hist, cap, count,
+                                                  nblk);
   return hipGetLastError();
 }
 
-hipError_t launch_finish(int nbox, int nblk, const BoxDev* boxes, int par, const double* bpart, int* pending,
-                         double* force, double* hist, int cap, long long* count, hipStream_t s) {
-  k_finish<<<(unsigned)nbox, kFinishBlock, 0, s>>>(boxes, par, nblk, bpart, pending, force, hist, cap, count);
+hipError_t launch_free(int nbox, BoxDev* boxes, const double* part, long long nslot, int par, double* fsum,
+                       hipStream_t s) {
+  k_free<<<(unsigned)nbox, kFinishBlock, 0, s>>>(boxes, part, nslot, par, fsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(int nbox, int nblk, BoxDev* boxes, int par, const double* bpart, int* pending,
+                         const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s) {
+  k_finish<<<(unsigned)nbox, kFinishBlock, 0, s>>>(boxes, par, nblk, bpart, pending, fsum, force, hist, cap, count);
   return hipGetLastError();
 }
 
@@ -1621,8 +1677,8 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
   template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const int*, const StepPtrs<R>&,   \
                                      hipStream_t, hipEvent_t, hipEvent_t);                                  \
   template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, int, hipStream_t);      \
-  template hipError_t launch_post<R>(int, int, BoxDev*, const StepPtrs<R>&, double*, int*, double*, double*,  \
-                                     int, long long*, hipStream_t);                                          \
+  template hipError_t launch_post<R>(int, int, BoxDev*, const StepPtrs<R>&, double*, int*, const double*,    \
+                                     double*, double*, int, long long*, hipStream_t);                        \
   template hipError_t launch_diag<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*, hipStream_t); \
   template hipError_t launch_defects<R>(const BoxDev*, int, long long, const R*, long long, double,         \
                                         unsigned char*, unsigned long long*, int, hipStream_t);             \

@@ -83,17 +83,23 @@ hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, lo
 // After the fused kernel: moving-boundary events, the next step's ghost Q,
 // per-block sums of the fused kernel's colloid slots and the event momenta
 // (nblk blocks, 12 doubles each, into bpart + 12 * nblk * a.par) and the
-// next position pos[a.par ^ 1].  The first block of each box first finishes
+// next position pos[a.par ^ 1].  The last block of each box first finishes
 // the previous step if pending[box] is set (its block sums are in the other
 // half of bpart): force, force history, count; then marks this step
-// pending.
+// pending.  A free colloid's slots were added by launch_free (fsum), which
+// also moved it; its block sums then hold only the event momenta.
 template <typename R>
 hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
-                       double* force, double* hist, int cap, long long* count, hipStream_t s);
-// Finish a pending step of buffer parity par from the host (one block per
-// box; boxes with pending[box] == 0 are left alone).
-hipError_t launch_finish(int nbox, int nblk, const BoxDev* boxes, int par, const double* bpart, int* pending,
-                         double* force, double* hist, int cap, long long* count, hipStream_t s);
+                       const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s);
+// Free colloids (one block per box, others untouched): the step's slot sums
+// into fsum [12 per box], the velocity update and the next position.
+hipError_t launch_free(int nbox, BoxDev* boxes, const double* part, long long nslot, int par, double* fsum,
+                       hipStream_t s);
+// Finish a pending step of buffer parity par (one block per box; boxes with
+// pending[box] == 0 are left alone); a free colloid also receives the
+// events' momentum.
+hipError_t launch_finish(int nbox, int nblk, BoxDev* boxes, int par, const double* bpart, int* pending,
+                         const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s);
 template <typename R>
 hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const StepPtrs<R>& a, double* out,
                        hipStream_t s);

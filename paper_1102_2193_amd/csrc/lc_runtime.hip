@@ -65,6 +65,7 @@ struct lc_ctx {
   double* dbpart = nullptr;     // 12 per post-step block, one half per buffer parity
   size_t dbpart_cap = 0;
   int* dpending = nullptr;      // per box: a step whose force sums are not yet added
+  double* dfsum = nullptr;      // 12 per box: link and stress sums of a free colloid's step
   bool maybe_pending = false;   // a step ran since the last finish from the host
   bool ghost_fresh = false;     // ghost Q of buffer cur matches the colloids
   double* dforce = nullptr;     // 12 per box
@@ -74,7 +75,7 @@ struct lc_ctx {
   double* ddiag = nullptr;
   size_t ddiag_cap = 0;
   long nstep = 0;
-  bool any_colloid = false, any_moving = false;
+  bool any_colloid = false, any_moving = false, any_free = false;
   bool use_graph = true;
   bool graph_ok = false;
   hipGraphExec_t gexec = nullptr;
@@ -112,13 +113,18 @@ void destroy_graph(lc_ctx* c) {
   c->graph_ok = false;
 }
 
-// Read the device copy of the descriptors back (the colloid position moves
-// on the device) before the host rewrites them.
+// Read the device copy of the descriptors back (the colloid position, and a
+// free colloid's velocities, change on the device) before the host rewrites
+// them.
 int pull_boxes(lc_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->hb.data(), c->dbox, sizeof(BoxDev) * c->nbox, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int b = 0; b < c->nbox; b++)
-    for (int a = 0; a < 3; a++) c->col[b].pos[a] = c->hb[b].pos[c->cur][a];
+    for (int a = 0; a < 3; a++) {
+      c->col[b].pos[a] = c->hb[b].pos[c->cur][a];
+      c->col[b].vel[a] = c->hb[b].vel[a];       // a free colloid's change on the device
+      c->col[b].omega[a] = c->hb[b].omega[a];
+    }
   return LC_OK;
 }
 
@@ -316,8 +322,8 @@ int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& 
 // (the next step's post-step kernel would otherwise do it).
 int flush(lc_ctx* c) {
   if (!c->maybe_pending) return LC_OK;
-  HIPCHK(c, lc::launch_finish(c->nbox, c->npost, c->dbox, c->cur ^ 1, c->dbpart, c->dpending, c->dforce, c->dhist,
-                              kHistCap, c->dcount, c->stream));
+  HIPCHK(c, lc::launch_finish(c->nbox, c->npost, c->dbox, c->cur ^ 1, c->dbpart, c->dpending, c->dfsum, c->dforce,
+                              c->dhist, kHistCap, c->dcount, c->stream));
   c->maybe_pending = false;
   return LC_OK;
 }
@@ -335,7 +341,7 @@ int layout(lc_ctx* c) {
   const TileShape& T = tile_shape(c, c->tile);
   long long tb = 0, gb = 0;
   int pblk = 0;
-  c->any_colloid = c->any_moving = false;
+  c->any_colloid = c->any_moving = c->any_free = false;
   std::vector<int2> tiles;
   if (T.kind == 1 && c->nbox > lc::kMaxBoxes) return fail(c, LC_EINVAL, "too many boxes for the marching kernel");
   if (T.kind == 1 && !march_fits(c))
@@ -371,17 +377,25 @@ int layout(lc_ctx* c) {
     B.a0 = k.a0;
     B.S0 = k.S0;
     B.W = k.W;
+    {
+      const double rc = k.rho_c > 0.0 ? k.rho_c : p.rho0;
+      const double M = 4.0 / 3.0 * acos(-1.0) * k.a0 * k.a0 * k.a0 * rc;
+      for (int a = 0; a < 3; a++) B.fext[a] = k.fext[a];
+      B.mass = M;
+      B.inertia = 0.4 * M * k.a0 * k.a0;
+    }
     const int ca = k.present ? (int)ceil(k.a0) : 0;
     B.ghost_ext = k.present ? 2 * ca + 3 : 0;
     B.ghost_base = (int)gb;
     gb += (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
-    const bool moving = k.present && k.motion == LC_PRESCRIBED;
+    const bool moving = k.present && k.motion != LC_FIXED;
     B.event_ext = moving ? 2 * ca + 5 : 0;
     // post-step threads: slot sums (kPostSlots slots each), one per event
     // candidate, one per ghost candidate, then one more block that only
     // finishes the previous step
     const long long nt = (long long)B.ntx * B.nty * B.ntz;
-    const long long nst = k.present ? (nt + lc::kPostSlots - 1) / lc::kPostSlots : 0;
+    // (a free colloid's slots are added before the post-step kernel)
+    const long long nst = k.present && k.motion != LC_FREE ? (nt + lc::kPostSlots - 1) / lc::kPostSlots : 0;
     const long long ne = (long long)B.event_ext * B.event_ext * B.event_ext;
     const long long ng = (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
     B.post_blk0 = pblk;
@@ -390,6 +404,7 @@ int layout(lc_ctx* c) {
     pblk += B.post_nblk;
     c->any_colloid |= (bool)k.present;
     c->any_moving |= moving;
+    c->any_free |= k.present && k.motion == LC_FREE;
   }
   if (tb > (1LL << 30)) return fail(c, LC_EINVAL, "too many tiles");
   c->ntile = (int)tb;
@@ -472,8 +487,15 @@ hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t
   e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, c->doffs, a, c->stream, k0, k1);
   if (e != hipSuccess) return e;
   c->maybe_pending = true;
-  return lc::launch_post<R>(c->npost, c->nbox, c->dbox, a, c->dbpart, c->dpending, c->dforce, c->dhist, kHistCap,
-                            c->dcount, c->stream);
+  // a free colloid is moved by its own force: the slot sums come first, and
+  // the step is finished at once (the next step reads the velocity)
+  if (c->any_free && (e = lc::launch_free(c->nbox, c->dbox, a.part, a.nslot, a.par, c->dfsum, c->stream)) != hipSuccess)
+    return e;
+  e = lc::launch_post<R>(c->npost, c->nbox, c->dbox, a, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
+                         kHistCap, c->dcount, c->stream);
+  if (e != hipSuccess || !c->any_free) return e;
+  return lc::launch_finish(c->nbox, c->npost, c->dbox, a.par, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
+                           kHistCap, c->dcount, c->stream);
 }
 
 hipError_t enqueue(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t k1 = nullptr) {
@@ -580,7 +602,11 @@ int check_colloid(const lc_params& p, const lc_colloid& k, lc_colloid& v, std::s
   const int Lmin = std::min(p.nx, std::min(p.ny, p.nz));
   if (!(v.a0 > 1.0) || !(2.0 * v.a0 + 4.0 <= Lmin)) { why = "colloid radius does not fit the box"; return LC_EINVAL; }
   if (v.anchoring < LC_ANCHOR_NONE || v.anchoring > LC_ANCHOR_PLANAR) { why = "bad anchoring"; return LC_EINVAL; }
-  if (v.motion != LC_FIXED && v.motion != LC_PRESCRIBED) { why = "bad motion"; return LC_EINVAL; }
+  if (v.motion != LC_FIXED && v.motion != LC_PRESCRIBED && v.motion != LC_FREE) { why = "bad motion"; return LC_EINVAL; }
+  if (!isfinite(v.fext[0]) || !isfinite(v.fext[1]) || !isfinite(v.fext[2]) || !isfinite(v.rho_c)) {
+    why = "external force and colloid density must be finite";
+    return LC_EINVAL;
+  }
   if (!(v.W >= 0.0)) { why = "W must be >= 0"; return LC_EINVAL; }
   if (v.anchoring != LC_ANCHOR_NONE && !(p.K + v.W > 0.0)) { why = "K + W must be positive"; return LC_EINVAL; }
   for (int a = 0; a < 3; a++)
@@ -690,12 +716,14 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
       hipMalloc(&c->dhist, sizeof(double) * 12 * (size_t)kHistCap * nbox) != hipSuccess ||
       hipMalloc(&c->dcount, sizeof(long long) * nbox) != hipSuccess ||
       hipMalloc(&c->dpending, sizeof(int) * nbox) != hipSuccess ||
+      hipMalloc(&c->dfsum, sizeof(double) * 12 * nbox) != hipSuccess ||
       hipMalloc(&c->dflag, sizeof(int)) != hipSuccess)
     return bail(LC_ENOMEM, "device allocation failed");
   hipMemsetAsync(c->dforce, 0, sizeof(double) * 12 * nbox, c->stream);
   hipMemsetAsync(c->dhist, 0, sizeof(double) * 12 * (size_t)kHistCap * nbox, c->stream);
   hipMemsetAsync(c->dcount, 0, sizeof(long long) * nbox, c->stream);
   hipMemsetAsync(c->dpending, 0, sizeof(int) * nbox, c->stream);
+  hipMemsetAsync(c->dfsum, 0, sizeof(double) * 12 * nbox, c->stream);
   hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream);
   for (int k = 0; k < 2; k++) {
     hipMemsetAsync(c->Q[k], 0, nq, c->stream);
@@ -739,7 +767,7 @@ void lc_destroy(lc_ctx* c) {
       if (c->Q[k]) hipFree(c->Q[k]);
       if (c->u[k]) hipFree(c->u[k]);
     }
-  void* bufs[] = {c->dbox,  c->dtiles, c->doffs, c->dpart,  c->dbpart, c->dpending,
+  void* bufs[] = {c->dbox,  c->dtiles, c->doffs, c->dpart,  c->dbpart, c->dpending, c->dfsum,
                   c->dforce, c->dhist,  c->dcount, c->dflag,  c->ddiag};
   for (void* b : bufs)
     if (b) hipFree(b);

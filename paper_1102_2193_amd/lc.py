@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblc.so")
 
 FP32, FP64 = 0, 1
 ANCHOR_NONE, ANCHOR_NORMAL, ANCHOR_PLANAR = 0, 1, 2
-FIXED, PRESCRIBED = 0, 1
+FIXED, PRESCRIBED, FREE = 0, 1, 2
 ANCHORING = {"none": ANCHOR_NONE, "normal": ANCHOR_NORMAL, "planar": ANCHOR_PLANAR}
 
 STATUS = {0: "LC_OK", 1: "LC_EINVAL", 2: "LC_ENOMEM", 3: "LC_EDEVICE", 4: "LC_ENUMERIC", 5: "LC_ESTATE"}
@@ -50,7 +50,8 @@ class Colloid(ctypes.Structure):
     _fields_ = [("present", ctypes.c_int), ("motion", ctypes.c_int), ("anchoring", ctypes.c_int),
                 ("pad_", ctypes.c_int), ("pos", ctypes.c_double * 3), ("a0", ctypes.c_double),
                 ("vel", ctypes.c_double * 3), ("omega", ctypes.c_double * 3),
-                ("S0", ctypes.c_double), ("W", ctypes.c_double)]
+                ("S0", ctypes.c_double), ("W", ctypes.c_double),
+                ("fext", ctypes.c_double * 3), ("rho_c", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):
@@ -124,13 +125,13 @@ def make_params(nx, ny=None, nz=None, precision=FP32, hydro=1, tau=1.0, rho0=1.0
 
 
 def make_colloid(pos, a0, anchoring=ANCHOR_NORMAL, W=math.inf, S0=0.5, vel=(0, 0, 0), omega=(0, 0, 0),
-                 motion=FIXED, present=1):
+                 motion=FIXED, present=1, fext=(0, 0, 0), rho_c=0.0):
     c = Colloid()
     c.present, c.motion = int(present), int(motion)
     c.anchoring = ANCHORING.get(anchoring, anchoring)
     for a in range(3):
-        c.pos[a], c.vel[a], c.omega[a] = pos[a], vel[a], omega[a]
-    c.a0, c.S0, c.W = a0, S0, W
+        c.pos[a], c.vel[a], c.omega[a], c.fext[a] = pos[a], vel[a], omega[a], fext[a]
+    c.a0, c.S0, c.W, c.rho_c = a0, S0, W, rho_c
     return c
 
 

@@ -38,12 +38,29 @@ def test_library_exports_every_declared_symbol(lib):
     assert sorted(lc.EXPORTS) == names
 
 
-def test_struct_sizes_match_header(lib):
+def test_struct_sizes_match_header(lib, tmp_path):
+    # the ctypes structures against the C header itself (sizes and offsets
+    # printed by a program compiled from include/lc.h)
+    import subprocess
     from paper_1102_2193_amd import lc
-    # int x6 + double x11 ; int x4 + double x12
-    assert ctypes.sizeof(lc.Params) == 6 * 4 + 11 * 8
-    assert ctypes.sizeof(lc.Colloid) == 4 * 4 + 12 * 8
-    assert ctypes.sizeof(lc.Diag) == 6 * 8
+    structs = {"lc_params": lc.Params, "lc_colloid": lc.Colloid, "lc_diag": lc.Diag}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 @pytest.mark.parametrize("field,value", [("nx", 4), ("tau", 0.5), ("precision", 7), ("rho0", 0.0),

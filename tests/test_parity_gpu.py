@@ -325,3 +325,82 @@ def test_full_size_drag128_against_oracle():
     # mass is conserved to FP32 round-off at full size
     d = r["ctx"].diag(0)
     assert d["mass"] == pytest.approx(r["ref"].diag()["mass"], rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# free colloid (velocity and position from the force)
+# ---------------------------------------------------------------------------
+FREE = dict(motion=2, vel=(0.03, -0.02, 0.01), omega=(0.0, 0.0, 0.002), fext=(2e-3, 0.0, -1e-3), rho_c=1.3)
+
+
+def _state(ctx, ref):
+    c, oc = ctx.get_colloid(0), ref.get_colloid()
+    return (np.array(list(c.pos) + list(c.vel) + list(c.omega)),
+            np.array(list(oc.pos) + list(oc.vel) + list(oc.omega)))
+
+
+def test_free_colloid_fp64_against_oracle():
+    say("case: 16^3 fp64 chiral planar W=0.02, free colloid a=3.5 with external force, 40 steps")
+    L = 16
+    prm = dict(NEM, q0=0.2)
+    col = dict(pos=(7.6, 8.3, 8.1), a0=3.5, anchoring="planar", W=0.02, S0=0.5, **FREE)
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=31, noise=0.02, director=(1, 0.2, 0.4))
+    r = run_pair((L, L, L), prm, 40, "fp64", colloid=col, Q0=Q0, hist=True)
+    check(r, 1e-10, 1e-12, tol_u=1e-8, tol_force=1e-8)
+    g, o = _state(r["ctx"], r["ref"])
+    say("   pos/vel/omega max diff %.3e" % np.max(np.abs(g - o)))
+    np.testing.assert_allclose(g, o, rtol=1e-9, atol=1e-13)
+    assert np.linalg.norm(g[3:6] - np.array(FREE["vel"])) > 1e-4   # it did move under the force
+
+
+def test_free_colloid_fp32_marching_against_oracle():
+    say("case: 32^3 fp32 normal W=0.01, free colloid a=4 pulled along x, 60 steps")
+    L = 32
+    col = dict(pos=(15.6, 16.3, 16.2), a0=4.0, anchoring="normal", W=0.01, S0=0.5, motion=2,
+               vel=(0.0, 0.0, 0.0), fext=(0.02, 0.0, 0.0), rho_c=1.0)
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=32)
+    r = run_pair((L, L, L), NEM, 60, "fp32", colloid=col, Q0=Q0, hist=True)
+    check(r, 1e-5, 1e-5, tol_force=1e-3)
+    g, o = _state(r["ctx"], r["ref"])
+    say("   vel gpu %s oracle %s" % (g[3:6], o[3:6]))
+    np.testing.assert_allclose(g[3:6], o[3:6], rtol=1e-4, atol=1e-9)
+    np.testing.assert_allclose(g[0:3], o[0:3], atol=1e-6)
+    assert o[3] > 1e-4                                             # pulled along +x
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_free_colloid_closed_form_without_fluid(precision):
+    from paper_1102_2193_amd import lc
+    say("case: 16^3 %s fluid off, Q = 0, free colloid with external force, 40 steps" % precision)
+    L, a, rho_c, n = 16, 3.0, 1.5, 40
+    fext, v0 = np.array([2e-3, -1e-3, 5e-4]), np.array([1e-3, 0.0, -2e-3])
+    ctx = lc.Context([dict(nx=L, precision=precision, **dict(NEM, hydro=0))])
+    ctx.set_colloid(0, (8.2, 7.9, 8.4), a, anchoring="none", motion=lc.FREE, vel=tuple(v0), fext=tuple(fext),
+                    rho_c=rho_c)
+    ctx.set_Q(0, np.zeros((5, L, L, L)))
+    ctx.step(n)
+    c = ctx.get_colloid(0)
+    acc = fext / (4.0 / 3.0 * math.pi * a ** 3 * rho_c)
+    np.testing.assert_allclose(np.array(c.vel), v0 + n * acc, rtol=1e-12, atol=1e-17)
+    np.testing.assert_allclose(np.array(c.pos), (np.array([8.2, 7.9, 8.4]) + n * v0 + acc * n * (n + 1) / 2) % L,
+                               atol=1e-12)
+    assert np.all(ctx.force_history(0, n) == 0.0)
+    ctx.close()
+
+
+def test_free_colloid_conserves_total_momentum():
+    from paper_1102_2193_amd import lc
+    say("case: 16^3 fp64 free colloid, no external force: fluid + colloid momentum, 20 steps")
+    L, a = 16, 3.5
+    ctx = lc.Context([dict(nx=L, precision="fp64", **NEM)])
+    ctx.set_colloid(0, (8.3, 7.6, 8.1), a, anchoring="planar", W=0.01, motion=lc.FREE, vel=(0.06, 0.0, -0.03))
+    ctx.set_Q(0, inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, 21, noise=0.02))
+    M = 4.0 / 3.0 * math.pi * a ** 3 * NEM.get("rho0", 1.0)
+
+    def total():
+        return ctx.diag(0)["momentum"] + M * np.array(ctx.get_colloid(0).vel)
+    p0 = total()
+    for _ in range(20):
+        ctx.step(1)
+        np.testing.assert_allclose(total(), p0, atol=1e-11)
+    ctx.close()
