@@ -176,6 +176,20 @@ def network_leg(L=64, reps=20):
             "train_flop": NN_TRAIN_FLOP_PER_VOXEL * L ** 3}
 
 
+def microrheology_leg():
+    """Free colloid pulled along and across the director (the paper's
+    microrheology set-up): steady speeds and their ratio."""
+    from paper_1102_2193_amd import microrheology as mr
+    t0 = time.perf_counter()
+    L, a, f = 128, 16.0, 0.09
+    res = mr.pull(L, a, f, settle=2000, steps=16000, every=500)
+    out = mr.summary(res, f, a)
+    out.update({"grid": [L, L, L], "a": a, "f": f, "settle_steps": 2000, "pull_steps": 16000,
+                "params": "A0=1, K=0.065, gamma=3, xi=0.7, Gamma=0.5, eta=0.1, planar W=inf",
+                "seconds": round(time.perf_counter() - t0, 1)})
+    return out
+
+
 def warm_start_leg(L=64):
     """Plain vs warm relaxation of two held-out cases, live."""
     from paper_1102_2193_amd import inputs, nn
@@ -207,7 +221,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="also time graph replay (1)")
-    ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start and network legs")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start, network and microrheology legs")
     ap.add_argument("--network-only", action="store_true", help="only time the warm-start network")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
@@ -287,6 +301,7 @@ def main():
     ctx.close()
     if not args.no_warm_start and args.workload == "drag128_fp32":
         out["warm_start"] = warm_start_leg()
+        out["microrheology"] = microrheology_leg()
         out["network"] = network_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
