@@ -325,7 +325,17 @@ __global__ void __launch_bounds__(256)
   const int i = blockIdx.x * 64 + lane;
   float acc = 0.f;
   if (i < np)
-    for (int k = w; k < nblk; k += 4) acc += part[(long long)k * np + i];
+    for (int k0 = w; k0 < nblk; k0 += 32) {
+      // eight loads in flight, added in the order k = w, w + 4, ...
+      float t[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int k = k0 + 4 * j;
+        t[j] = k < nblk ? part[(long long)k * np + i] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j++) acc += t[j];
+    }
   s[w][lane] = acc;
   __syncthreads();
   if (w == 0 && i < np) {
@@ -335,15 +345,32 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Bias gradient partials: part[b][o] = sum of dz over voxels [b*chunk, ...)
+// Bias gradient partials: part[b][o] = sum of dz over voxels [b*chunk, ...).
+// A thread reads eight channels (16 bytes) of one voxel per load, four
+// voxels in flight; the voxel lanes are then added in lane order.
 __global__ void __launch_bounds__(256)
     k_bgrad(long long V, int chunk, int COUTP, const uint16_t* __restrict__ dz, float* __restrict__ part) {
-  __shared__ float s[256];
-  const int o = threadIdx.x % COUTP, lane = threadIdx.x / COUTP, nl = 256 / COUTP;
-  float acc = 0.f;
-  const long long v0 = (long long)blockIdx.x * chunk;
-  for (long long v = v0 + lane; v < v0 + chunk && v < V; v += nl) acc += bf2f(dz[v * COUTP + o]);
-  s[threadIdx.x] = acc;
+  __shared__ float s[256 * 8];
+  const int ng = COUTP / 8, cg = threadIdx.x % ng, lane = threadIdx.x / ng, nl = 256 / ng;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const long long v0 = (long long)blockIdx.x * chunk, v1 = v0 + chunk < V ? v0 + chunk : V;
+  for (long long v = v0 + lane; v < v1; v += 4LL * nl) {
+    u4 t[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const long long vj = v + (long long)j * nl;
+      t[j] = vj < v1 ? *(const u4*)(dz + vj * COUTP + 8 * cg) : u4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        acc[2 * q] += bf2f((uint16_t)(t[j][q] & 0xffffu));
+        acc[2 * q + 1] += bf2f((uint16_t)(t[j][q] >> 16));
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; q++) s[lane * COUTP + 8 * cg + q] = acc[q];
   __syncthreads();
   if (threadIdx.x < COUTP) {
     float t = 0.f;

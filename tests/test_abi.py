@@ -43,8 +43,9 @@ def test_struct_sizes_match_header(lib, tmp_path):
     # printed by a program compiled from include/lc.h)
     import subprocess
     from paper_1102_2193_amd import lc
-    structs = {"lc_params": lc.Params, "lc_colloid": lc.Colloid, "lc_diag": lc.Diag}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lc.h"', "int main(void) {"]
+    from paper_1102_2193_amd import nn
+    structs = {"lc_params": lc.Params, "lc_colloid": lc.Colloid, "lc_diag": lc.Diag, "lc_nn_case": nn.Case}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lc.h"', '#include "lc_nn.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
         for fname, _ in py._fields_:

@@ -198,3 +198,27 @@ def test_reading_forces_between_steps_changes_nothing():
         out.append(snapshot(ctx, 1, 32))
         ctx.close()
     assert_same(out[0], out[1])
+
+
+def test_free_colloid_continues_bit_for_bit():
+    # the state carries the free colloid's current velocity and spin
+    from paper_1102_2193_amd import lc
+    say("case: checkpoint 20^3 fp64 free colloid pulled by an external force, save at 9, continue 21")
+    L = 20
+    box = [dict(nx=L, precision="fp64", **NEM)]
+    a = lc.Context(box)
+    a.set_colloid(0, (9.6, 10.3, 10.1), 3.5, anchoring="planar", W=0.01, motion=lc.FREE, vel=(0.02, 0.0, 0.01),
+                  fext=(4e-3, -1e-3, 0.0), rho_c=1.2)
+    a.set_Q(0, inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=14))
+    a.step(9)
+    state = a.get_state()
+    a.step(21)
+    ref = snapshot(a, 1, 30)
+    va = np.array(list(a.get_colloid(0).vel) + list(a.get_colloid(0).omega))
+    b = lc.Context(box)
+    b.set_state(state)
+    b.step(21)
+    assert_same(snapshot(b, 1, 30), ref)
+    np.testing.assert_array_equal(np.array(list(b.get_colloid(0).vel) + list(b.get_colloid(0).omega)), va)
+    a.close()
+    b.close()
