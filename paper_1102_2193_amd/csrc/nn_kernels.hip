@@ -197,9 +197,12 @@ __global__ void __launch_bounds__(256)
 // weight gradient: dW[t][o][c] = sum_p dz[p][o] x[p + d_t][c]
 // ---------------------------------------------------------------------
 // Block b accumulates over tiles [b*tpb, (b+1)*tpb) and writes its partial
-// sums part[b][27][COUT][CIN]; wave w owns taps w, w+4, ...
+// sums part[b][27][COUT][CIN]; wave w of the kWgThreads / 64 owns taps
+// w, w + 8, ... (at most four: the accumulators stay small enough for two
+// waves per SIMD)
+constexpr int kWgThreads = 512;
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kWgThreads)
     k_wgrad(int L, int tpb, const uint16_t* __restrict__ dz, const uint16_t* __restrict__ x, float* __restrict__ part) {
   constexpr int PS = TV + 8, XS = HV + 8;   // LDS row strides
   __shared__ uint16_t sd[COUT * PS];        // [o][p]
@@ -207,7 +210,7 @@ __global__ void __launch_bounds__(256)
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int ri = lane & 15, kq = lane >> 4;
   const int ntx = L / TX, nty = L / TY, ntz = L / TZ, ntile = ntx * nty * ntz;
-  constexpr int NTAP = 7;
+  constexpr int NW = kWgThreads / 64, NTAP = (27 + NW - 1) / NW;
   f4 acc[NTAP][COUT / 16][CIN / 16];
 #pragma unroll
   for (int a = 0; a < NTAP; a++)
@@ -220,11 +223,11 @@ __global__ void __launch_bounds__(256)
     // staged transposed ([channel][voxel]), eight channels per 16-byte
     // load; every load of the tile is issued before the first LDS store
     constexpr int DC = COUT / 8, XC = CIN / 8;
-    constexpr int NID = (TV * DC + 255) / 256, NIX = (HV * XC + 255) / 256;
+    constexpr int NID = (TV * DC + kWgThreads - 1) / kWgThreads, NIX = (HV * XC + kWgThreads - 1) / kWgThreads;
     u4 td[NID], tx[NIX];
 #pragma unroll
     for (int it = 0; it < NID; it++) {
-      const int e = tid + it * 256;
+      const int e = tid + it * kWgThreads;
       if (e < TV * DC) {
         const int p = e / DC, o = 8 * (e - p * DC);
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
@@ -234,7 +237,7 @@ __global__ void __launch_bounds__(256)
     }
 #pragma unroll
     for (int it = 0; it < NIX; it++) {
-      const int e = tid + it * 256;
+      const int e = tid + it * kWgThreads;
       if (e < HV * XC) {
         const int v = e / XC, c = 8 * (e - v * XC);
         const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
@@ -246,7 +249,7 @@ __global__ void __launch_bounds__(256)
     __syncthreads();   // the previous tile's LDS reads are done
 #pragma unroll
     for (int it = 0; it < NID; it++) {
-      const int e = tid + it * 256;
+      const int e = tid + it * kWgThreads;
       if (e < TV * DC) {
         const int p = e / DC, o = 8 * (e - p * DC);
 #pragma unroll
@@ -258,7 +261,7 @@ __global__ void __launch_bounds__(256)
     }
 #pragma unroll
     for (int it = 0; it < NIX; it++) {
-      const int e = tid + it * 256;
+      const int e = tid + it * kWgThreads;
       if (e < HV * XC) {
         const int v = e / XC, c = 8 * (e - v * XC);
 #pragma unroll
@@ -271,7 +274,7 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
 #pragma unroll
     for (int a = 0; a < NTAP; a++) {
-      const int t = wv + 4 * a;
+      const int t = wv + NW * a;
       if (t >= 27) break;
       const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dzz = t / 9 - 1;
       for (int ks = 0; ks < TV / 16; ks++) {
@@ -297,7 +300,7 @@ __global__ void __launch_bounds__(256)
   float* out = part + (long long)blockIdx.x * 27 * COUT * CIN;
 #pragma unroll
   for (int a = 0; a < NTAP; a++) {
-    const int t = wv + 4 * a;
+    const int t = wv + NW * a;
     if (t >= 27) break;
 #pragma unroll
     for (int m = 0; m < COUT / 16; m++)
@@ -536,7 +539,7 @@ hipError_t launch_wgrad(int cinp, int coutp, int L, int nblk, int tpb, const uin
                         float* part, hipStream_t s) {
 #define LCNN_WG(CI, CO)                                                  \
   if (cinp == CI && coutp == CO) {                                       \
-    k_wgrad<CI, CO><<<nblk, 256, 0, s>>>(L, tpb, dz, x, part);           \
+    k_wgrad<CI, CO><<<nblk, kWgThreads, 0, s>>>(L, tpb, dz, x, part);    \
     return hipGetLastError();                                            \
   }
   LCNN_WG(16, 32)
