@@ -1269,36 +1269,56 @@ __device__ inline void event_site(const BoxDev& B, const double Rc[3], const dou
 // post-step: events, next step's ghost Q, colloid sums, history, R += v
 // ---------------------------------------------------------------------
 // Force, torque and history entry of one finished step of box b: the block
-// vectors of its post-step kernel added in block order (nt threads).
+// vectors of its post-step kernel added in block order (nt threads).  Every
+// load (block vectors, step count, the pending flag when one is given) is
+// issued before the first sum, so the finish costs one memory round trip;
+// each thread still adds its vectors in increasing block order.  With a flag
+// that reads zero nothing is written.
 template <int NT>
 __device__ inline void finish_box(BoxDev& B, int b, const double* __restrict__ bpart, const double* __restrict__ fsum,
                                   double* __restrict__ force, double* __restrict__ hist, int cap,
-                                  long long* __restrict__ count, double* sred, double* sres) {
+                                  long long* __restrict__ count, double* sred, double* sres,
+                                  const int* __restrict__ pend = nullptr) {
+  constexpr int KB = 4;   // block vectors in flight per thread
+  const bool go = pend == nullptr || *pend != 0;
+  const long long n = count[b];
+  const int nblk = B.post_nblk;
+  const double* p0 = bpart + 12LL * B.post_blk0;
   double w[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = threadIdx.x; k < B.post_nblk; k += NT) {
-    const double* p = bpart + 12LL * (B.post_blk0 + k);
-    for (int c = 0; c < 12; c++) w[c] += p[c];
+  for (int k0 = 0; k0 < nblk; k0 += KB * NT) {
+    double t[KB][12];
+#pragma unroll
+    for (int j = 0; j < KB; j++) {
+      const int k = k0 + j * NT + (int)threadIdx.x;
+      const double* p = p0 + 12LL * (k < nblk ? k : 0);
+#pragma unroll
+      for (int c = 0; c < 12; c++) t[j][c] = p[c];
+    }
+#pragma unroll
+    for (int j = 0; j < KB; j++)
+      if (k0 + j * NT + (int)threadIdx.x < nblk)
+#pragma unroll
+        for (int c = 0; c < 12; c++) w[c] += t[j][c];
   }
   block_sum<NT, 12>(w, sred, sres);
   __syncthreads();
+  if (!go) return;
   // a free colloid: the link and stress sums were added before the move
   // (k_free); the block vectors hold the events' momentum, which also goes
   // to its velocity
   const bool free_motion = B.present && B.motion == 2;
   if (threadIdx.x < 12) {
     const double val = !B.present ? 0.0 : (free_motion ? fsum[12 * b + threadIdx.x] + sres[threadIdx.x] : sres[threadIdx.x]);
-    const long long n = count[b];
     force[12 * b + threadIdx.x] = val;
     hist[((long long)b * cap + (n % cap)) * 12 + threadIdx.x] = val;
   }
-  __syncthreads();
   if (threadIdx.x == 0) {
     if (free_motion)
       for (int k = 0; k < 3; k++) {
         B.vel[k] += sres[k] / B.mass;
         B.omega[k] += sres[6 + k] / B.inertia;
       }
-    count[b] += 1;
+    count[b] = n + 1;
   }
 }
 
@@ -1358,12 +1378,8 @@ __global__ void __launch_bounds__(kPostBlock)
   BoxDev& B = boxes[b];
   const int par = a.par;
   const bool finisher = (int)blockIdx.x == B.post_blk0 + B.post_nblk - 1;
-  if (finisher && pending[b]) {
-    finish_box<kPostBlock>(B, b, bpart + 12LL * nblk_all * (par ^ 1), fsum, force, hist, cap, count, sred, sres);
-    __syncthreads();
-  }
-  long long l = (long long)((int)blockIdx.x - B.post_blk0) * kPostBlock + threadIdx.x;
-  double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // the positions first: the finish below changes only a free colloid's
+  // velocity, which the next position (already formed by k_free) does not use
   const double Rc[3] = {B.pos[par][0], B.pos[par][1], B.pos[par][2]};
   const bool free_motion = B.present && B.motion == 2;
   const bool moving = B.present && B.motion != 0;
@@ -1374,6 +1390,13 @@ __global__ void __launch_bounds__(kPostBlock)
   } else if (moving) {
     advanced_pos(B, par, Rn);
   }
+  if (finisher) {
+    finish_box<kPostBlock>(B, b, bpart + 12LL * nblk_all * (par ^ 1), fsum, force, hist, cap, count, sred, sres,
+                           pending + b);
+    __syncthreads();
+  }
+  long long l = (long long)((int)blockIdx.x - B.post_blk0) * kPostBlock + threadIdx.x;
+  double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (B.present) {
     const long long nt = (long long)B.ntx * B.nty * B.ntz;
     const long long nst = free_motion ? 0 : (nt + kPostSlots - 1) / kPostSlots;
