@@ -123,18 +123,30 @@ struct FieldBuf {
       : r(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)((unsigned)ncomp * (unsigned)ns * 4u),
                                             0x00020000)),
         cs((unsigned)ns * 4u) {}
+  // Scalar offset of component c.  The empty asm hides the stride from the
+  // optimiser at each access, so the product is formed by one scalar
+  // multiply next to its load or store; left visible, all eighteen products
+  // are hoisted out of the plane loop, overflow the scalar registers and come
+  // back through vector-lane reloads (a vector instruction plus a wait
+  // before each access).
+  __device__ unsigned co(int c) const {
+    if (c == 0) return 0u;
+    unsigned k = cs;
+    asm volatile("" : "+s"(k));
+    return (unsigned)c * k;
+  }
   // aux 2 = non-temporal (streamed once)
   __device__ float ld(int c, unsigned s) const {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, s * 4u, (unsigned)c * cs, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, s * 4u, co(c), 0));
   }
   __device__ float ld_nt(int c, unsigned s) const {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, s * 4u, (unsigned)c * cs, 2));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, s * 4u, co(c), 2));
   }
   __device__ void st(int c, unsigned s, float v) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, s * 4u, (unsigned)c * cs, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, s * 4u, co(c), 0);
   }
   __device__ void st_nt(int c, unsigned s, float v) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, s * 4u, (unsigned)c * cs, 2);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, s * 4u, co(c), 2);
   }
 };
 
