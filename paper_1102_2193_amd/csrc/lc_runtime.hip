@@ -134,8 +134,31 @@ int pull_boxes(lc_ctx* c) {
 const int kMargin = 2;       // sites of colloid motion covered between layouts
 // Cost model of marching work, in plane-times of the solid-free path: a
 // fixed start per work item (prologue loads and stresses) plus one per
-// plane, about twice that per plane where the colloid can reach (measured).
-const double kItemStart = 1.08, kNearPlaneCost = 1.64;
+// plane; where the colloid can reach, 1.43 per plane, and 1.95 where the
+// column block's own rectangle of the plane holds solid nodes (fitted to
+// per-block clocks of the 128^3 drag case: 5.3, 7.6 and 10.3 us per plane).
+const double kItemStart = 1.08, kNearPlaneCost = 1.43, kSolidPlaneCost = 1.95;
+
+// Does the rectangle [x0, x0 + ex) x [y0, y0 + ey) of plane z hold a lattice
+// node inside the colloid (any periodic image)?  The lattice node nearest to
+// the centre is found axis by axis; only the schedule's cost uses it.
+bool host_solid_rect(const lc_params& p, const lc_colloid& k, int x0, int y0, int ex, int ey, int z) {
+  if (!k.present) return false;
+  const int lo[3] = {x0, y0, z}, hi[3] = {x0 + ex - 1, y0 + ey - 1, z}, L[3] = {p.nx, p.ny, p.nz};
+  double d2 = 0.0;
+  for (int a = 0; a < 3; a++) {
+    double best = 1e300;
+    for (int m = -1; m <= 1; m++) {
+      const double c = k.pos[a] + m * L[a];
+      double q = floor(c + 0.5);
+      q = q < lo[a] ? lo[a] : (q > hi[a] ? hi[a] : q);
+      const double e = (q - c) * (q - c);
+      best = e < best ? e : best;
+    }
+    d2 += best;
+  }
+  return d2 < k.a0 * k.a0;
+}
 
 bool host_near(const lc_params& p, const lc_colloid& k, int x0, int y0, int z0, int ex, int ey, int ez,
                int margin) {
@@ -158,12 +181,12 @@ bool host_near(const lc_params& p, const lc_colloid& k, int x0, int y0, int z0, 
 // Persistent-block schedule of the marching kernel.  The z groups of every
 // column block, taken in spatial order (box, column block, z), carry an
 // estimated cost: one plane-time per plane, kNearPlaneCost where the
-// colloid can reach, plus kItemStart for each work item (run of groups of
-// one column block) a block starts.  The sequence is cut into at most
-// `slots` contiguous segments, each at most `cap`, with the smallest cap
-// found by bisection; segment r goes to block (r / per_die) + 8 (r % per_die),
-// so every die takes a contiguous part of the domain (L2 locality).  Every
-// (box, column block, group) is checked to be covered exactly once.
+// colloid can reach, kSolidPlaneCost where the block's rectangle of the plane
+// holds solid nodes, plus kItemStart for each work item (run of groups of
+// one column block) a block starts.  Each column block's run is cut into
+// pieces of equal cost, the piece counts apportioned over the resident
+// blocks, and the pieces dealt out die by die (below).  Every (box, column
+// block, group) is checked to be covered exactly once.
 int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& order, std::vector<int>& offs) {
   struct Grp {
     int b, cb, g;
@@ -180,7 +203,10 @@ int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& 
       for (int g = 0; g < B.ntz; g++) {
         const bool nr =
             host_near(p, k, x0 - 2, y0 - 2, g * lc::kGroup - 2, T.x + 4, T.y + 4, lc::kGroup + 4, kMargin);
-        grp.push_back({b, cb, g, lc::kGroup * (nr ? kNearPlaneCost : 1.0)});
+        double cost = 0.0;
+        for (int z = g * lc::kGroup; z < (g + 1) * lc::kGroup && z < B.nz; z++)
+          cost += !nr ? 1.0 : (host_solid_rect(p, k, x0, y0, T.x, T.y, z) ? kSolidPlaneCost : kNearPlaneCost);
+        grp.push_back({b, cb, g, cost});
       }
     }
   }
