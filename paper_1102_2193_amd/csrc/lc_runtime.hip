@@ -136,8 +136,10 @@ const int kMargin = 2;       // sites of colloid motion covered between layouts
 // fixed start per work item (prologue loads and stresses) plus one per
 // plane; where the colloid can reach, 1.43 per plane, and 1.95 where the
 // column block's own rectangle of the plane holds solid nodes (fitted to
-// per-block clocks of the 128^3 drag case: 5.3, 7.6 and 10.3 us per plane).
-const double kItemStart = 1.08, kNearPlaneCost = 1.43, kSolidPlaneCost = 1.95;
+// per-block clocks of the 128^3 drag case: 5.3, 7.6 and 10.3 us per plane,
+// 12 us for each further item a block starts).
+const double kItemStart = 2.3, kNearPlaneCost = 1.43, kSolidPlaneCost = 1.95;
+const int kMaxPiecesPerBlock = 3;
 
 // Does the rectangle [x0, x0 + ex) x [y0, y0 + ey) of plane z hold a lattice
 // node inside the colloid (any periodic image)?  The lattice node nearest to
@@ -229,82 +231,100 @@ int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& 
     i = j;
   }
   auto piece = [](const Col& k) { return k.cost / k.n + kItemStart; };
-  if ((int)cols.size() <= slots) {
-    typedef std::pair<double, int> P;   // (piece cost, column)
-    std::priority_queue<P> heap;
-    for (int q = 0; q < (int)cols.size(); q++) heap.push(P(piece(cols[q]), q));
-    for (int used = (int)cols.size(); used < slots && !heap.empty(); used++) {
-      const int q = heap.top().second;
-      heap.pop();
-      if (cols[q].n >= (int)(cols[q].last - cols[q].first)) continue;   // one group per piece already
-      cols[q].n++;
-      heap.push(P(piece(cols[q]), q));
-    }
-  }
   struct Piece {
     size_t first, last;
     double cost;
   };
-  std::vector<Piece> pieces;
-  for (const Col& k : cols) {
-    double acc = 0.0;
-    int made = 0;
-    size_t start = k.first;
-    for (size_t g = k.first; g < k.last; g++) {
-      // a new piece starts where the cumulative cost first reaches made/n
-      if (g > k.first && made < k.n && acc >= k.cost * made / k.n - 1e-9) {
-        pieces.push_back({start, g, 0.0});
-        start = g;
+  // One plan for `target` pieces in all: returns the largest estimated
+  // load of a block and fills bins.
+  auto plan = [&](int target, std::vector<std::vector<int2>>& bins) -> double {
+    std::vector<Col> cs = cols;
+    if ((int)cs.size() <= target) {
+      typedef std::pair<double, int> P;   // (piece cost, column)
+      std::priority_queue<P> heap;
+      for (int q = 0; q < (int)cs.size(); q++) heap.push(P(piece(cs[q]), q));
+      for (int used = (int)cs.size(); used < target && !heap.empty(); used++) {
+        const int q = heap.top().second;
+        heap.pop();
+        if (cs[q].n >= (int)(cs[q].last - cs[q].first)) continue;   // one group per piece already
+        cs[q].n++;
+        heap.push(P(piece(cs[q]), q));
       }
-      if (g == k.first || g == start) made++;
-      acc += grp[g].cost;
     }
-    pieces.push_back({start, k.last, 0.0});
-  }
-  for (Piece& pc : pieces) {
-    pc.cost = kItemStart;
-    for (size_t g = pc.first; g < pc.last; g++) pc.cost += grp[g].cost;
-  }
-  // Pieces ordered by (box, first plane, column block); the q-th goes to
-  // block (q / per_die) + 8 (q % per_die), so each die takes every column
-  // block of a slab of planes and the halo rows its blocks share with their
-  // x and y neighbours pass through the same L2.  With more pieces than
-  // blocks (very large boxes), the extra pieces go longest first to the
-  // least loaded block of the same die.
-  std::stable_sort(pieces.begin(), pieces.end(), [&](const Piece& u, const Piece& v) {
-    const Grp& a = grp[u.first];
-    const Grp& b = grp[v.first];
-    if (a.b != b.b) return a.b < b.b;
-    if (a.g != b.g) return a.g < b.g;
-    return a.cb < b.cb;
-  });
-  const int per_die = slots / kXcd;
-  const int np = (int)pieces.size();
-  std::vector<std::vector<int2>> bins(slots);
-  std::vector<double> load(slots, 0.0);
-  const int per_die_pieces = (np + kXcd - 1) / kXcd;
-  for (int d = 0; d < kXcd; d++) {
-    const int q0 = std::min(np, d * per_die_pieces), q1 = std::min(np, (d + 1) * per_die_pieces);
-    std::vector<int> idx;
-    for (int q = q0; q < q1; q++) idx.push_back(q);
-    if ((int)idx.size() > per_die)
-      std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) { return pieces[u].cost > pieces[v].cost; });
-    for (int t = 0; t < (int)idx.size(); t++) {
-      int j = t;
-      if (t >= per_die) {
-        j = 0;
-        for (int m = 1; m < per_die; m++)
-          if (load[d + kXcd * m] < load[d + kXcd * j]) j = m;
+    std::vector<Piece> pieces;
+    for (const Col& k : cs) {
+      double acc = 0.0;
+      int made = 0;
+      size_t start = k.first;
+      for (size_t g = k.first; g < k.last; g++) {
+        // a new piece starts where the cumulative cost first reaches made/n
+        if (g > k.first && made < k.n && acc >= k.cost * made / k.n - 1e-9) {
+          pieces.push_back({start, g, 0.0});
+          start = g;
+        }
+        if (g == k.first || g == start) made++;
+        acc += grp[g].cost;
       }
-      const int blk = d + kXcd * j;
-      const Piece& pc = pieces[idx[t]];
-      load[blk] += pc.cost;
-      size_t i = pc.first;
-      while (i < pc.last) {
-        size_t e = std::min(pc.last, i + (size_t)(lc::kMaxGroups - 1));
-        bins[blk].push_back(lc::march_item(grp[i].b, grp[i].cb, grp[i].g, (int)(e - i)));
-        i = e;
+      pieces.push_back({start, k.last, 0.0});
+    }
+    for (Piece& pc : pieces) {
+      pc.cost = kItemStart;
+      for (size_t g = pc.first; g < pc.last; g++) pc.cost += grp[g].cost;
+    }
+    // Pieces ordered by (box, first plane, column block); the q-th goes to
+    // block (q / per_die) + 8 (q % per_die), so each die takes every column
+    // block of a slab of planes and the halo rows its blocks share with
+    // their x and y neighbours pass through the same L2.  With more pieces
+    // than blocks, a die's pieces go longest first to its least loaded block.
+    std::stable_sort(pieces.begin(), pieces.end(), [&](const Piece& u, const Piece& v) {
+      const Grp& a = grp[u.first];
+      const Grp& b = grp[v.first];
+      if (a.b != b.b) return a.b < b.b;
+      if (a.g != b.g) return a.g < b.g;
+      return a.cb < b.cb;
+    });
+    const int per_die = slots / kXcd;
+    const int np = (int)pieces.size();
+    bins.assign(slots, std::vector<int2>());
+    std::vector<double> load(slots, 0.0);
+    const int per_die_pieces = (np + kXcd - 1) / kXcd;
+    for (int d = 0; d < kXcd; d++) {
+      const int q0 = std::min(np, d * per_die_pieces), q1 = std::min(np, (d + 1) * per_die_pieces);
+      std::vector<int> idx;
+      for (int q = q0; q < q1; q++) idx.push_back(q);
+      if ((int)idx.size() > per_die)
+        std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) { return pieces[u].cost > pieces[v].cost; });
+      for (int t = 0; t < (int)idx.size(); t++) {
+        int j = t;
+        if (t >= per_die) {
+          j = 0;
+          for (int m = 1; m < per_die; m++)
+            if (load[d + kXcd * m] < load[d + kXcd * j]) j = m;
+        }
+        const int blk = d + kXcd * j;
+        const Piece& pc = pieces[idx[t]];
+        load[blk] += pc.cost;
+        size_t i = pc.first;
+        while (i < pc.last) {
+          size_t e = std::min(pc.last, i + (size_t)(lc::kMaxGroups - 1));
+          bins[blk].push_back(lc::march_item(grp[i].b, grp[i].cb, grp[i].g, (int)(e - i)));
+          i = e;
+        }
       }
+    }
+    return *std::max_element(load.begin(), load.end());
+  };
+  // One, two or three pieces per resident block: more pieces spread the
+  // colloid's expensive planes over more blocks but each adds an item start;
+  // the plan with the smallest estimated largest load wins (fewer pieces on
+  // a tie within 1%).
+  std::vector<std::vector<int2>> bins, trial;
+  double best = plan(slots, bins);
+  for (int k = 2; k <= kMaxPiecesPerBlock; k++) {
+    const double m = plan(slots * k, trial);
+    if (m < best * 0.99) {
+      best = m;
+      bins.swap(trial);
     }
   }
   // coverage: every (box, column block, group) exactly once

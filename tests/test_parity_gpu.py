@@ -205,6 +205,38 @@ def test_fp32_tiles_agree():
         assert np.linalg.norm(F - res[0][3]) <= 1e-4 * np.linalg.norm(res[0][3]) + 1e-8
 
 
+def test_march_blocks_with_several_items_agree_with_3d_tiles():
+    """512 x 512 x 16: the 32x16 and 64x8 column tiles give 512 column
+    blocks, more than the resident blocks of the persistent kernel, so every
+    block marches two or more work items (the layout of large boxes); the
+    3D-tile kernel, which has no schedule, is the reference."""
+    from paper_1102_2193_amd import lc
+    say("case: 512x512x16 fp32, marching tiles with several items per block vs the 3D tile")
+    dims = (512, 512, 16)
+    Q0 = inputs.noisy_nematic_q(*dims, inputs.Q_INIT, seed=7)
+    res = {}
+    for tile in (6, 5, 8):
+        ctx = lc.Context([dict(nx=dims[0], ny=dims[1], nz=dims[2], precision="fp32", **NEM)])
+        shape = ctx.tile_shape(tile)
+        ctx.set_tile(tile)
+        nblk, _ = ctx.launch_info()
+        if tile != 6:
+            ncb = (dims[0] // shape[0]) * (dims[1] // shape[1])
+            say("   tile %s: %d column blocks on %d blocks" % (shape, ncb, nblk))
+            assert ncb > nblk
+        ctx.set_colloid(0, (256.0, 256.0, 8.0), 5.0, anchoring="normal", W=0.01)
+        ctx.set_Q(0, Q0)
+        ctx.step(10)
+        res[tile] = (ctx.get_Q(0), ctx.get_f(0), ctx.force(0))
+        ctx.close()
+    for tile in (5, 8):
+        dq = np.max(np.abs(res[tile][0] - res[6][0]))
+        df = np.max(np.abs(res[tile][1] - res[6][1]))
+        say("   tile %d: max |dQ| %.3e |df| %.3e" % (tile, dq, df))
+        assert dq < 1e-6 and df < 1e-7
+        assert np.linalg.norm(res[tile][2] - res[6][2]) <= 1e-4 * np.linalg.norm(res[6][2]) + 1e-8
+
+
 def test_batch_equals_single_boxes_and_oracle():
     from oracle import lco
     from paper_1102_2193_amd import lc
