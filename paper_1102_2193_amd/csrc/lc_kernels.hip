@@ -820,9 +820,16 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   R h_cur[5], h_nxt[5], pz_m[3] = {(R)0, (R)0, (R)0}, pz_c[3] = {(R)0, (R)0, (R)0},
                         pz_n[3] = {(R)0, (R)0, (R)0};
   {
+    // Plane z0-1 needs only its z column, but it is computed exactly as the
+    // loop computes every plane (face rows into the P slot that plane z0+1
+    // overwrites next, the field kept live by an empty asm): the compiler
+    // fuses multiplies and adds by how their results are used, so a leaner
+    // copy could round the z column differently and make the bits depend on
+    // where work items start.
     R hdummy[5];
-    plane_stress(0, 1, 2, 1, false, hdummy, pz_m);   // plane z0-1: z column only
-    plane_stress(1, 2, 3, 0, true, h_cur, pz_c);     // plane z0
+    plane_stress(0, 1, 2, 1, true, hdummy, pz_m);   // plane z0-1
+    asm volatile("" ::"v"(hdummy[0]), "v"(hdummy[1]), "v"(hdummy[2]), "v"(hdummy[3]), "v"(hdummy[4]));
+    plane_stress(1, 2, 3, 0, true, h_cur, pz_c);    // plane z0
   }
   lds_sync();
 
