@@ -237,14 +237,18 @@ def test_march_blocks_with_several_items_agree_with_3d_tiles():
         assert np.linalg.norm(res[tile][2] - res[6][2]) <= 1e-4 * np.linalg.norm(res[6][2]) + 1e-8
 
 
-def test_same_bits_for_any_work_split():
+@pytest.mark.parametrize("anchoring,motion", [("normal", "fixed"), ("planar", "free")])
+def test_same_bits_for_any_work_split(anchoring, motion):
     """A 128^3 box with an a = 16 colloid marched alone and next to a 64^3
     box: the second box takes resident blocks, so the first box's column
     blocks are cut into different runs of planes (work items start at other
     planes next to the colloid).  Every plane's arithmetic is the same
     wherever an item starts, so the bits agree."""
     from paper_1102_2193_amd import lc
-    say("case: 128^3 fp32 a = 16 normal, alone vs beside a 64^3 box (different work items)")
+    say("case: 128^3 fp32 a = 16 %s %s, alone vs beside a 64^3 box (different work items)" % (anchoring, motion))
+    kw = dict(anchoring=anchoring, W=math.inf)
+    if motion == "free":
+        kw.update(motion=lc.FREE, fext=(0.0, 0.0, 0.05), rho_c=1.0)
     box = dict(nx=128, precision="fp32", **NEM)
     other = dict(nx=64, precision="fp32", **NEM)
     Q0 = inputs.uniaxial_q(128, 128, 128, inputs.Q_INIT, director=(0.0, 0.0, 1.0))
@@ -252,14 +256,15 @@ def test_same_bits_for_any_work_split():
     for boxes in ([box], [box, other]):
         ctx = lc.Context(boxes)
         ctx.set_tile(5)
-        ctx.set_colloid(0, (64.0, 64.0, 64.0), 16.0, anchoring="normal", W=math.inf)
+        ctx.set_colloid(0, (64.0, 64.0, 64.0), 16.0, **kw)
         ctx.set_Q(0, Q0)
         if len(boxes) > 1:
             ctx.set_Q(1, inputs.noisy_nematic_q(64, 64, 64, inputs.Q_INIT, seed=9))
         ctx.step(8)
-        res.append((ctx.get_Q(0), ctx.get_f(0), ctx.get_u(0), ctx.force(0)))
+        c = ctx.get_colloid(0)
+        res.append((ctx.get_Q(0), ctx.get_f(0), ctx.get_u(0), ctx.force(0), np.array(c.pos), np.array(c.vel)))
         ctx.close()
-    for k, name in enumerate(("Q", "f", "u", "force")):
+    for k, name in enumerate(("Q", "f", "u", "force", "position", "velocity")):
         np.testing.assert_array_equal(res[0][k], res[1][k], err_msg=name)
 
 
