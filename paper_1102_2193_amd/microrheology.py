@@ -82,16 +82,19 @@ def pull(L=128, a=16.0, f=0.09, settle=2000, steps=16000, every=500, tile=None):
 
 
 def summary(res, f, a, eta=(PARAMS["tau"] - 0.5) / 3.0):
-    """Steady speeds (mean over the last quarter of the samples), their ratio
-    and the effective viscosities of Stokes' law f = 6 pi eta_eff a v (no
-    correction for the periodic images)."""
+    """Steady speeds (mean over the last quarter of the samples), their ratio,
+    the drag coefficients of the linear drag law f = A v that the paper fits
+    (A along and across the director; it prints 63.2 and 116.9) and the
+    effective viscosities of Stokes' law f = 6 pi eta_eff a v (no correction
+    for the periodic images)."""
     def steady(series):
         v = np.array([s[1] for s in series])
         return float(np.mean(v[-max(1, len(v) // 4):]))
     va, vp = steady(res["along"]), steady(res["perp"])
     return {"v_along": va, "v_perp": vp, "ratio_along_over_perp": va / vp,
+            "drag_along": f / va, "drag_perp": f / vp,
             "eta_eff_along": f / (6 * math.pi * a * va), "eta_eff_perp": f / (6 * math.pi * a * vp),
-            "eta": eta, "paper_ratio": 1.85}
+            "eta": eta, "paper_ratio": 1.85, "paper_drag_along": 63.2, "paper_drag_perp": 116.9}
 
 
 def main(argv=None):
