@@ -197,10 +197,14 @@ int lc_get_diag(lc_ctx* ctx, int box, lc_diag* out);
  * the number of such sites.  mask may be NULL. */
 int lc_defects(lc_ctx* ctx, int box, double threshold, unsigned char* mask, long* count_out);
 
-/* Execution controls.  Tile shapes are the fused kernel's block shapes
- * (same results for every shape); lc_num_tiles / lc_tile_shape list them
- * for the context's precision, lc_set_tile picks one.  Graphs capture
- * repeated steps in a HIP graph (default on). */
+/* Execution controls.  Tile shapes are the fused kernel's block shapes:
+ * every shape does the same per-site arithmetic, and results of different
+ * shapes agree to rounding (the stress sums are grouped differently).  For
+ * one shape the bits do not depend on how a box's planes are split into
+ * work items, on the other boxes of the context or on graphs.
+ * lc_num_tiles / lc_tile_shape list the shapes for the context's
+ * precision, lc_set_tile picks one.  Graphs capture repeated steps in a
+ * HIP graph (default on). */
 int lc_num_tiles(const lc_ctx* ctx);
 int lc_tile_shape(const lc_ctx* ctx, int id, int out[3]);
 int lc_set_tile(lc_ctx* ctx, int id);
