@@ -149,7 +149,20 @@ def cpu_baseline(wl, target_s):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": L ** 3 * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "first %d steps of the %d^3 box in FP64 (%.1f s)" % (n, L, dt)}
+            "sample": "first %d steps of the %d^3 box in FP64 (%.1f s)" % (n, L, dt),
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def network_leg(L=64, reps=20):
