@@ -321,6 +321,8 @@ def main():
         out["network"] = network_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        # same box, GPU step against the FP64 oracle on the host cores
+        out["cpu_baseline"]["gpu_over_oracle"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
 
 
