@@ -216,10 +216,13 @@ int lc_use_graph(lc_ctx* ctx, int enable);
 int lc_launch_info(const lc_ctx* ctx, long out[2]);
 
 /* Run nsteps steps without graphs, with start/stop HIP events carried by
- * every fused-kernel dispatch (hipExtLaunchKernel: no separate event
- * commands between the kernels) and events on the context's stream around
- * the whole run: out[0] = mean fused-kernel time per launch (ms), out[1] =
- * mean time per step (ms), out[2] = total (ms).  Synchronises the stream. */
+ * fused-kernel dispatches (hipExtLaunchKernel: no separate event commands
+ * between the kernels) and events on the context's stream around the whole
+ * run.  A dispatch that carries events adds about 6 us between kernels on
+ * MI355X, so only every s-th dispatch does, s = ceil(nsteps / 64): at most
+ * 64 timed dispatches spread evenly over the run.  out[0] = mean
+ * fused-kernel time of the timed dispatches (ms), out[1] = mean time per
+ * step (ms), out[2] = total (ms).  Synchronises the stream. */
 int lc_time_kernel(lc_ctx* ctx, int nsteps, double out[3]);
 
 #ifdef __cplusplus

@@ -32,6 +32,7 @@ const int kNumF64 = sizeof(kTilesF64) / sizeof(kTilesF64[0]);
 
 const int kHistCap = 8192;     // force history ring (steps)
 const int kGraphSteps = 16;    // steps per captured graph (even)
+const int kTimedDispatches = 64;  // most fused-kernel dispatches lc_time_kernel times
 const int kXcd = 8;            // accelerator complex dies on MI355X
 
 std::string g_create_error;
@@ -1233,27 +1234,33 @@ int lc_time_kernel(lc_ctx* c, int nsteps, double out[3]) {
   if (!c || !out || nsteps < 1) return LC_EINVAL;
   int rc = ghost_pass(c);
   if (rc != LC_OK) return rc;
-  std::vector<hipEvent_t> ev(2 * nsteps + 2);
+  // every stride-th dispatch carries the events (the last of each run of
+  // stride), at most kTimedDispatches over the run
+  const int stride = (nsteps + kTimedDispatches - 1) / kTimedDispatches;
+  const int nt = nsteps / stride;
+  std::vector<hipEvent_t> ev(2 * nt + 2);
   for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
-  HIPCHK(c, hipEventRecord(ev[2 * nsteps], c->stream));
+  HIPCHK(c, hipEventRecord(ev[2 * nt], c->stream));
   for (int k = 0; k < nsteps; k++) {
-    hipError_t e = enqueue(c, c->cur, ev[2 * k], ev[2 * k + 1]);
+    const bool timed = (k + 1) % stride == 0;
+    const int j = (k + 1) / stride - 1;
+    hipError_t e = timed ? enqueue(c, c->cur, ev[2 * j], ev[2 * j + 1]) : enqueue(c, c->cur);
     if (e != hipSuccess) return fail(c, LC_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     c->cur ^= 1;
     c->nstep++;
   }
-  HIPCHK(c, hipEventRecord(ev[2 * nsteps + 1], c->stream));
-  HIPCHK(c, hipEventSynchronize(ev[2 * nsteps + 1]));
+  HIPCHK(c, hipEventRecord(ev[2 * nt + 1], c->stream));
+  HIPCHK(c, hipEventSynchronize(ev[2 * nt + 1]));
   double ks = 0.0;
-  for (int k = 0; k < nsteps; k++) {
+  for (int j = 0; j < nt; j++) {
     float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+    HIPCHK(c, hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
     ks += ms;
   }
   float tot = 0.f;
-  HIPCHK(c, hipEventElapsedTime(&tot, ev[2 * nsteps], ev[2 * nsteps + 1]));
+  HIPCHK(c, hipEventElapsedTime(&tot, ev[2 * nt], ev[2 * nt + 1]));
   for (auto& e : ev) hipEventDestroy(e);
-  out[0] = ks / nsteps;
+  out[0] = ks / nt;
   out[1] = tot / nsteps;
   out[2] = tot;
   return check_flag(c);
