@@ -299,13 +299,39 @@ __device__ inline void corotation(R xi, const R W[3][3], const R q5[5], R S5[5])
   }
 }
 
+// One Jacobi rotation zeroing a[P][Q] (R the third index), applied to the
+// eigenvector columns v.  The pivot is a template argument so that a and v
+// stay in registers (runtime indices would put both arrays in scratch).
+template <int P, int Q>
+__device__ inline void jacobi_rot(double (&a)[3][3], double (&v)[3][3]) {
+  constexpr int R = 3 - P - Q;
+  const double apq = a[P][Q];
+  const double th = (a[Q][Q] - a[P][P]) / (2.0 * apq);
+  const double t = fabs(th) > 1e150 ? 0.5 / th : (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+  const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+  const double arp = a[R][P], arq = a[R][Q];
+  a[P][P] -= t * apq;
+  a[Q][Q] += t * apq;
+  a[P][Q] = a[Q][P] = 0.0;
+  a[R][P] = a[P][R] = c * arp - s * arq;
+  a[R][Q] = a[Q][R] = s * arp + c * arq;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const double vkp = v[k][P], vkq = v[k][Q];
+    v[k][P] = c * vkp - s * vkq;
+    v[k][Q] = s * vkp + c * vkq;
+  }
+}
+
 // Principal axis of a symmetric 3x3 matrix (FP64): classical Jacobi, each
 // rotation annihilating the largest off-diagonal entry, until the
 // off-diagonal mass is below 1e-30 of the total; the eigenvector of the
 // largest diagonal entry (lowest index on ties).
 __device__ inline void principal_axis(const double A[3][3], double n[3]) {
   double a[3][3], v[3][3];
+#pragma unroll
   for (int i = 0; i < 3; i++)
+#pragma unroll
     for (int j = 0; j < 3; j++) {
       a[i][j] = 0.5 * (A[i][j] + A[j][i]);
       v[i][j] = i == j ? 1.0 : 0.0;
@@ -314,34 +340,21 @@ __device__ inline void principal_axis(const double A[3][3], double n[3]) {
     double o01 = fabs(a[0][1]), o02 = fabs(a[0][2]), o12 = fabs(a[1][2]);
     double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
     double tot = 0.0;
+#pragma unroll
     for (int i = 0; i < 3; i++)
+#pragma unroll
       for (int j = 0; j < 3; j++) tot += a[i][j] * a[i][j];
     if (off == 0.0 || off <= 1e-30 * tot) break;
-    int p = 0, q = 1;
-    if (o02 > o01 && o02 >= o12) { p = 0; q = 2; }
-    else if (o12 > o01 && o12 > o02) { p = 1; q = 2; }
-    const double apq = a[p][q];
-    const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
-    const double t = fabs(th) > 1e150 ? 0.5 / th
-                                      : (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-    const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-    const int r = 3 - p - q;
-    const double arp = a[r][p], arq = a[r][q];
-    a[p][p] -= t * apq;
-    a[q][q] += t * apq;
-    a[p][q] = a[q][p] = 0.0;
-    a[r][p] = a[p][r] = c * arp - s * arq;
-    a[r][q] = a[q][r] = s * arp + c * arq;
-    for (int k = 0; k < 3; k++) {
-      const double vkp = v[k][p], vkq = v[k][q];
-      v[k][p] = c * vkp - s * vkq;
-      v[k][q] = s * vkp + c * vkq;
-    }
+    if (o02 > o01 && o02 >= o12) jacobi_rot<0, 2>(a, v);
+    else if (o12 > o01 && o12 > o02) jacobi_rot<1, 2>(a, v);
+    else jacobi_rot<0, 1>(a, v);
   }
+  double best = a[0][0];
   int k = 0;
-  if (a[1][1] > a[k][k]) k = 1;
-  if (a[2][2] > a[k][k]) k = 2;
-  n[0] = v[0][k]; n[1] = v[1][k]; n[2] = v[2][k];
+  if (a[1][1] > best) { k = 1; best = a[1][1]; }
+  if (a[2][2] > best) k = 2;
+#pragma unroll
+  for (int i = 0; i < 3; i++) n[i] = k == 0 ? v[i][0] : (k == 1 ? v[i][1] : v[i][2]);
 }
 
 // Anchoring target Q^0 = S0 (n0 n0 - I/3) at a boundary solid node

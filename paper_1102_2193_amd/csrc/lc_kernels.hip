@@ -1355,9 +1355,23 @@ __global__ void __launch_bounds__(kFinishBlock)
   if (!(B.present && B.motion == 2)) return;
   const long long nt = (long long)B.ntx * B.nty * B.ntz;
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (long long k = threadIdx.x; k < nt; k += kFinishBlock) {
-    const double* p = part + B.tile_base + k;
-    for (int c = 0; c < 12; c++) v[c] += p[c * nslot];
+  // two slots per thread in flight (more would spill at 1024 threads),
+  // added in increasing slot order
+  constexpr int KS = 2;
+  for (long long k0 = 0; k0 < nt; k0 += KS * kFinishBlock) {
+    double t[KS][12];
+#pragma unroll
+    for (int j = 0; j < KS; j++) {
+      const long long k = k0 + j * kFinishBlock + threadIdx.x;
+      const double* p = part + B.tile_base + (k < nt ? k : 0);
+#pragma unroll
+      for (int c = 0; c < 12; c++) t[j][c] = p[c * nslot];
+    }
+#pragma unroll
+    for (int j = 0; j < KS; j++)
+      if (k0 + j * kFinishBlock + threadIdx.x < nt)
+#pragma unroll
+        for (int c = 0; c < 12; c++) v[c] += t[j][c];
   }
   block_sum<kFinishBlock, 12>(v, sred, sres);
   __syncthreads();

@@ -783,12 +783,23 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
                                       : lc::launch_fill<double>((double*)c->f[k], c->nsites, p[0].rho0, c->stream);
     if (e != hipSuccess) return bail(LC_EDEVICE, std::string("init: ") + hipGetErrorString(e));
   }
-  if (!march_fits(c))   // default to the first 3D-tile shape
+  if (!march_fits(c)) {   // default to the first 3D-tile shape
     for (int t = 0; t < num_tiles(c); t++)
       if (tile_shape(c, t).kind == 0) {
         c->tile = t;
         break;
       }
+  } else if (c->prec == LC_FP32) {
+    // default: the marching shape measured fastest on 128^3 boxes (32 x 16
+    // columns, groups of 8 planes); lc_set_tile or a tuner picks others
+    for (int t = 0; t < num_tiles(c); t++) {
+      const TileShape& T = tile_shape(c, t);
+      if (T.kind == 1 && T.x == 32 && T.y == 16 && T.z == 8) {
+        c->tile = t;
+        break;
+      }
+    }
+  }
   rc = layout(c);
   if (rc != LC_OK) return bail(rc, c->err);
   for (int b = 0; b < nbox; b++) {
