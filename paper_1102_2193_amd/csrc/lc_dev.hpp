@@ -222,7 +222,8 @@ __device__ inline void mol_field(const Mat<R>& p, const Stencil<R>& st, R q[3][3
     }
 }
 
-// One-constant free-energy density f (Eq. 1 with the P:96 equivalence):
+// One-constant free-energy density f (Eq. 1 in the one-constant form that
+// Sec. 2.1 states is equivalent to it):
 // bulk + K/2 |dQ|^2 + 2 K q0 Q:M + 2 K q0^2 |Q|^2.
 template <typename R, bool CHIRAL>
 __device__ inline R energy_density(const Mat<R>& p, const Stencil<R>& st, const R q[3][3], const R q2[3][3],

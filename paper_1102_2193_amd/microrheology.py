@@ -1,4 +1,4 @@
-"""Active microrheology of a colloid in a nematic (Sec. 3.1, Fig. 5).
+"""Active microrheology of a colloid in a nematic (Sec. 3.1, Fig. 3).
 
 A colloid with planar (tangential) anchoring sits in a nematic whose far
 field lies along z.  After the director field has settled around the fixed

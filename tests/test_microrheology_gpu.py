@@ -1,4 +1,4 @@
-"""Active microrheology of a colloid in a nematic (Sec. 3.1, Fig. 5).
+"""Active microrheology of a colloid in a nematic (Sec. 3.1, Fig. 3).
 
 A free colloid with planar anchoring (a = 16, W infinite) is pulled with the
 constant force f = 0.09 along and across the far-field director.  The paper

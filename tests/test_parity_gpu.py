@@ -373,23 +373,6 @@ def test_numeric_error_is_reported():
     assert e.value.code == 4
 
 
-def test_full_size_drag128_against_oracle():
-    # the benchmark's workload and launch configuration (128^3 fp32, colloid
-    # a = 8 moving along x, normal anchoring W = 0.01), a few steps compared
-    # over the whole field
-    from paper_1102_2193_amd import lc
-    say("case: 128^3 fp32 drag workload, 4 steps vs oracle")
-    L = 128
-    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=2)
-    col = dict(pos=(64.0, 64.0, 64.0), a0=8.0, anchoring="normal", W=0.01, S0=0.5, vel=(1e-3, 0, 0),
-               motion=lc.PRESCRIBED)
-    r = run_pair((L, L, L), NEM, 4, "fp32", colloid=col, Q0=Q0, hist=True)
-    check(r, 1e-5, 1e-5, tol_force=1e-3)
-    # mass is conserved to FP32 round-off at full size
-    d = r["ctx"].diag(0)
-    assert d["mass"] == pytest.approx(r["ref"].diag()["mass"], rel=1e-6)
-
-
 # ---------------------------------------------------------------------------
 # free colloid (velocity and position from the force)
 # ---------------------------------------------------------------------------

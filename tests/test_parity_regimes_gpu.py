@@ -1,0 +1,189 @@
+"""GPU parity outside the unit-relaxation regime and at the workloads' full sizes.
+
+* The paper's material parameters (Sec. 2.1: A0 = 1, K = 0.065, gamma = 3,
+  xi = 0.7, Gamma = 0.5) with BGK relaxation times tau = 0.8 (the
+  viscosity 0.1 of Sec. 3.1) and tau = 1.5.  At tau = 1 the collision
+  forgets f (f* = f_eq + S/2), so only tau != 1 exercises the relaxation
+  term and the Guo source factor 1 - 1/(2 tau).  Planar anchoring (the
+  paper's fixed Q^0), a fixed and a free colloid.  FP64 to round-off; FP32
+  to 1e-5 on Q and f, 1e-3 on the force, and element by element on the
+  deviations from rest f - w and on u (bound below).
+* The 128^3 drag workload for 100 steps, the 128^3 cholesteric workload
+  with the a = 16 colloid, and the 48-box batch against one oracle run per
+  box.
+
+FP32 bound on f - w and u, element by element relative to the largest
+reference value over fluid sites: each step rounds u = (j + F/2)/rho and
+the populations it forms to FP32 (relative 2^-24 of rho ~ 1 and of the
+force sums), and these errors add over the steps at most linearly, so
+after n steps the deviation is below c n 2^-24 relative to the largest
+value; c = 40 covers the force term, whose face differences cancel digits
+of the stress (measured: well inside it, see the printed errors).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1102_2193_amd import inputs
+from test_parity_gpu import ANCH, check, rel_inf, rel_l2, run_pair, say
+
+pytestmark = pytest.mark.gpu
+
+PAPER = dict(inputs.PAPER_CHOLESTERIC)
+W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def fp32_dev_bound(nsteps):
+    return 40.0 * nsteps * 2.0 ** -24
+
+
+def check_dev(r, bound):
+    """f - w and u element by element over fluid sites."""
+    m = r["fluid"]
+    fw, fwr = r["f"] - W19[:, None, None, None], r["fr"] - W19[:, None, None, None]
+    ef = rel_inf(fw, fwr, m)
+    eu = rel_inf(r["u"], r["ur"], m)
+    say("   rel err f - w %.3e, u %.3e (bound %.3e)" % (ef, eu, bound))
+    assert ef < bound, ("f - w", ef, bound)
+    assert eu < bound, ("u", eu, bound)
+
+
+def planar_colloid(pos, a0, motion):
+    c = dict(pos=pos, a0=a0, anchoring="planar", W=math.inf, S0=0.5)
+    if motion == "free":
+        c.update(motion=2, vel=(0.01, 0.0, -0.005), omega=(0.0, 0.001, 0.0), fext=(0.02, 0.0, -0.01), rho_c=1.0)
+    return c
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.5])
+@pytest.mark.parametrize("motion", ["fixed", "free"])
+def test_fp64_paper_parameters_tau(tau, motion):
+    say("case: 16^3 fp64 A0=1 K=0.065 tau=%g planar W=inf, %s colloid a=4, 40 steps" % (tau, motion))
+    L = 16
+    prm = dict(PAPER, tau=tau)
+    Q0 = inputs.noisy_nematic_q(L, L, L, 0.5, seed=51, noise=0.02, director=(1, 0.2, 0.4))
+    r = run_pair((L, L, L), prm, 40, "fp64", colloid=planar_colloid((7.6, 8.3, 8.1), 4.0, motion), Q0=Q0,
+                 hist=True)
+    check(r, 1e-10, 1e-12, tol_u=1e-8, tol_force=1e-8)
+    check_dev(r, 1e-9)
+    if motion == "free":
+        c, oc = r["ctx"].get_colloid(0), r["ref"].get_colloid()
+        np.testing.assert_allclose(np.array(list(c.pos) + list(c.vel)), np.array(list(oc.pos) + list(oc.vel)),
+                                   rtol=1e-9, atol=1e-13)
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.5])
+@pytest.mark.parametrize("motion", ["fixed", "free"])
+def test_fp32_paper_parameters_tau(tau, motion):
+    say("case: 32^3 fp32 A0=1 K=0.065 tau=%g planar W=inf, %s colloid a=6, 100 steps" % (tau, motion))
+    L, n = 32, 100
+    prm = dict(PAPER, tau=tau)
+    Q0 = inputs.noisy_nematic_q(L, L, L, 0.5, seed=52)
+    r = run_pair((L, L, L), prm, n, "fp32", colloid=planar_colloid((15.6, 16.3, 16.2), 6.0, motion), Q0=Q0,
+                 hist=True)
+    check(r, 1e-5, 1e-5, tol_force=1e-3)
+    check_dev(r, fp32_dev_bound(n))
+    d = r["ctx"].diag(0)
+    say("   max |u| %.3e" % d["umax"])
+    assert d["umax"] > 1e-5   # the anchoring drives a flow: the relaxation term is exercised
+
+
+def test_full_size_drag128_100_steps_every_tile():
+    """The benchmark's workload (128^3 FP32, a = 8 moving along x, normal
+    anchoring W = 0.01) with graph replay, the benchmark's stepping, for 100
+    steps against one oracle run, for every FP32 tile shape (the benchmark
+    times the one its tuner picks)."""
+    from oracle import lco
+    from paper_1102_2193_amd import lc
+    say("case: 128^3 fp32 drag workload, 100 steps vs oracle, every tile")
+    L, n = 128, 100
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=2)
+    col = dict(pos=(64.0, 64.0, 64.0), a0=8.0, anchoring="normal", W=0.01, S0=0.5, vel=(1e-3, 0, 0))
+    ref = lco.Sim(L, **inputs.NEMATIC)
+    ref.set_colloid(col["pos"], col["a0"], anchoring=ANCH["normal"], W=0.01, S0=0.5, vel=col["vel"],
+                    motion=lco.PRESCRIBED)
+    ref.set_Q(Q0)
+    hr = []
+    for _ in range(n):
+        ref.step(1)
+        hr.append(ref.force())
+    base = dict(Qr=ref.get_Q(), fr=ref.get_f(), ur=ref.get_u(), Hr=np.array(hr), fluid=~ref.solid())
+    pos_ref = np.array(ref.get_colloid().pos)
+    ntile = None
+    t = 0
+    while ntile is None or t < ntile:
+        ctx = lc.Context([dict(nx=L, precision="fp32", **inputs.NEMATIC)])
+        ntile = ctx.num_tiles()
+        ctx.set_tile(t)
+        ctx.set_colloid(0, col["pos"], col["a0"], anchoring="normal", W=0.01, S0=0.5, vel=col["vel"],
+                        motion=lc.PRESCRIBED)
+        ctx.set_Q(0, Q0)
+        ctx.step(n)
+        say("  tile %d %s" % (t, ctx.tile_shape(t)))
+        r = dict(base, Q=ctx.get_Q(0), f=ctx.get_f(0), u=ctx.get_u(0), H=ctx.force_history(0, n))
+        check(r, 1e-5, 1e-5, tol_force=1e-3)
+        check_dev(r, fp32_dev_bound(n))
+        np.testing.assert_array_equal(np.array(ctx.get_colloid(0).pos), pos_ref)
+        ctx.close()
+        t += 1
+
+
+def test_full_size_cholesteric128_a16():
+    say("case: 128^3 fp32 cholesteric p=32, fixed homeotropic a=16 W=inf, 20 steps vs oracle")
+    L, n = 128, 20
+    q0 = 2 * math.pi / 32
+    prm = dict(inputs.NEMATIC, q0=q0)
+    col = dict(pos=(64.0, 64.0, 64.0), a0=16.0, anchoring="normal", W=math.inf, S0=0.5)
+    Q0 = inputs.helix_q(L, L, L, q0, inputs.Q_INIT)
+    r = run_pair((L, L, L), prm, n, "fp32", colloid=col, Q0=Q0, hist=True)
+    check(r, 1e-5, 1e-5, tol_force=1e-3)
+    check_dev(r, fp32_dev_bound(n))
+
+
+def test_batch48_against_oracle_per_box():
+    """The 48-box batch (L in {32..64}, a in [3, 12], pitch in [16, 48]
+    commensurate, fixed homeotropic colloids) in one context for 20 steps,
+    each box against its own oracle run; the default marching tile, the
+    wide one and the 3D tile (the shapes the tuner chooses among for it)."""
+    from oracle import lco
+    from paper_1102_2193_amd import lc
+    say("case: batch of 48 cholesteric fp32 boxes, 20 steps vs one oracle run per box")
+    n = 20
+    specs = inputs.batch_boxes(4)
+    boxes = [dict(nx=s["L"], precision="fp32", **dict(inputs.NEMATIC, q0=s["q0"])) for s in specs]
+    Qs = [inputs.helix_q(s["L"], s["L"], s["L"], s["q0"], inputs.Q_INIT) for s in specs]
+    refs = []
+    for b, s in enumerate(specs):
+        L, c = s["L"], s["L"] / 2.0
+        ref = lco.Sim(L, **dict(inputs.NEMATIC, q0=s["q0"]))
+        ref.set_colloid((c, c, c), s["a"], anchoring=ANCH["normal"], W=math.inf)
+        ref.set_Q(Qs[b])
+        hr = []
+        for _ in range(n):
+            ref.step(1)
+            hr.append(ref.force())
+        refs.append((ref.get_Q(), ref.get_f(), np.array(hr), ~ref.solid()))
+        del ref
+    say("   oracle done: %d sites" % sum(s["L"] ** 3 for s in specs))
+    for shape in ((32, 16, 8), (64, 8, 8), (16, 8, 2)):
+        ctx = lc.Context(boxes)
+        tile = [t for t in range(ctx.num_tiles()) if tuple(ctx.tile_shape(t)) == shape][0]
+        ctx.set_tile(tile)
+        for b, s in enumerate(specs):
+            c = s["L"] / 2.0
+            ctx.set_colloid(b, (c, c, c), s["a"], anchoring="normal", W=math.inf)
+            ctx.set_Q(b, Qs[b])
+        ctx.step(n)
+        worst = 0.0
+        for b, (Qr, fr, Hr, m) in enumerate(refs):
+            Q, f = ctx.get_Q(b), ctx.get_f(b)
+            eq = max(rel_inf(Q, Qr, m), rel_l2(Q, Qr, m))
+            ef = max(rel_inf(f, fr, m), rel_l2(f, fr, m))
+            eF = np.linalg.norm(ctx.force_history(b, n) - Hr)
+            bound = max(1e-3 * np.linalg.norm(Hr), 1e-6 * math.sqrt(n))
+            worst = max(worst, eq, ef)
+            assert eq < 1e-5 and ef < 1e-5, (shape, b, eq, ef)
+            assert eF <= bound, (shape, b, eF, bound)
+        say("   tile %s: worst rel err of Q and f over the 48 boxes %.3e" % (shape, worst))
+        ctx.close()
