@@ -178,6 +178,10 @@ int lc_set_state(lc_ctx* ctx, const void* buf, size_t bytes);
  * Asynchronous; replays a captured HIP graph when graphs are enabled. */
 int lc_step(lc_ctx* ctx, int nsteps);
 int lc_sync(lc_ctx* ctx);       /* wait for the stream; LC_ENUMERIC if flagged */
+/* Capture the step graph now (graphs on and none captured for the current
+ * layout), so that the next lc_step does not pay for the capture.  Queues
+ * no work; a no-op when graphs are off or already captured. */
+int lc_prepare(lc_ctx* ctx);
 long lc_get_nstep(lc_ctx* ctx); /* steps taken (host count) */
 
 /* Colloid force and torque of the last step: F_bbl[3], F_stress[3],

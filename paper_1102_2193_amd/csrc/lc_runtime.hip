@@ -1096,6 +1096,12 @@ int lc_step(lc_ctx* c, int nsteps) {
   return LC_OK;
 }
 
+int lc_prepare(lc_ctx* c) {
+  if (!c) return LC_EINVAL;
+  if (!c->use_graph || c->graph_ok) return LC_OK;
+  return build_graph(c);
+}
+
 int lc_sync(lc_ctx* c) {
   if (!c) return LC_EINVAL;
   return check_flag(c);

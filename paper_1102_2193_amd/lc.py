@@ -24,7 +24,7 @@ STATUS = {0: "LC_OK", 1: "LC_EINVAL", 2: "LC_ENOMEM", 3: "LC_EDEVICE", 4: "LC_EN
 EXPORTS = [
     "lc_create", "lc_create_batch", "lc_destroy", "lc_last_error", "lc_buffer_bytes", "lc_bind_buffers",
     "lc_set_colloid", "lc_get_colloid", "lc_set_Q", "lc_set_f", "lc_set_u", "lc_get_Q", "lc_get_f",
-    "lc_get_u", "lc_state_bytes", "lc_get_state", "lc_set_state", "lc_step", "lc_sync", "lc_get_nstep",
+    "lc_get_u", "lc_state_bytes", "lc_get_state", "lc_set_state", "lc_step", "lc_sync", "lc_get_nstep", "lc_prepare",
     "lc_get_force", "lc_get_force_history",
     "lc_history_capacity", "lc_get_diag", "lc_defects", "lc_num_tiles", "lc_tile_shape", "lc_set_tile",
     "lc_get_tile", "lc_use_graph", "lc_launch_info", "lc_time_kernel",
@@ -88,6 +88,7 @@ def load():
     L.lc_set_state.argtypes = [vp, vp, ctypes.c_size_t]
     L.lc_step.argtypes = [vp, ip]
     L.lc_sync.argtypes = [vp]
+    L.lc_prepare.argtypes = [vp]
     L.lc_get_nstep.argtypes = [vp]
     L.lc_get_nstep.restype = ctypes.c_long
     L.lc_get_force_history.argtypes = [vp, ip, ip, dp]
@@ -250,6 +251,10 @@ class Context:
 
     def sync(self):
         self._chk(self._L.lc_sync(self._h))
+
+    def prepare(self):
+        """Capture the step graph ahead of the next step (lc_prepare)."""
+        self._chk(self._L.lc_prepare(self._h))
 
     @property
     def nstep(self):
