@@ -196,6 +196,18 @@ int lc_history_capacity(const lc_ctx* ctx);
 
 int lc_get_diag(lc_ctx* ctx, int box, lc_diag* out);
 
+/* lc_get_diag for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same summation order, so the same bits, but the
+ * per-block partials and totals live in a static device array of 1 MiB per
+ * GPU, held until the process ends, instead of memory the context
+ * allocates; the call allocates nothing.  Boxes of more than 5,591,040
+ * sites (21,840 blocks of 256) do not fit: LC_EINVAL with a message.  Every
+ * call on one GPU uses that GPU's one array, so calls that overlap on one
+ * GPU (several host threads, or contexts on different streams) race and
+ * must be serialised by the caller.  Synchronises the context's stream. */
+int lc_get_diag_noalloc(lc_ctx* ctx, int box, lc_diag* out);
+
 /* Defect sites (Sec. 3.1 footnote: order-parameter isosurface): mask[s] = 1
  * where a fluid site has (3/2) lambda_max(Q) < threshold; count_out gets
  * the number of such sites.  mask may be NULL. */

@@ -1586,6 +1586,24 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) out[6LL * blockIdx.x + 5] = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
 }
 
+// Totals of the diagnostics partials of nb blocks (6 doubles each): thread
+// c < 5 adds component c over the blocks in block order starting from zero,
+// thread 5 takes the maximum of component 5 -- the order lc_get_diag uses
+// on the host, so both give the same bits.
+__global__ void __launch_bounds__(64)
+    k_diag_total(const double* __restrict__ part, long long nb, double* __restrict__ out6) {
+  const int c = threadIdx.x;
+  if (c >= 6) return;
+  double s = 0.0;
+#pragma unroll 8
+  for (long long k = 0; k < nb; k++) {
+    const double v = part[6 * k + c];
+    if (c < 5) s += v;
+    else s = s < v ? v : s;
+  }
+  out6[c] = s;
+}
+
 // Largest eigenvalue of a symmetric traceless 3x3 matrix (trigonometric
 // solution of the characteristic cubic).
 __device__ inline double lambda_max(const double q[3][3]) {
@@ -1713,6 +1731,11 @@ template <typename R>
 hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const StepPtrs<R>& a, double* out,
                        hipStream_t s) {
   k_diag<R><<<(unsigned)((nsite + 255) / 256), 256, 0, s>>>(boxes, box, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_total(const double* part, long long nb, double* out6, hipStream_t s) {
+  k_diag_total<<<1, 64, 0, s>>>(part, nb, out6);
   return hipGetLastError();
 }
 

@@ -103,6 +103,10 @@ hipError_t launch_finish(int nbox, int nblk, BoxDev* boxes, int par, const doubl
 template <typename R>
 hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const StepPtrs<R>& a, double* out,
                        hipStream_t s);
+// Totals of nb diagnostics partials (6 doubles each, as written by
+// launch_diag) into out6: sums of components 0..4 in block order, maximum of
+// component 5.
+hipError_t launch_diag_total(const double* part, long long nb, double* out6, hipStream_t s);
 template <typename R>
 hipError_t launch_defects(const BoxDev* boxes, int box, long long nsite, const R* Q, long long NS, double thr,
                           unsigned char* mask, unsigned long long* count, int par, hipStream_t s);

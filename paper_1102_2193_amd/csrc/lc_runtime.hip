@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <vector>
@@ -37,10 +38,49 @@ const int kXcd = 8;            // accelerator complex dies on MI355X
 
 std::string g_create_error;
 
+// Diagnostics without allocation (lc_get_diag_noalloc): the partials of the
+// diagnostics kernel, 6 doubles per block of 256 sites, and the six totals
+// live in one static device array per GPU.
+constexpr long long kNoallocDiagBlocks = 21840;   // boxes of up to 5,591,040 sites
+constexpr long long kNoallocTotals = 6 * kNoallocDiagBlocks;
+constexpr long long kScratchDoubles = kNoallocTotals + 8;   // 1.0 MiB
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// Scratch of lc_get_diag_noalloc (sizes above).  Each GPU the library runs
+// on holds its own copy until the process ends.  In host code this name is
+// not a device address: kernels and copies take the per-device address that
+// scratch_address() obtains with hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+hipError_t scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct lc_ctx {
   int nbox = 0;
+  int dev = 0;                  // device current at creation
+  double* scratch_dev = nullptr;  // that device's address of the static scratch
+  std::string scratch_err;        // why scratch_dev is null
   int prec = LC_FP32;
   size_t esz = 4;
   std::vector<lc_params> prm;
@@ -754,9 +794,11 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
   }
   const size_t nf = 19 * c->nsites * c->esz, nq = 5 * c->nsites * c->esz, nu = 3 * c->nsites * c->esz;
   for (int k = 0; k < 2; k++) {
-    if (hipMalloc(&c->f[k], nf) != hipSuccess || hipMalloc(&c->Q[k], nq) != hipSuccess ||
-        hipMalloc(&c->u[k], nu) != hipSuccess)
-      return bail(LC_ENOMEM, "device allocation of the fields failed");
+    hipError_t e = hipMalloc(&c->f[k], nf);
+    if (e == hipSuccess) e = hipMalloc(&c->Q[k], nq);
+    if (e == hipSuccess) e = hipMalloc(&c->u[k], nu);
+    if (e != hipSuccess)
+      return bail(LC_ENOMEM, std::string("device allocation of the fields failed: ") + hipGetErrorString(e));
   }
   if (hipMalloc(&c->dbox, sizeof(BoxDev) * nbox) != hipSuccess ||
       hipMalloc(&c->dforce, sizeof(double) * 12 * nbox) != hipSuccess ||
@@ -766,6 +808,18 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
       hipMalloc(&c->dfsum, sizeof(double) * 12 * nbox) != hipSuccess ||
       hipMalloc(&c->dflag, sizeof(int)) != hipSuccess)
     return bail(LC_ENOMEM, "device allocation failed");
+  {
+    // the device the fields were allocated on (current), and its copy of the
+    // static scratch
+    // static scratch (only lc_get_diag_noalloc needs it: a failure here is
+    // reported by that call)
+    hipError_t e = hipGetDevice(&c->dev);
+    if (e == hipSuccess) e = scratch_address(c->dev, &c->scratch_dev);
+    if (e != hipSuccess) {
+      c->scratch_dev = nullptr;
+      c->scratch_err = std::string("device / static scratch address: ") + hipGetErrorString(e);
+    }
+  }
   hipMemsetAsync(c->dforce, 0, sizeof(double) * 12 * nbox, c->stream);
   hipMemsetAsync(c->dhist, 0, sizeof(double) * 12 * (size_t)kHistCap * nbox, c->stream);
   hipMemsetAsync(c->dcount, 0, sizeof(long long) * nbox, c->stream);
@@ -1176,6 +1230,45 @@ int lc_get_diag(lc_ctx* c, int box, lc_diag* out) {
     for (int a = 0; a < 3; a++) out->momentum[a] += h[6 * k + 2 + a];
     out->umax = std::max(out->umax, h[6 * k + 5]);
   }
+  return LC_OK;
+}
+
+int lc_get_diag_noalloc(lc_ctx* c, int box, lc_diag* out) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!out) return fail(c, LC_EINVAL, "out is NULL");
+  const long long n = box_sites(c->prm[box]);
+  const long long nb = (n + 255) / 256;
+  if (nb > kNoallocDiagBlocks)
+    return fail(c, LC_EINVAL, "box of " + std::to_string(n) + " sites exceeds the static diagnostics scratch (at most " +
+                                  std::to_string(kNoallocDiagBlocks * 256) + " sites); use lc_get_diag");
+  if (!c->scratch_dev) return fail(c, LC_EDEVICE, c->scratch_err);
+  if ((rc = check_flag(c)) != LC_OK) return rc;
+  hipError_t e;
+  if (c->prec == LC_FP32) {
+    lc::StepPtrs<float> a = ptrs<float>(c, c->cur);
+    if (c->any_colloid &&
+        (e = lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->cur,
+                                     c->stream)) != hipSuccess)
+      return fail(c, LC_EDEVICE, std::string("ghost launch: ") + hipGetErrorString(e));
+    e = lc::launch_diag<float>(c->dbox, box, n, a, c->scratch_dev, c->stream);
+  } else {
+    lc::StepPtrs<double> a = ptrs<double>(c, c->cur);
+    if (c->any_colloid &&
+        (e = lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->cur,
+                                      c->stream)) != hipSuccess)
+      return fail(c, LC_EDEVICE, std::string("ghost launch: ") + hipGetErrorString(e));
+    e = lc::launch_diag<double>(c->dbox, box, n, a, c->scratch_dev, c->stream);
+  }
+  HIPCHK(c, e);
+  HIPCHK(c, lc::launch_diag_total(c->scratch_dev, nb, c->scratch_dev + kNoallocTotals, c->stream));
+  double tot[6];
+  HIPCHK(c, hipMemcpyAsync(tot, c->scratch_dev + kNoallocTotals, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out->free_energy = tot[0];
+  out->mass = tot[1];
+  for (int a = 0; a < 3; a++) out->momentum[a] = tot[2 + a];
+  out->umax = tot[5];
   return LC_OK;
 }
 

@@ -26,7 +26,7 @@ EXPORTS = [
     "lc_set_colloid", "lc_get_colloid", "lc_set_Q", "lc_set_f", "lc_set_u", "lc_get_Q", "lc_get_f",
     "lc_get_u", "lc_state_bytes", "lc_get_state", "lc_set_state", "lc_step", "lc_sync", "lc_get_nstep", "lc_prepare",
     "lc_get_force", "lc_get_force_history",
-    "lc_history_capacity", "lc_get_diag", "lc_defects", "lc_num_tiles", "lc_tile_shape", "lc_set_tile",
+    "lc_history_capacity", "lc_get_diag", "lc_get_diag_noalloc", "lc_defects", "lc_num_tiles", "lc_tile_shape", "lc_set_tile",
     "lc_get_tile", "lc_use_graph", "lc_launch_info", "lc_time_kernel",
 ]
 
@@ -69,6 +69,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("liblc.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # The library runs on the HIP runtime torch has loaded (same soname).  Let
+    # torch initialise it before the library's code objects (and its static
+    # device array) are registered with it: loaded first, the library's own
+    # calls later failed with "no ROCm-capable device" while torch's worked.
+    import torch
+    torch.cuda.is_available()
     L = ctypes.CDLL(LIB_PATH)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
     L.lc_create.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
@@ -94,6 +100,7 @@ def load():
     L.lc_get_force_history.argtypes = [vp, ip, ip, dp]
     L.lc_history_capacity.argtypes = [vp]
     L.lc_get_diag.argtypes = [vp, ip, ctypes.POINTER(Diag)]
+    L.lc_get_diag_noalloc.argtypes = [vp, ip, ctypes.POINTER(Diag)]
     L.lc_defects.argtypes = [vp, ip, ctypes.c_double, ctypes.POINTER(ctypes.c_ubyte),
                              ctypes.POINTER(ctypes.c_long)]
     L.lc_num_tiles.argtypes = [vp]
