@@ -288,9 +288,13 @@ int lco_create(const lco_params* p, lco_sim** out) {
   if (p->nx < 4 || p->ny < 4 || p->nz < 4) return LCO_EINVAL;
   if (!(p->tau > 0.5) || !(p->rho0 > 0.0) || !(p->Gamma >= 0.0) || !(p->K >= 0.0))
     return LCO_EINVAL;
+  if (p->advection < 0 || p->advection > 3) return LCO_EINVAL;
+  if (p->stencil != 0 && p->stencil != 7 && p->stencil != 27) return LCO_EINVAL;
   lco_sim* s = (lco_sim*)calloc(1, sizeof(lco_sim));
   if (!s) return LCO_ENOMEM;
   s->p = *p;
+  if (s->p.advection == 0) s->p.advection = 1;
+  if (s->p.stencil == 0) s->p.stencil = 7;
   s->N = (long)p->nx * p->ny * p->nz;
   long N = s->N;
   s->f = (double*)calloc(19 * N, sizeof(double));
@@ -429,8 +433,18 @@ long lco_get_nstep(const lco_sim* s) { return s ? s->nstep : -1; }
 /* step pieces                                                          */
 /* ------------------------------------------------------------------ */
 
+/* A solid node within reach of a fluid node's Q stencil: a fluid face
+ * neighbour (7-point stencil) or a fluid node among its 26 neighbours
+ * (27-point stencil). */
 static int is_boundary_solid(const lco_sim* s, int x, int y, int z) {
   if (!s->solid[sidx(s, x, y, z)]) return 0;
+  if (s->p.stencil == 27) {
+    for (int dz = -1; dz <= 1; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++)
+          if ((dx || dy || dz) && !s->solid[sidx(s, x + dx, y + dy, z + dz)]) return 1;
+    return 0;
+  }
   static const int E[6][3] = {{1,0,0},{-1,0,0},{0,1,0},{0,-1,0},{0,0,1},{0,0,-1}};
   for (int k = 0; k < 6; k++)
     if (!s->solid[sidx(s, x + E[k][0], y + E[k][1], z + E[k][2])]) return 1;
@@ -493,13 +507,28 @@ static void ghost_all(lco_sim* s, double* Q) {
     if (!is_boundary_solid(s, x, y, z)) continue;
     double qbar[3][3] = {{0}}, qn[3][3], q0[3][3], qs[3][3];
     int nf = 0;
-    for (int k = 0; k < 6; k++) {
-      long j = sidx(s, x + E[k][0], y + E[k][1], z + E[k][2]);
-      if (s->solid[j]) continue;
-      full_from5(Q, N, j, qn);
-      for (int a = 0; a < 3; a++)
-        for (int b = 0; b < 3; b++) qbar[a][b] += qn[a][b];
-      nf++;
+    if (s->p.stencil == 27) {
+      /* the mean over the fluid nodes among the 26 neighbours */
+      for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+          for (int dx = -1; dx <= 1; dx++) {
+            if (!(dx || dy || dz)) continue;
+            long j = sidx(s, x + dx, y + dy, z + dz);
+            if (s->solid[j]) continue;
+            full_from5(Q, N, j, qn);
+            for (int a = 0; a < 3; a++)
+              for (int b = 0; b < 3; b++) qbar[a][b] += qn[a][b];
+            nf++;
+          }
+    } else {
+      for (int k = 0; k < 6; k++) {
+        long j = sidx(s, x + E[k][0], y + E[k][1], z + E[k][2]);
+        if (s->solid[j]) continue;
+        full_from5(Q, N, j, qn);
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) qbar[a][b] += qn[a][b];
+        nf++;
+      }
     }
     for (int a = 0; a < 3; a++)
       for (int b = 0; b < 3; b++) qbar[a][b] /= nf;
@@ -526,6 +555,37 @@ static void stencil(const lco_sim* s, const double* Q, int x, int y, int z,
                     double q[3][3], double dq[3][3][3], double lap[3][3]) {
   long N = s->N;
   full_from5(Q, N, sidx(s, x, y, z), q);
+  if (s->p.stencil == 27) {
+    /* isotropic 27-point operators (the variant of the "same stencil"
+     * reading): D_g Q = 3 sum_i w_i c_ig Q(x + c_i) with the D3Q27 weights
+     * 2/27 (faces), 1/54 (edges), 1/216 (corners), whose second moment is
+     * 1/3; Laplacian (14 sum_faces + 3 sum_edges + sum_corners - 128 Q)/30,
+     * exact on quadratics with an isotropic leading error */
+    for (int g = 0; g < 3; g++)
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) dq[g][a][b] = 0.0;
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) lap[a][b] = 0.0;
+    for (int dz = -1; dz <= 1; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+          const int n = abs(dx) + abs(dy) + abs(dz);
+          if (n == 0) continue;
+          const double wg = n == 1 ? 2.0 / 27.0 : (n == 2 ? 1.0 / 54.0 : 1.0 / 216.0);
+          const double wl = n == 1 ? 14.0 : (n == 2 ? 3.0 : 1.0);
+          const int c[3] = {dx, dy, dz};
+          double qn[3][3];
+          full_from5(Q, N, sidx(s, x + dx, y + dy, z + dz), qn);
+          for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+              lap[a][b] += wl * qn[a][b];
+              for (int g = 0; g < 3; g++) dq[g][a][b] += 3.0 * wg * c[g] * qn[a][b];
+            }
+        }
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) lap[a][b] = (lap[a][b] - 128.0 * q[a][b]) / 30.0;
+    return;
+  }
   for (int a = 0; a < 3; a++)
     for (int b = 0; b < 3; b++) lap[a][b] = -6.0 * q[a][b];
   for (int g = 0; g < 3; g++) {
@@ -702,6 +762,51 @@ static void site_velocity(const lco_sim* s, int x, int y, int z, double u[3]) {
   }
 }
 
+/* Advective flux through the face between node (x,y,z) and its neighbour
+ * at +e_b (Sec. 2.2): ubar Q_face with ubar the mean of the two nodes'
+ * velocities and Q_face taken upwind; zero when either node is solid.
+ * Orders of the upwind value: 1 the upwind node; 2 linear extrapolation
+ * from the two upwind nodes, (3 Q_up - Q_upup)/2; 3 upwind-biased,
+ * (2 Q_down + 5 Q_up - Q_upup)/6.  A face whose wider stencil reaches a
+ * solid node takes the first-order value. */
+static void face_flux(const lco_sim* s, int x, int y, int z, int b, double phi[3][3]) {
+  long N = s->N;
+  int e[3] = {0, 0, 0};
+  e[b] = 1;
+  for (int a = 0; a < 3; a++)
+    for (int c = 0; c < 3; c++) phi[a][c] = 0.0;
+  long j0 = sidx(s, x, y, z), j1 = sidx(s, x + e[0], y + e[1], z + e[2]);
+  if (s->solid[j0] || s->solid[j1]) return;
+  double u0[3], u1[3];
+  site_velocity(s, x, y, z, u0);
+  site_velocity(s, x + e[0], y + e[1], z + e[2], u1);
+  double uf = 0.5 * (u0[b] + u1[b]);
+  /* along the flow: upwind node, the one before it, the downwind node */
+  long jup, jupup, jdown;
+  if (uf >= 0.0) {
+    jup = j0; jdown = j1; jupup = sidx(s, x - e[0], y - e[1], z - e[2]);
+  } else {
+    jup = j1; jdown = j0; jupup = sidx(s, x + 2 * e[0], y + 2 * e[1], z + 2 * e[2]);
+  }
+  int order = s->p.advection;
+  if (order > 1 && s->solid[jupup]) order = 1;
+  double qu[3][3], qd[3][3], quu[3][3], qf[3][3];
+  full_from5(s->Q, N, jup, qu);
+  if (order == 1) {
+    for (int a = 0; a < 3; a++)
+      for (int c = 0; c < 3; c++) qf[a][c] = qu[a][c];
+  } else {
+    full_from5(s->Q, N, jupup, quu);
+    full_from5(s->Q, N, jdown, qd);
+    for (int a = 0; a < 3; a++)
+      for (int c = 0; c < 3; c++)
+        qf[a][c] = order == 2 ? (3.0 * qu[a][c] - quu[a][c]) / 2.0
+                              : (2.0 * qd[a][c] + 5.0 * qu[a][c] - quu[a][c]) / 6.0;
+  }
+  for (int a = 0; a < 3; a++)
+    for (int c = 0; c < 3; c++) phi[a][c] = uf * qf[a][c];
+}
+
 /* Beris-Edwards update at fluid nodes, forward Euler with dt = 1:
  * Q^{n+1} = Q^n - div(u Q) + S(W, Q^n) + Gamma H^n.  Velocity gradient by
  * central differences with v + omega x r at solid nodes; advective fluxes
@@ -734,21 +839,9 @@ static void be_update(lco_sim* s) {
         site_velocity(s, x - e[0], y - e[1], z - e[2], um);
         for (int a = 0; a < 3; a++) W[a][b] = 0.5 * (up[a] - um[a]);
         /* advective fluxes through the + and - faces along b */
-        long jp = sidx(s, x + e[0], y + e[1], z + e[2]);
-        long jm = sidx(s, x - e[0], y - e[1], z - e[2]);
-        double phip[3][3] = {{0}}, phim[3][3] = {{0}}, qo[3][3];
-        if (!s->solid[jp]) {
-          double uf = 0.5 * (u0[b] + up[b]);
-          if (uf >= 0.0) { for (int a = 0; a < 3; a++) for (int c = 0; c < 3; c++) qo[a][c] = q[a][c]; }
-          else full_from5(s->Q, N, jp, qo);
-          for (int a = 0; a < 3; a++) for (int c = 0; c < 3; c++) phip[a][c] = uf * qo[a][c];
-        }
-        if (!s->solid[jm]) {
-          double uf = 0.5 * (um[b] + u0[b]);
-          if (uf >= 0.0) full_from5(s->Q, N, jm, qo);
-          else { for (int a = 0; a < 3; a++) for (int c = 0; c < 3; c++) qo[a][c] = q[a][c]; }
-          for (int a = 0; a < 3; a++) for (int c = 0; c < 3; c++) phim[a][c] = uf * qo[a][c];
-        }
+        double phip[3][3], phim[3][3];
+        face_flux(s, x, y, z, b, phip);
+        face_flux(s, x - e[0], y - e[1], z - e[2], b, phim);
         for (int a = 0; a < 3; a++)
           for (int c = 0; c < 3; c++) dQ[a][c] -= phip[a][c] - phim[a][c];
       }

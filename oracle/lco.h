@@ -40,6 +40,18 @@ typedef struct lco_params {
   double rho0;            /* reference density (initial fluid, BBL, new fluid) */
   double A0, gamma, K, q0, xi, Gamma;   /* Eq. (1), Eq. (2), Eq. (4) */
   double body_force[3];   /* uniform force density on fluid nodes */
+  /* Variants of two readings of Sec. 2.2 (0 selects the default):
+   * advection: order of the upwind face values of the advective flux,
+   *   1 (first order, default), 2 (second-order upwind: linear
+   *   extrapolation from the two upwind nodes), 3 (third-order
+   *   upwind-biased: two upwind nodes and the downwind one); a face whose
+   *   wider stencil reaches a solid node uses first order;
+   * stencil: finite-difference stencil of the Q derivatives, 7 (central
+   *   first derivatives and compact Laplacian, default) or 27 (isotropic
+   *   27-point gradient and Laplacian; ghost Q then goes to every solid node
+   *   with a fluid node among its 26 neighbours, from their mean). */
+  int advection;
+  int stencil;
 } lco_params;
 
 typedef struct lco_colloid {

@@ -26,7 +26,8 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("A0", ctypes.c_double), ("gamma", ctypes.c_double), ("K", ctypes.c_double),
                 ("q0", ctypes.c_double), ("xi", ctypes.c_double), ("Gamma", ctypes.c_double),
-                ("body_force", ctypes.c_double * 3)]
+                ("body_force", ctypes.c_double * 3),
+                ("advection", ctypes.c_int), ("stencil", ctypes.c_int)]
 
 
 class Colloid(ctypes.Structure):
@@ -78,8 +79,9 @@ def _dp(a):
 
 
 def make_params(nx, ny, nz, hydro=1, tau=1.0, rho0=1.0, A0=0.01, gamma=3.0, K=0.01, q0=0.0,
-                xi=0.7, Gamma=0.5, body_force=(0.0, 0.0, 0.0)):
+                xi=0.7, Gamma=0.5, body_force=(0.0, 0.0, 0.0), advection=1, stencil=7):
     p = Params()
+    p.advection, p.stencil = advection, stencil
     p.nx, p.ny, p.nz, p.hydro = nx, ny, nz, hydro
     p.tau, p.rho0, p.A0, p.gamma, p.K, p.q0, p.xi, p.Gamma = tau, rho0, A0, gamma, K, q0, xi, Gamma
     for a in range(3):
