@@ -68,6 +68,19 @@ typedef struct lc_params {
   double tau, rho0;
   double A0, gamma, K, q0, xi, Gamma;
   double body_force[3];
+  /* Variants of two readings of Sec. 2.2 (0 selects the default; both need
+   * a 3D-tile shape of the fused kernel, which a context with a variant box
+   * gets by default):
+   * advection: order of the upwind face values of the advective flux of Q:
+   *   1 first order (default), 2 second-order upwind (3 Q_up - Q_upup)/2,
+   *   3 third-order upwind-biased (2 Q_down + 5 Q_up - Q_upup)/6; a face whose
+   *   wider stencil reaches a solid node takes the first-order value;
+   * stencil: 7 (central first derivatives and compact Laplacian, default)
+   *   or 27 (isotropic 27-point gradient and Laplacian; ghost Q then goes to
+   *   every solid node with a fluid node among its 26 neighbours, from the
+   *   mean of those). */
+  int advection;
+  int stencil;
 } lc_params;
 
 /* One spherical colloid (Sec. 2.2): nodes with |x - R|^2 < a0^2 are solid.

@@ -23,6 +23,7 @@ struct BoxDev {
   double tau, rho0, A0, gamma, K, q0, xi, Gamma;
   double itau, fsrc;                     // 1/tau and 1 - 1/(2 tau)
   double body[3];
+  int adv, st27;                         // advection order (1..3); 27-point Q stencil
   int present, motion, anchoring, pad_;
   // colloid centre at the start of a step, by the step's buffer parity: the
   // post-step kernel of a step writes the other slot
@@ -178,6 +179,42 @@ __device__ inline void stencil5(const R c5[5], const R xp[5], const R xm[5], con
     st.d[1][k] = (R)0.5 * (yp[k] - ym[k]);
     st.d[2][k] = (R)0.5 * (zp[k] - zm[k]);
     st.lap[k] = ((xp[k] + xm[k]) + (yp[k] + ym[k])) + (zp[k] + zm[k]) - (R)6 * c5[k];
+  }
+}
+
+// Isotropic 27-point variant of the stencil (the alternative reading of
+// "the same stencil", Sec. 2.2): D_g Q = 3 sum_i w_i c_ig Q(x + c_i) with the
+// D3Q27 weights 2/27 (faces), 1/54 (edges), 1/216 (corners), whose second
+// moment is 1/3, and the Laplacian (14 sum_faces + 3 sum_edges + sum_corners
+// - 128 Q)/30.  q points at the node in component 0 of a Q box with
+// component stride cs, row stride sy and plane stride sz.
+template <typename R>
+__device__ inline void stencil27(const R* q, int cs, int sy, int sz, Stencil<R>& st) {
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    const R* p = q + k * cs;
+    R lap = (R)0, d0 = (R)0, d1 = (R)0, d2 = (R)0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; dz++)
+#pragma unroll
+      for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+        for (int dx = -1; dx <= 1; dx++) {
+          const int n = (dx != 0) + (dy != 0) + (dz != 0);
+          if (n == 0) continue;
+          const R v = p[dx + dy * sy + dz * sz];
+          const R wl = n == 1 ? (R)14 : (n == 2 ? (R)3 : (R)1);
+          const R wg = n == 1 ? (R)(3.0 * 2.0 / 27.0) : (n == 2 ? (R)(3.0 / 54.0) : (R)(3.0 / 216.0));
+          lap += wl * v;
+          if (dx) d0 += (dx > 0 ? wg : -wg) * v;
+          if (dy) d1 += (dy > 0 ? wg : -wg) * v;
+          if (dz) d2 += (dz > 0 ? wg : -wg) * v;
+        }
+    st.q[k] = p[0];
+    st.d[0][k] = d0;
+    st.d[1][k] = d1;
+    st.d[2][k] = d2;
+    st.lap[k] = (lap - (R)128 * p[0]) / (R)30;
   }
 }
 

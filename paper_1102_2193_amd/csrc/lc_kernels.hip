@@ -219,6 +219,7 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
   // a single conditional correction wraps every halo coordinate
   const bool wide = nx >= TX + 2 && ny >= TY + 2 && nz >= TZ + 2;
   const Mat<R> mp(B);
+  const int adv = B.adv;
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
   const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
@@ -269,9 +270,12 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
   const int qc = (lz + 2) * QSZ + (ly + 2) * QSY + (lx + 2);
   const bool fluid = !sS[qc];
   R h5[5];
+  const bool st27 = B.st27 != 0;
   {
     Stencil<R> st;
-    {
+    if (st27) {
+      stencil27(sQ + qc, QN, QSY, QSZ, st);
+    } else {
       R c5[5], xp[5], xm[5], yp[5], ym[5], zp[5], zm[5];
 #pragma unroll
       for (int c = 0; c < 5; c++) {
@@ -315,7 +319,9 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
       const int qh = (pz + 1) * QSZ + (py + 1) * QSY + (px + 1);
       if (near && sS[qh]) continue;
       Stencil<R> st;
-      {
+      if (st27) {
+        stencil27(sQ + qh, QN, QSY, QSZ, st);
+      } else {
         R c5[5], xp[5], xm[5], yp[5], ym[5], zp[5], zm[5];
 #pragma unroll
         for (int c = 0; c < 5; c++) {
@@ -431,11 +437,37 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
         }
         const bool fp = !solid_nb[2 * b + 1], fm = !solid_nb[2 * b + 2];
         const R ufp = (R)0.5 * (u0[b] + up[b]), ufm = (R)0.5 * (um[b] + u0[b]);
+        if (adv == 1) {
 #pragma unroll
-        for (int c = 0; c < 5; c++) {
-          const R phip = fp ? ufp * (ufp >= (R)0 ? q5[c] : sQ[c * QN + qc + qst[b]]) : (R)0;
-          const R phim = fm ? ufm * (ufm >= (R)0 ? sQ[c * QN + qc - qst[b]] : q5[c]) : (R)0;
-          dQ[c] -= phip - phim;
+          for (int c = 0; c < 5; c++) {
+            const R phip = fp ? ufp * (ufp >= (R)0 ? q5[c] : sQ[c * QN + qc + qst[b]]) : (R)0;
+            const R phim = fm ? ufm * (ufm >= (R)0 ? sQ[c * QN + qc - qst[b]] : q5[c]) : (R)0;
+            dQ[c] -= phip - phim;
+          }
+        } else {
+          // higher-order upwind face values; a face whose wider stencil
+          // reaches a solid node takes the first-order value
+          const int st = qst[b];
+          auto face = [&](int lo, R uf, bool open, R phi[5]) {
+            const int up = uf >= (R)0 ? lo : lo + st, dn = uf >= (R)0 ? lo + st : lo;
+            const int upup = uf >= (R)0 ? lo - st : lo + 2 * st;
+            const bool wide = !(NEAR && sS[upup]);
+#pragma unroll
+            for (int c = 0; c < 5; c++) {
+              const R qu = sQ[c * QN + up];
+              R qf = qu;
+              if (wide) {
+                const R quu = sQ[c * QN + upup];
+                qf = adv == 2 ? ((R)3 * qu - quu) / (R)2 : ((R)2 * sQ[c * QN + dn] + (R)5 * qu - quu) / (R)6;
+              }
+              phi[c] = open ? uf * qf : (R)0;
+            }
+          };
+          R phip[5], phim[5];
+          face(qc, ufp, fp, phip);
+          face(qc - st, ufm, fm, phim);
+#pragma unroll
+          for (int c = 0; c < 5; c++) dQ[c] -= phip[c] - phim[c];
         }
       }
       R S5[5];
@@ -1138,6 +1170,10 @@ __device__ inline void exposed_q(const BoxDev& B, const double Rold[3], const do
   for (int c = 0; c < 5; c++) q5[c] = (double)(R)(nf ? qm[c] / nf : 0.0);
 }
 
+template <typename R>
+__device__ inline void ghost_finish(const BoxDev& B, const double Rc[3], int x, int y, int z, double (&qbar)[3][3],
+                                    int nf, R* __restrict__ Q, long long NS);
+
 // Anchoring at node (x, y, z) for the colloid at Rc: if the node is solid
 // with at least one fluid face neighbour, Q there becomes Q^0 (or its blend
 // with the neighbours' mean for finite W).  When the colloid has just moved
@@ -1147,6 +1183,34 @@ template <typename R>
 __device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const double Rc[3], bool moved, int x,
                                   int y, int z, R* __restrict__ Q, long long NS) {
   if (!inside(B, Rc, x, y, z)) return;
+  double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  int nf = 0;
+  if (B.st27) {
+    // 27-point stencil: every solid node with a fluid node among its 26
+    // neighbours, Qbar the mean of those (z, y, x order)
+    for (int dz = -1; dz <= 1; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+          if (!(dx || dy || dz)) continue;
+          const int xn = wrapc(x + dx, B.nx), yn = wrapc(y + dy, B.ny), zn = wrapc(z + dz, B.nz);
+          if (inside(B, Rc, xn, yn, zn)) continue;
+          double qq[3][3];
+          if (moved && inside(B, Rold, xn, yn, zn)) {
+            double q5[5];
+            exposed_q<R>(B, Rold, Rc, xn, yn, zn, Q, NS, q5);
+            qq[0][0] = q5[0]; qq[0][1] = q5[1]; qq[0][2] = q5[2];
+            qq[1][0] = q5[1]; qq[1][1] = q5[3]; qq[1][2] = q5[4];
+            qq[2][0] = q5[2]; qq[2][1] = q5[4]; qq[2][2] = -q5[0] - q5[3];
+          } else {
+            load_full(Q, NS, site_of(B, xn, yn, zn), qq);
+          }
+          for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) qbar[i][j] += qq[i][j];
+          nf++;
+        }
+    ghost_finish<R>(B, Rc, x, y, z, qbar, nf, Q, NS);
+    return;
+  }
   const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
   // all six neighbours are read at once (the loads overlap), then the fluid
   // ones are added in neighbour order
@@ -1170,8 +1234,6 @@ __device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const d
       qn[k][2][0] = q5[2]; qn[k][2][1] = q5[4]; qn[k][2][2] = -q5[0] - q5[3];
     }
   }
-  double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  int nf = 0;
 #pragma unroll
   for (int k = 0; k < 6; k++) {
     if (!fl[k]) continue;
@@ -1179,6 +1241,15 @@ __device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const d
       for (int j = 0; j < 3; j++) qbar[i][j] += qn[k][i][j];
     nf++;
   }
+  ghost_finish<R>(B, Rc, x, y, z, qbar, nf, Q, NS);
+}
+
+// Ghost Q of a solid node from the sum qbar of its nf fluid neighbours:
+// nothing for an interior node (nf = 0), else Q^0 (fixed anchoring), its
+// blend with the neighbours' mean (finite W) or the mean (no anchoring).
+template <typename R>
+__device__ inline void ghost_finish(const BoxDev& B, const double Rc[3], int x, int y, int z, double (&qbar)[3][3],
+                                    int nf, R* __restrict__ Q, long long NS) {
   if (nf == 0) return;  // interior solid node
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) qbar[i][j] /= nf;
@@ -1509,13 +1580,33 @@ __global__ void __launch_bounds__(256)
     const double A0 = B.A0, gm = B.gamma, K = B.K, q0 = B.q0;
     if (!sx) {
       double d[3][3][3];
-      const int e[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-      for (int c = 0; c < 3; c++) {
-        double qp[3][3], qm[3][3];
-        load_full(a.Qin, NS, gidx(x + e[c][0], y + e[c][1], z + e[c][2]), qp);
-        load_full(a.Qin, NS, gidx(x - e[c][0], y - e[c][1], z - e[c][2]), qm);
-        for (int i = 0; i < 3; i++)
-          for (int j = 0; j < 3; j++) d[c][i][j] = 0.5 * (qp[i][j] - qm[i][j]);
+      if (B.st27) {
+        // isotropic 27-point gradient (the stencil the box's field uses)
+        for (int c = 0; c < 3; c++)
+          for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) d[c][i][j] = 0.0;
+        for (int dz = -1; dz <= 1; dz++)
+          for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+              const int n = (dx != 0) + (dy != 0) + (dz != 0);
+              if (n == 0) continue;
+              const double wg = 3.0 * (n == 1 ? 2.0 / 27.0 : (n == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
+              const int cc[3] = {dx, dy, dz};
+              double qq[3][3];
+              load_full(a.Qin, NS, gidx(x + dx, y + dy, z + dz), qq);
+              for (int c = 0; c < 3; c++)
+                for (int i = 0; i < 3; i++)
+                  for (int j = 0; j < 3; j++) d[c][i][j] += wg * cc[c] * qq[i][j];
+            }
+      } else {
+        const int e[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        for (int c = 0; c < 3; c++) {
+          double qp[3][3], qm[3][3];
+          load_full(a.Qin, NS, gidx(x + e[c][0], y + e[c][1], z + e[c][2]), qp);
+          load_full(a.Qin, NS, gidx(x - e[c][0], y - e[c][1], z - e[c][2]), qm);
+          for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) d[c][i][j] = 0.5 * (qp[i][j] - qm[i][j]);
+        }
       }
       double tr2 = 0, tr3 = 0, chi = 0;
       for (int i = 0; i < 3; i++)
@@ -1556,13 +1647,26 @@ __global__ void __launch_bounds__(256)
         const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
         double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, qs[3][3], qz[3][3];
         int nf = 0;
-        for (int k = 0; k < 6; k++) {
-          if (solid(xs + nb[k][0], ys + nb[k][1], zs + nb[k][2])) continue;
-          double qq[3][3];
-          load_full(a.Qin, NS, gidx(xs + nb[k][0], ys + nb[k][1], zs + nb[k][2]), qq);
-          for (int i = 0; i < 3; i++)
-            for (int j = 0; j < 3; j++) qbar[i][j] += qq[i][j];
-          nf++;
+        if (B.st27) {
+          for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+              for (int dx = -1; dx <= 1; dx++) {
+                if (!(dx || dy || dz) || solid(xs + dx, ys + dy, zs + dz)) continue;
+                double qq[3][3];
+                load_full(a.Qin, NS, gidx(xs + dx, ys + dy, zs + dz), qq);
+                for (int i = 0; i < 3; i++)
+                  for (int j = 0; j < 3; j++) qbar[i][j] += qq[i][j];
+                nf++;
+              }
+        } else {
+          for (int k = 0; k < 6; k++) {
+            if (solid(xs + nb[k][0], ys + nb[k][1], zs + nb[k][2])) continue;
+            double qq[3][3];
+            load_full(a.Qin, NS, gidx(xs + nb[k][0], ys + nb[k][1], zs + nb[k][2]), qq);
+            for (int i = 0; i < 3; i++)
+              for (int j = 0; j < 3; j++) qbar[i][j] += qq[i][j];
+            nf++;
+          }
         }
         for (int i = 0; i < 3; i++)
           for (int j = 0; j < 3; j++) qbar[i][j] /= nf;

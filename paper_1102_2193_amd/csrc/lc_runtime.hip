@@ -420,6 +420,14 @@ int flush(lc_ctx* c) {
 // below 4 GiB.
 bool march_fits(const lc_ctx* c) { return 19.0 * 4.0 * (double)c->nsites < 4294967296.0; }
 
+// Boxes with higher-order advection or the 27-point stencil run on the
+// 3D-tile kernel only.
+bool has_variants(const lc_ctx* c) {
+  for (const BoxDev& B : c->hb)
+    if (B.adv != 1 || B.st27) return true;
+  return false;
+}
+
 int layout(lc_ctx* c) {
   {
     int rc = flush(c);   // the block sums of a pending step follow the old layout
@@ -433,6 +441,9 @@ int layout(lc_ctx* c) {
   if (T.kind == 1 && c->nbox > lc::kMaxBoxes) return fail(c, LC_EINVAL, "too many boxes for the marching kernel");
   if (T.kind == 1 && !march_fits(c))
     return fail(c, LC_EINVAL, "context too large for the marching kernel (19 x sites x 4 bytes >= 4 GiB); use a 3D tile");
+  if (T.kind == 1 && has_variants(c))
+    return fail(c, LC_EINVAL,
+                "the marching kernel has first-order advection and the 7-point stencil only; use a 3D tile");
   for (int b = 0; b < c->nbox; b++) {
     BoxDev& B = c->hb[b];
     const lc_params& p = c->prm[b];
@@ -636,6 +647,8 @@ int validate_params(const lc_params& p, std::string& why) {
   if (!(p.tau > 0.5)) { why = "tau must exceed 1/2"; return LC_EINVAL; }
   if (!(p.rho0 > 0.0)) { why = "rho0 must be positive"; return LC_EINVAL; }
   if (!(p.Gamma >= 0.0) || !(p.K >= 0.0)) { why = "Gamma and K must be >= 0"; return LC_EINVAL; }
+  if (p.advection < 0 || p.advection > 3) { why = "advection order must be 1, 2 or 3 (0: 1)"; return LC_EINVAL; }
+  if (p.stencil != 0 && p.stencil != 7 && p.stencil != 27) { why = "stencil must be 7 or 27 (0: 7)"; return LC_EINVAL; }
   if (!isfinite(p.A0) || !isfinite(p.gamma) || !isfinite(p.q0) || !isfinite(p.xi)) {
     why = "non-finite material parameter";
     return LC_EINVAL;
@@ -772,6 +785,8 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
     B.itau = 1.0 / q.tau;
     B.fsrc = 1.0 - 0.5 / q.tau;
     for (int a = 0; a < 3; a++) B.body[a] = q.body_force[a];
+    B.adv = q.advection ? q.advection : 1;
+    B.st27 = q.stencil == 27 ? 1 : 0;
   }
   c->nsites = off;
   // kernels address each component with 32-bit byte offsets
@@ -837,7 +852,7 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
                                       : lc::launch_fill<double>((double*)c->f[k], c->nsites, p[0].rho0, c->stream);
     if (e != hipSuccess) return bail(LC_EDEVICE, std::string("init: ") + hipGetErrorString(e));
   }
-  if (!march_fits(c)) {   // default to the first 3D-tile shape
+  if (!march_fits(c) || has_variants(c)) {   // default to the first 3D-tile shape
     for (int t = 0; t < num_tiles(c); t++)
       if (tile_shape(c, t).kind == 0) {
         c->tile = t;
@@ -1320,8 +1335,16 @@ int lc_set_tile(lc_ctx* c, int id) {
   if (id == c->tile) return LC_OK;
   int rc = pull_boxes(c);
   if (rc) return rc;
+  const int old = c->tile;
   c->tile = id;
-  return layout(c);
+  rc = layout(c);
+  if (rc != LC_OK) {   // keep the context on its previous shape
+    const std::string why = c->err;
+    c->tile = old;
+    layout(c);
+    c->err = why;
+  }
+  return rc;
 }
 
 int lc_get_tile(const lc_ctx* c) { return c ? c->tile : -1; }

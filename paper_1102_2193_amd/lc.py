@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("A0", ctypes.c_double), ("gamma", ctypes.c_double), ("K", ctypes.c_double),
                 ("q0", ctypes.c_double), ("xi", ctypes.c_double), ("Gamma", ctypes.c_double),
-                ("body_force", ctypes.c_double * 3)]
+                ("body_force", ctypes.c_double * 3),
+                ("advection", ctypes.c_int), ("stencil", ctypes.c_int)]
 
 
 class Colloid(ctypes.Structure):
@@ -119,8 +120,9 @@ def _dp(a):
 
 
 def make_params(nx, ny=None, nz=None, precision=FP32, hydro=1, tau=1.0, rho0=1.0, A0=0.01, gamma=3.0,
-                K=0.01, q0=0.0, xi=0.7, Gamma=0.5, body_force=(0.0, 0.0, 0.0)):
+                K=0.01, q0=0.0, xi=0.7, Gamma=0.5, body_force=(0.0, 0.0, 0.0), advection=1, stencil=7):
     p = Params()
+    p.advection, p.stencil = int(advection), int(stencil)
     p.nx = nx
     p.ny = nx if ny is None else ny
     p.nz = nx if nz is None else nz

@@ -45,9 +45,13 @@ def load_cache():
 
 def tune(ctx, steps=40, warm=8):
     """Time every tile shape on ctx; returns {tile_id: mean step ms}."""
+    from . import lc
     res = {}
     for t in range(ctx.num_tiles()):
-        ctx.set_tile(t)
+        try:
+            ctx.set_tile(t)
+        except lc.LCError:     # a shape the context's boxes cannot use
+            continue
         ctx.time_kernel(warm)
         res[t] = ctx.time_kernel(steps)["step_ms"]
     return res
