@@ -46,7 +46,9 @@ static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 struct lco_sim {
   lco_params p;
-  lco_colloid c;
+  lco_colloid c[LCO_MAX_COLLOIDS];  /* the first ncol are present */
+  int ncol;
+  int err;                  /* a step found two colloids too close: stepping stops */
   long N;
   long nstep;
   double *f, *fn, *fstar;   /* 19N */
@@ -54,8 +56,8 @@ struct lco_sim {
   double *Q0;               /* 5N, anchoring target at boundary solid nodes */
   double *u;                /* 3N, velocity of the previous collision */
   double *H, *P, *F;        /* 5N, 9N, 3N work */
-  unsigned char *solid;     /* N */
-  double force[12];
+  unsigned char *solid;     /* N: 0 fluid, k + 1 inside colloid k */
+  double force[LCO_MAX_COLLOIDS][12];
 };
 
 /* ------------------------------------------------------------------ */
@@ -120,11 +122,14 @@ static void rel_pos(const lco_sim* s, const double R[3], double px, double py, d
 /* Solid/fluid assignment from the nominal radius and the position
  * (Sec. 2.2): a node is solid iff |x - R|^2 < a0^2 (distance exactly a0
  * counts as fluid). */
-static int inside(const lco_sim* s, const double R[3], int x, int y, int z) {
+static int inside(const lco_sim* s, const lco_colloid* c, const double R[3], int x, int y, int z) {
   double r[3];
   rel_pos(s, R, x, y, z, r);
-  return r[0] * r[0] + r[1] * r[1] + r[2] * r[2] < s->c.a0 * s->c.a0;
+  return r[0] * r[0] + r[1] * r[1] + r[2] * r[2] < c->a0 * c->a0;
 }
+
+/* Colloid k of a solid node (solid[i] = k + 1). */
+static const lco_colloid* owner(const lco_sim* s, long i) { return &s->c[s->solid[i] - 1]; }
 
 /* rigid-body velocity v + omega x r (Sec. 2.2) */
 static void rigid_vel(const lco_colloid* c, const double r[3], double ub[3]) {
@@ -331,7 +336,9 @@ static void classify(lco_sim* s) {
   for (long i = 0; i < N; i++) {
     int x, y, z;
     scoord(s, i, &x, &y, &z);
-    s->solid[i] = (unsigned char)(s->c.present && inside(s, s->c.pos, x, y, z));
+    s->solid[i] = 0;
+    for (int k = 0; k < s->ncol && !s->solid[i]; k++)
+      if (inside(s, &s->c[k], s->c[k].pos, x, y, z)) s->solid[i] = (unsigned char)(k + 1);
   }
 }
 
@@ -345,35 +352,74 @@ static void clear_solid_fluid(lco_sim* s) {
   }
 }
 
-int lco_set_colloid(lco_sim* s, const lco_colloid* c) {
-  if (!s || !c) return LCO_EINVAL;
-  if (c->present) {
-    int Lmin = s->p.nx < s->p.ny ? s->p.nx : s->p.ny;
-    if (s->p.nz < Lmin) Lmin = s->p.nz;
-    if (!(c->a0 > 1.0) || !(2.0 * c->a0 + 4.0 <= Lmin)) return LCO_EINVAL;
-    if (c->anchoring < LCO_ANCHOR_NONE || c->anchoring > LCO_ANCHOR_PLANAR) return LCO_EINVAL;
-    if (c->motion != LCO_FIXED && c->motion != LCO_PRESCRIBED && c->motion != LCO_FREE) return LCO_EINVAL;
-    if (!(c->W >= 0.0)) return LCO_EINVAL;
-    if (c->anchoring != LCO_ANCHOR_NONE && !(s->p.K + c->W > 0.0)) return LCO_EINVAL;
-  }
-  s->c = *c;
-  if (c->present) {
+/* Minimum-image distance between two centres. */
+static double centre_distance(const lco_sim* s, const double A[3], const double B[3]) {
+  double r[3];
+  rel_pos(s, A, B[0], B[1], B[2], r);
+  return sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+}
+
+/* Several colloids in one box must keep their surfaces at least
+ * LCO_COLLOID_GAP lattice units apart (Introduction / Sec. 3.2 outlook:
+ * interactions through the liquid crystal, no lubrication): then no fluid
+ * node has links or faces to two colloids, and every ghost node's fluid
+ * neighbours and every uncovered node's neighbours see one colloid only. */
+static int separated(const lco_sim* s, int n, const lco_colloid* c) {
+  for (int i = 0; i < n; i++)
+    for (int j = i + 1; j < n; j++)
+      if (centre_distance(s, c[i].pos, c[j].pos) < c[i].a0 + c[j].a0 + LCO_COLLOID_GAP) return 0;
+  return 1;
+}
+
+int lco_set_colloids(lco_sim* s, int n, const lco_colloid* c) {
+  if (!s || n < 0 || n > LCO_MAX_COLLOIDS || (n > 0 && !c)) return LCO_EINVAL;
+  int Lmin = s->p.nx < s->p.ny ? s->p.nx : s->p.ny;
+  if (s->p.nz < Lmin) Lmin = s->p.nz;
+  lco_colloid v[LCO_MAX_COLLOIDS];
+  memset(v, 0, sizeof(v));
+  for (int k = 0; k < n; k++) {
+    if (!c[k].present) return LCO_EINVAL;
+    if (!(c[k].a0 > 1.0) || !(2.0 * c[k].a0 + 4.0 <= Lmin)) return LCO_EINVAL;
+    if (c[k].anchoring < LCO_ANCHOR_NONE || c[k].anchoring > LCO_ANCHOR_PLANAR) return LCO_EINVAL;
+    if (c[k].motion != LCO_FIXED && c[k].motion != LCO_PRESCRIBED && c[k].motion != LCO_FREE) return LCO_EINVAL;
+    if (!(c[k].W >= 0.0)) return LCO_EINVAL;
+    if (c[k].anchoring != LCO_ANCHOR_NONE && !(s->p.K + c[k].W > 0.0)) return LCO_EINVAL;
+    v[k] = c[k];
     /* keep the centre inside [0, L) */
     int L[3] = {s->p.nx, s->p.ny, s->p.nz};
     for (int a = 0; a < 3; a++) {
-      double r = fmod(s->c.pos[a], (double)L[a]);
+      double r = fmod(v[k].pos[a], (double)L[a]);
       if (r < 0) r += L[a];
-      s->c.pos[a] = r;
+      v[k].pos[a] = r;
     }
   }
+  if (!separated(s, n, v)) return LCO_EINVAL;
+  for (int k = 0; k < n; k++) s->c[k] = v[k];
+  s->ncol = n;
+  memset(s->force, 0, sizeof(s->force));
+  s->err = 0;
   classify(s);
   clear_solid_fluid(s);
   return LCO_OK;
 }
 
+int lco_set_colloid(lco_sim* s, const lco_colloid* c) {
+  if (!s || !c) return LCO_EINVAL;
+  return lco_set_colloids(s, c->present ? 1 : 0, c);
+}
+
 int lco_get_colloid(const lco_sim* s, lco_colloid* c) {
   if (!s || !c) return LCO_EINVAL;
-  *c = s->c;
+  if (s->ncol > 0) *c = s->c[0];
+  else memset(c, 0, sizeof(*c));
+  return LCO_OK;
+}
+
+int lco_num_colloids(const lco_sim* s) { return s ? s->ncol : -1; }
+
+int lco_get_colloids(const lco_sim* s, int n, lco_colloid* c) {
+  if (!s || n < 0 || n > s->ncol || (n > 0 && !c)) return LCO_EINVAL;
+  for (int k = 0; k < n; k++) c[k] = s->c[k];
   return LCO_OK;
 }
 
@@ -423,7 +469,13 @@ int lco_get_solid(const lco_sim* s, unsigned char* solid) {
 
 int lco_get_force(const lco_sim* s, double out[12]) {
   if (!s || !out) return LCO_EINVAL;
-  memcpy(out, s->force, sizeof(s->force));
+  memcpy(out, s->force[0], sizeof(s->force[0]));
+  return LCO_OK;
+}
+
+int lco_get_forces(const lco_sim* s, int n, double* out) {
+  if (!s || n < 0 || n > s->ncol || (n > 0 && !out)) return LCO_EINVAL;
+  memcpy(out, s->force, sizeof(double) * 12 * n);
   return LCO_OK;
 }
 
@@ -457,15 +509,15 @@ static int is_boundary_solid(const lco_sim* s, int x, int y, int z) {
  * axis of qbar (the "existing director") projected onto the tangent plane
  * and normalised, with fallbacks s x z, then s x x when the projection
  * vanishes. */
-static void anchoring_target(const lco_sim* s, int x, int y, int z, double qbar[3][3],
-                             double q0[3][3]) {
+static void anchoring_target(const lco_sim* s, const lco_colloid* c, int x, int y, int z,
+                             double qbar[3][3], double q0[3][3]) {
   double r[3], sh[3];
-  rel_pos(s, s->c.pos, x, y, z, r);
+  rel_pos(s, c->pos, x, y, z, r);
   double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   if (rn < 1e-12) { sh[0] = 0; sh[1] = 0; sh[2] = 1; }
   else { sh[0] = r[0] / rn; sh[1] = r[1] / rn; sh[2] = r[2] / rn; }
   double n0[3];
-  if (s->c.anchoring == LCO_ANCHOR_PLANAR) {
+  if (c->anchoring == LCO_ANCHOR_PLANAR) {
     double A9[9], n[3];
     for (int a = 0; a < 3; a++)
       for (int b = 0; b < 3; b++) A9[3 * a + b] = qbar[a][b];
@@ -489,7 +541,7 @@ static void anchoring_target(const lco_sim* s, int x, int y, int z, double qbar[
   }
   for (int a = 0; a < 3; a++)
     for (int b = 0; b < 3; b++)
-      q0[a][b] = s->c.S0 * (n0[a] * n0[b] - (a == b ? 1.0 / 3.0 : 0.0));
+      q0[a][b] = c->S0 * (n0[a] * n0[b] - (a == b ? 1.0 / 3.0 : 0.0));
 }
 
 /* Ghost Q at every boundary solid node, from the current Q at its fluid
@@ -497,7 +549,7 @@ static void anchoring_target(const lco_sim* s, int x, int y, int z, double qbar[
  * paper; a finite W blends (K qbar + W Q^0)/(K + W), the minimiser of
  * K/2|qbar - Qs|^2 + W/2|Qs - Q^0|^2; no anchoring copies qbar. */
 static void ghost_all(lco_sim* s, double* Q) {
-  if (!s->c.present) return;
+  if (!s->ncol) return;
   long N = s->N;
   static const int E[6][3] = {{1,0,0},{-1,0,0},{0,1,0},{0,-1,0},{0,0,1},{0,0,-1}};
   #pragma omp parallel for schedule(static)
@@ -532,15 +584,16 @@ static void ghost_all(lco_sim* s, double* Q) {
     }
     for (int a = 0; a < 3; a++)
       for (int b = 0; b < 3; b++) qbar[a][b] /= nf;
-    if (s->c.anchoring == LCO_ANCHOR_NONE) {
+    const lco_colloid* c = owner(s, i);
+    if (c->anchoring == LCO_ANCHOR_NONE) {
       store5(Q, N, i, qbar);
       double z0[3][3] = {{0}};
       store5(s->Q0, N, i, z0);
       continue;
     }
-    anchoring_target(s, x, y, z, qbar, q0);
+    anchoring_target(s, c, x, y, z, qbar, q0);
     store5(s->Q0, N, i, q0);
-    double K = s->p.K, W = s->c.W;
+    double K = s->p.K, W = c->W;
     for (int a = 0; a < 3; a++)
       for (int b = 0; b < 3; b++)
         qs[a][b] = isinf(W) ? q0[a][b] : (K * qbar[a][b] + W * q0[a][b]) / (K + W);
@@ -727,10 +780,11 @@ static void compute_F(lco_sim* s) {
 /* Colloid force and torque from the stress: the sum of P.s over the
  * solid-fluid control-volume faces (Sec. 2.2, F^coll = int P.s dS), with s
  * the outward colloid normal of the face.  Serial for a fixed order. */
-static void colloid_stress(lco_sim* s, double Fs[3], double Ts[3]) {
+static void colloid_stress(lco_sim* s, double Fs[][3], double Ts[][3]) {
   long N = s->N;
-  for (int a = 0; a < 3; a++) Fs[a] = Ts[a] = 0.0;
-  if (!s->c.present) return;
+  for (int k = 0; k < LCO_MAX_COLLOIDS; k++)
+    for (int a = 0; a < 3; a++) Fs[k][a] = Ts[k][a] = 0.0;
+  if (!s->ncol) return;
   for (long i = 0; i < N; i++) {
     if (s->solid[i]) continue;
     int x, y, z;
@@ -743,10 +797,11 @@ static void colloid_stress(lco_sim* s, double Fs[3], double Ts[3]) {
         if (!s->solid[j]) continue;
         /* the solid node sits at x + sg e_b: outward colloid normal -sg e_b */
         double ps[3], r[3], t[3];
+        const int k = s->solid[j] - 1;
         for (int a = 0; a < 3; a++) ps[a] = -sg * s->P[(3 * a + b) * N + i];
-        rel_pos(s, s->c.pos, x + 0.5 * e[0], y + 0.5 * e[1], z + 0.5 * e[2], r);
+        rel_pos(s, s->c[k].pos, x + 0.5 * e[0], y + 0.5 * e[1], z + 0.5 * e[2], r);
         cross(r, ps, t);
-        for (int a = 0; a < 3; a++) { Fs[a] += ps[a]; Ts[a] += t[a]; }
+        for (int a = 0; a < 3; a++) { Fs[k][a] += ps[a]; Ts[k][a] += t[a]; }
       }
   }
 }
@@ -755,8 +810,9 @@ static void site_velocity(const lco_sim* s, int x, int y, int z, double u[3]) {
   long j = sidx(s, x, y, z);
   if (s->solid[j]) {
     double r[3];
-    rel_pos(s, s->c.pos, x, y, z, r);
-    rigid_vel(&s->c, r, u);
+    const lco_colloid* c = owner(s, j);
+    rel_pos(s, c->pos, x, y, z, r);
+    rigid_vel(c, r, u);
   } else {
     for (int a = 0; a < 3; a++) u[a] = s->u[a * s->N + j];
   }
@@ -892,7 +948,7 @@ static void lb_collide(lco_sim* s) {
  * moving-wall correction -6 w_i rho0 c_i.u_b, u_b the rigid-body velocity at
  * the link midpoint; the momentum (2 f*_i - 6 w_i rho0 c_i.u_b) c_i goes to
  * the colloid. */
-static void lb_stream(lco_sim* s, double Fb[3], double Tb[3]) {
+static void lb_stream(lco_sim* s, double Fb[][3], double Tb[][3]) {
   long N = s->N;
   #pragma omp parallel for schedule(static)
   for (long k = 0; k < 19 * N; k++) s->fn[k] = 0.0;
@@ -908,15 +964,17 @@ static void lb_stream(lco_sim* s, double Fb[3], double Tb[3]) {
         s->fn[k * N + j] = fs;
       } else {
         double r[3], ub[3];
-        rel_pos(s, s->c.pos, x + 0.5 * CV[k][0], y + 0.5 * CV[k][1], z + 0.5 * CV[k][2], r);
-        rigid_vel(&s->c, r, ub);
+        const lco_colloid* c = owner(s, j);
+        rel_pos(s, c->pos, x + 0.5 * CV[k][0], y + 0.5 * CV[k][1], z + 0.5 * CV[k][2], r);
+        rigid_vel(c, r, ub);
         double cub = CV[k][0] * ub[0] + CV[k][1] * ub[1] + CV[k][2] * ub[2];
         s->fn[opposite(k) * N + i] = fs - 6.0 * WT[k] * s->p.rho0 * cub;
       }
     }
   }
-  for (int a = 0; a < 3; a++) Fb[a] = Tb[a] = 0.0;
-  if (!s->c.present) return;
+  for (int c = 0; c < LCO_MAX_COLLOIDS; c++)
+    for (int a = 0; a < 3; a++) Fb[c][a] = Tb[c][a] = 0.0;
+  if (!s->ncol) return;
   for (long i = 0; i < N; i++) {
     if (s->solid[i]) continue;
     int x, y, z;
@@ -925,13 +983,14 @@ static void lb_stream(lco_sim* s, double Fb[3], double Tb[3]) {
       long j = sidx(s, x + CV[k][0], y + CV[k][1], z + CV[k][2]);
       if (!s->solid[j]) continue;
       double r[3], ub[3], dp[3], t[3];
-      rel_pos(s, s->c.pos, x + 0.5 * CV[k][0], y + 0.5 * CV[k][1], z + 0.5 * CV[k][2], r);
-      rigid_vel(&s->c, r, ub);
+      const int ic = s->solid[j] - 1;
+      rel_pos(s, s->c[ic].pos, x + 0.5 * CV[k][0], y + 0.5 * CV[k][1], z + 0.5 * CV[k][2], r);
+      rigid_vel(&s->c[ic], r, ub);
       double cub = CV[k][0] * ub[0] + CV[k][1] * ub[1] + CV[k][2] * ub[2];
       double m = 2.0 * s->fstar[k * N + i] - 6.0 * WT[k] * s->p.rho0 * cub;
       for (int a = 0; a < 3; a++) dp[a] = m * CV[k][a];
       cross(r, dp, t);
-      for (int a = 0; a < 3; a++) { Fb[a] += dp[a]; Tb[a] += t[a]; }
+      for (int a = 0; a < 3; a++) { Fb[ic][a] += dp[a]; Tb[ic][a] += t[a]; }
     }
   }
 }
@@ -944,46 +1003,56 @@ static void lb_stream(lco_sim* s, double Fb[3], double Tb[3]) {
  * both before and after the move (zero if there is none); a node that
  * becomes solid is dropped.  The momentum of removed and added fluid goes
  * to the colloid (added to Fe, Te). */
-static void events(lco_sim* s, double* Qn, double Fe[3], double Te[3]) {
-  for (int a = 0; a < 3; a++) Fe[a] = Te[a] = 0.0;
-  if (!s->c.present || s->c.motion == LCO_FIXED) return;
+static void events(lco_sim* s, double* Qn, double Fe[][3], double Te[][3]) {
+  for (int k = 0; k < LCO_MAX_COLLOIDS; k++)
+    for (int a = 0; a < 3; a++) Fe[k][a] = Te[k][a] = 0.0;
+  int moving = 0;
+  for (int k = 0; k < s->ncol; k++) moving |= s->c[k].motion != LCO_FIXED;
+  if (!moving) return;
   long N = s->N;
   int L[3] = {s->p.nx, s->p.ny, s->p.nz};
-  double Rn[3];
-  for (int a = 0; a < 3; a++) {
-    Rn[a] = s->c.pos[a] + s->c.vel[a];
-    if (Rn[a] >= L[a]) Rn[a] -= L[a];
-    if (Rn[a] < 0.0) Rn[a] += L[a];
-  }
+  double Rn[LCO_MAX_COLLOIDS][3];
+  for (int k = 0; k < s->ncol; k++)
+    for (int a = 0; a < 3; a++) {
+      Rn[k][a] = s->c[k].pos[a];
+      if (s->c[k].motion == LCO_FIXED) continue;
+      Rn[k][a] += s->c[k].vel[a];
+      if (Rn[k][a] >= L[a]) Rn[k][a] -= L[a];
+      if (Rn[k][a] < 0.0) Rn[k][a] += L[a];
+    }
   unsigned char* nsolid = (unsigned char*)malloc(N);
   for (long i = 0; i < N; i++) {
     int x, y, z;
     scoord(s, i, &x, &y, &z);
-    nsolid[i] = (unsigned char)inside(s, Rn, x, y, z);
+    nsolid[i] = 0;
+    for (int k = 0; k < s->ncol && !nsolid[i]; k++)
+      if (inside(s, &s->c[k], Rn[k], x, y, z)) nsolid[i] = (unsigned char)(k + 1);
   }
   static const int E[6][3] = {{1,0,0},{-1,0,0},{0,1,0},{0,-1,0},{0,0,1},{0,0,-1}};
   for (long i = 0; i < N; i++) {
     int was = s->solid[i], now = nsolid[i];
     if (was == now) continue;
+    if (was && now) { s->err = 1; continue; }   /* from one colloid into another: excluded by the gap */
+    const int k = (was ? was : now) - 1;
     int x, y, z;
     scoord(s, i, &x, &y, &z);
     double r[3], p[3] = {0, 0, 0}, t[3];
-    rel_pos(s, Rn, x, y, z, r);
+    rel_pos(s, Rn[k], x, y, z, r);
     if (was && !now) {
       double ub[3], feq[19];
-      rigid_vel(&s->c, r, ub);
+      rigid_vel(&s->c[k], r, ub);
       if (s->p.hydro) {
         lco_feq(s->p.rho0, ub, feq);
-        for (int k = 0; k < 19; k++) {
-          s->fn[k * N + i] = feq[k];
-          for (int a = 0; a < 3; a++) p[a] -= feq[k] * CV[k][a];
+        for (int q = 0; q < 19; q++) {
+          s->fn[q * N + i] = feq[q];
+          for (int a = 0; a < 3; a++) p[a] -= feq[q] * CV[q][a];
         }
         for (int a = 0; a < 3; a++) s->u[a * N + i] = ub[a];
       }
       double qm[3][3] = {{0}}, qk[3][3];
       int nf = 0;
-      for (int k = 0; k < 6; k++) {
-        long j = sidx(s, x + E[k][0], y + E[k][1], z + E[k][2]);
+      for (int q = 0; q < 6; q++) {
+        long j = sidx(s, x + E[q][0], y + E[q][1], z + E[q][2]);
         if (s->solid[j] || nsolid[j]) continue;
         full_from5(Qn, N, j, qk);
         for (int a = 0; a < 3; a++)
@@ -995,18 +1064,19 @@ static void events(lco_sim* s, double* Qn, double Fe[3], double Te[3]) {
       store5(Qn, N, i, qm);
     } else {
       if (s->p.hydro) {
-        for (int k = 0; k < 19; k++) {
-          for (int a = 0; a < 3; a++) p[a] += s->fn[k * N + i] * CV[k][a];
-          s->fn[k * N + i] = 0.0;
+        for (int q = 0; q < 19; q++) {
+          for (int a = 0; a < 3; a++) p[a] += s->fn[q * N + i] * CV[q][a];
+          s->fn[q * N + i] = 0.0;
         }
         for (int a = 0; a < 3; a++) s->u[a * N + i] = 0.0;
       }
     }
     cross(r, p, t);
-    for (int a = 0; a < 3; a++) { Fe[a] += p[a]; Te[a] += t[a]; }
+    for (int a = 0; a < 3; a++) { Fe[k][a] += p[a]; Te[k][a] += t[a]; }
   }
   memcpy(s->solid, nsolid, N);
-  for (int a = 0; a < 3; a++) s->c.pos[a] = Rn[a];
+  for (int k = 0; k < s->ncol; k++)
+    for (int a = 0; a < 3; a++) s->c[k].pos[a] = Rn[k][a];
   free(nsolid);
 }
 
@@ -1014,8 +1084,10 @@ static void events(lco_sim* s, double* Qn, double Fe[3], double Te[3]) {
  * Q^{n+1} with u^{n-1}; LB collision with F^n storing u^n; streaming with
  * bounce-back; colloid events. */
 static void step_once(lco_sim* s) {
-  double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0}, Fb[3] = {0, 0, 0}, Tb[3] = {0, 0, 0};
-  double Fe[3], Te[3];
+  double Fs[LCO_MAX_COLLOIDS][3], Ts[LCO_MAX_COLLOIDS][3], Fb[LCO_MAX_COLLOIDS][3],
+      Tb[LCO_MAX_COLLOIDS][3], Fe[LCO_MAX_COLLOIDS][3], Te[LCO_MAX_COLLOIDS][3];
+  for (int k = 0; k < LCO_MAX_COLLOIDS; k++)
+    for (int a = 0; a < 3; a++) Fs[k][a] = Ts[k][a] = Fb[k][a] = Tb[k][a] = 0.0;
   ghost_all(s, s->Q);
   compute_HP(s, s->Q, s->p.hydro);
   if (s->p.hydro) {
@@ -1027,39 +1099,54 @@ static void step_once(lco_sim* s) {
     lb_collide(s);
     lb_stream(s, Fb, Tb);
   }
-  const int free_motion = s->c.present && s->c.motion == LCO_FREE;
-  double M = 0.0, I = 0.0;
-  if (free_motion) {
-    const double rc = s->c.rho_c > 0.0 ? s->c.rho_c : s->p.rho0;
-    const double a = s->c.a0;
-    M = 4.0 / 3.0 * acos(-1.0) * a * a * a * rc;
-    I = 0.4 * M * a * a;
+  double M[LCO_MAX_COLLOIDS] = {0}, I[LCO_MAX_COLLOIDS] = {0};
+  for (int c = 0; c < s->ncol; c++) {
+    lco_colloid* cc = &s->c[c];
+    if (cc->motion != LCO_FREE) continue;
+    const double rc = cc->rho_c > 0.0 ? cc->rho_c : s->p.rho0;
+    const double a = cc->a0;
+    M[c] = 4.0 / 3.0 * acos(-1.0) * a * a * a * rc;
+    I[c] = 0.4 * M[c] * a * a;
     for (int k = 0; k < 3; k++) {
-      s->c.vel[k] += (Fb[k] + Fs[k] + s->c.fext[k]) / M;
-      s->c.omega[k] += (Tb[k] + Ts[k]) / I;
+      cc->vel[k] += (Fb[c][k] + Fs[c][k] + cc->fext[k]) / M[c];
+      cc->omega[k] += (Tb[c][k] + Ts[c][k]) / I[c];
     }
   }
   events(s, s->Qn, Fe, Te);
-  if (free_motion)
+  for (int c = 0; c < s->ncol; c++) {
+    lco_colloid* cc = &s->c[c];
+    if (cc->motion != LCO_FREE) continue;
     for (int k = 0; k < 3; k++) {
-      s->c.vel[k] += Fe[k] / M;
-      s->c.omega[k] += Te[k] / I;
+      cc->vel[k] += Fe[c][k] / M[c];
+      cc->omega[k] += Te[c][k] / I[c];
     }
+  }
   double* t = s->Q; s->Q = s->Qn; s->Qn = t;
   if (s->p.hydro) { t = s->f; s->f = s->fn; s->fn = t; }
-  for (int a = 0; a < 3; a++) {
-    s->force[a] = Fb[a] + Fe[a];
-    s->force[3 + a] = Fs[a];
-    s->force[6 + a] = Tb[a] + Te[a];
-    s->force[9 + a] = Ts[a];
-  }
+  memset(s->force, 0, sizeof(s->force));
+  for (int c = 0; c < s->ncol; c++)
+    for (int a = 0; a < 3; a++) {
+      s->force[c][a] = Fb[c][a] + Fe[c][a];
+      s->force[c][3 + a] = Fs[c][a];
+      s->force[c][6 + a] = Tb[c][a] + Te[c][a];
+      s->force[c][9 + a] = Ts[c][a];
+    }
   s->nstep++;
 }
 
+/* A step may start only with every pair of colloids at least
+ * LCO_COLLOID_GAP apart (surface to surface); otherwise the step is refused
+ * and the simulation stops (LCO_ESTATE). */
 int lco_step(lco_sim* s, int nsteps) {
   if (!s || nsteps < 0) return LCO_EINVAL;
-  for (int n = 0; n < nsteps; n++) step_once(s);
-  return LCO_OK;
+  for (int n = 0; n < nsteps; n++) {
+    if (s->err || !separated(s, s->ncol, s->c)) {
+      s->err = 1;
+      return LCO_ESTATE;
+    }
+    step_once(s);
+  }
+  return s->err ? LCO_ESTATE : LCO_OK;
 }
 
 int lco_ghost(lco_sim* s, double* Q5_out) {
@@ -1091,7 +1178,7 @@ static double free_energy(lco_sim* s) {
   ghost_all(s, s->Q);
   long double Fd = 0.0L;   /* extended-precision accumulator */
   const double K = s->p.K, q0 = s->p.q0;
-  int finiteW = s->c.present && s->c.anchoring != LCO_ANCHOR_NONE && !isinf(s->c.W);
+
   for (long i = 0; i < N; i++) {
     int x, y, z;
     scoord(s, i, &x, &y, &z);
@@ -1113,14 +1200,16 @@ static double free_energy(lco_sim* s) {
       for (int a = 0; a < 3; a++)
         for (int c = 0; c < 3; c++) d[a][c] = qb[a][c] - qa[a][c];
       Fd += 0.5 * K * frob2(d);
-      if (finiteW && (s->solid[i] != s->solid[j])) {
+      if (!s->solid[i] != !s->solid[j]) {
         long js = s->solid[i] ? i : j;
+        const lco_colloid* cl = owner(s, js);
+        if (cl->anchoring == LCO_ANCHOR_NONE || isinf(cl->W)) continue;
         double qs[3][3], qz[3][3];
         full_from5(s->Q, N, js, qs);
         full_from5(s->Q0, N, js, qz);
         for (int a = 0; a < 3; a++)
           for (int c = 0; c < 3; c++) d[a][c] = qs[a][c] - qz[a][c];
-        Fd += 0.5 * s->c.W * frob2(d);
+        Fd += 0.5 * cl->W * frob2(d);
       }
     }
   }

@@ -1,6 +1,6 @@
 /*
  * lco.h -- plain FP64 CPU oracle of the hybrid lattice-Boltzmann /
- * finite-difference step for one colloid in a liquid crystal
+ * finite-difference step for colloids in a liquid crystal
  * (Lintuvuori, Marenduzzo, Stratford, Cates, "Colloids in liquid crystals:
  * a lattice Boltzmann study", Soft Matter 2011).
  *
@@ -32,6 +32,11 @@ extern "C" {
 enum { LCO_OK = 0, LCO_EINVAL = 1, LCO_ENOMEM = 2, LCO_ESTATE = 5 };
 enum { LCO_ANCHOR_NONE = 0, LCO_ANCHOR_NORMAL = 1, LCO_ANCHOR_PLANAR = 2 };
 enum { LCO_FIXED = 0, LCO_PRESCRIBED = 1, LCO_FREE = 2 };
+/* Colloids per box, and the least surface-to-surface distance two of them
+ * may have at the start of a step (no lubrication; then no fluid node has
+ * links or faces to two colloids). */
+enum { LCO_MAX_COLLOIDS = 16 };
+#define LCO_COLLOID_GAP 3.0
 
 typedef struct lco_params {
   int nx, ny, nz;
@@ -82,8 +87,15 @@ typedef struct lco_sim lco_sim;
 
 int  lco_create(const lco_params* p, lco_sim** out);
 void lco_destroy(lco_sim* s);
+/* Colloids of the box.  lco_set_colloids replaces them with n (0..16), all
+ * present and pairwise at least LCO_COLLOID_GAP apart surface to surface
+ * (else LCO_EINVAL); lco_set_colloid sets the one colloid c (none if
+ * c->present is 0).  Getters: colloid 0, the number, the first n. */
+int  lco_set_colloids(lco_sim* s, int n, const lco_colloid* c);
 int  lco_set_colloid(lco_sim* s, const lco_colloid* c);
 int  lco_get_colloid(const lco_sim* s, lco_colloid* c);
+int  lco_num_colloids(const lco_sim* s);
+int  lco_get_colloids(const lco_sim* s, int n, lco_colloid* c);
 int  lco_set_Q(lco_sim* s, const double* Q5);      /* 5*N */
 int  lco_set_f(lco_sim* s, const double* f19);     /* 19*N, pre-collision */
 int  lco_set_u(lco_sim* s, const double* u3);      /* 3*N lagged velocity */
@@ -91,8 +103,13 @@ int  lco_get_Q(const lco_sim* s, double* Q5);
 int  lco_get_f(const lco_sim* s, double* f19);
 int  lco_get_u(const lco_sim* s, double* u3);
 int  lco_get_solid(const lco_sim* s, unsigned char* solid);
+/* LCO_ESTATE: a step would start with two colloids closer than the gap
+ * (the simulation then stays stopped). */
 int  lco_step(lco_sim* s, int nsteps);
+/* Force and torque of the last step, 12 doubles per colloid: colloid 0 /
+ * the first n colloids. */
 int  lco_get_force(const lco_sim* s, double out[12]);
+int  lco_get_forces(const lco_sim* s, int n, double* out);
 long lco_get_nstep(const lco_sim* s);
 /* F_d, mass, momentum[3], max|u|  (Q ghost values refreshed first) */
 int  lco_get_diag(lco_sim* s, double out[6]);

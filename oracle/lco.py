@@ -16,6 +16,8 @@ from . import build as _build
 
 ANCHOR_NONE, ANCHOR_NORMAL, ANCHOR_PLANAR = 0, 1, 2
 FIXED, PRESCRIBED, FREE = 0, 1, 2
+MAX_COLLOIDS = 16
+COLLOID_GAP = 3.0
 
 _lib = None
 
@@ -51,6 +53,10 @@ def lib():
         L.lco_destroy.restype = None
         L.lco_set_colloid.argtypes = [vp, ctypes.POINTER(Colloid)]
         L.lco_get_colloid.argtypes = [vp, ctypes.POINTER(Colloid)]
+        L.lco_set_colloids.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Colloid)]
+        L.lco_get_colloids.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Colloid)]
+        L.lco_num_colloids.argtypes = [vp]
+        L.lco_get_forces.argtypes = [vp, ctypes.c_int, dp]
         for name in ("lco_set_Q", "lco_set_f", "lco_set_u", "lco_get_Q", "lco_get_f",
                      "lco_get_u", "lco_get_force", "lco_get_diag", "lco_ghost"):
             getattr(L, name).argtypes = [vp, dp]
@@ -144,7 +150,7 @@ def single_site(params, W, nsteps, Q5):
 
 
 class Sim:
-    """One periodic box with at most one colloid, stepped in FP64."""
+    """One periodic box with up to 16 colloids, stepped in FP64."""
 
     def __init__(self, nx, ny=None, nz=None, **kw):
         ny = nx if ny is None else ny
@@ -176,6 +182,36 @@ class Sim:
         c = Colloid()
         self._chk(lib().lco_get_colloid(self._h, ctypes.byref(c)), "lco_get_colloid")
         return c
+
+    def set_colloids(self, specs):
+        """specs: list of dicts with pos, a0 and make_colloid's keywords."""
+        arr = (Colloid * max(1, len(specs)))()
+        for k, sp in enumerate(specs):
+            sp = dict(sp)
+            arr[k] = make_colloid(sp.pop("pos"), sp.pop("a0"), **sp)
+        self._chk(lib().lco_set_colloids(self._h, len(specs), arr), "lco_set_colloids")
+
+    def num_colloids(self):
+        return int(lib().lco_num_colloids(self._h))
+
+    def get_colloids(self):
+        n = self.num_colloids()
+        arr = (Colloid * max(1, n))()
+        self._chk(lib().lco_get_colloids(self._h, n, arr), "lco_get_colloids")
+        return [arr[k] for k in range(n)]
+
+    def forces(self):
+        n = self.num_colloids()
+        out = np.zeros((max(1, n), 12))
+        self._chk(lib().lco_get_forces(self._h, n, _dp(out)), "lco_get_forces")
+        return out[:n]
+
+    def solid_id(self):
+        """0 at fluid nodes, k + 1 inside colloid k."""
+        a = np.zeros(self.shape, dtype=np.uint8)
+        self._chk(lib().lco_get_solid(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))),
+                  "lco_get_solid")
+        return a
 
     def _set(self, name, arr, ncomp):
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape(ncomp, *self.shape)
@@ -214,7 +250,10 @@ class Sim:
         return a.astype(bool)
 
     def step(self, n=1):
-        self._chk(lib().lco_step(self._h, int(n)), "lco_step")
+        rc = lib().lco_step(self._h, int(n))
+        if rc == 5:
+            raise RuntimeError("lco_step refused: two colloids closer than the gap")
+        self._chk(rc, "lco_step")
 
     @property
     def nstep(self):
