@@ -7,8 +7,10 @@
  * One step couples D3Q19 collide-and-stream for the fluid (Sec. 2.1,
  * Navier-Stokes equation; Sec. 2.2, bounce-back on links) to a
  * finite-difference Beris-Edwards update of the Q tensor (Eq. 1 free
- * energy, Eq. 2 dynamics, Eq. 4 stress) around one colloid per box with
- * normal or planar anchoring (Sec. 2.2, equation for Q^0).
+ * energy, Eq. 2 dynamics, Eq. 4 stress) around colloids with normal or
+ * planar anchoring (Sec. 2.2, equation for Q^0): one per box, or several
+ * (the colloid-colloid interactions of the paper's outlook, Introduction and
+ * Sec. 3.2).
  *
  * Conventions shared by every call
  *  - Return value: LC_OK (0) or a positive lc_status code.  Nothing throws
@@ -46,7 +48,8 @@ typedef enum lc_status {
   LC_ENOMEM = 2,     /* device or host allocation failed */
   LC_EDEVICE = 3,    /* a HIP call failed */
   LC_ENUMERIC = 4,   /* a step produced a non-finite value or |u| >= 0.3 */
-  LC_ESTATE = 5      /* call not valid in the current state */
+  LC_ESTATE = 5      /* call not valid in the current state, or two colloids
+                        started a step closer than LC_COLLOID_GAP */
 } lc_status;
 
 enum { LC_FP32 = 0, LC_FP64 = 1 };
@@ -144,9 +147,28 @@ int lc_buffer_bytes(const lc_ctx* ctx, size_t out[3]);
  * lc_destroy.  Pointers must be 256-byte aligned. */
 int lc_bind_buffers(lc_ctx* ctx, void* f0, void* f1, void* Q0, void* Q1, void* u0, void* u1);
 
-/* Colloid of box `box` (Sec. 2.2).  Rejects a sphere that does not fit
- * (2 a0 + 4 > min box edge) or a0 <= 1. */
+/* Colloids of box `box` (Sec. 2.2).  A box holds 0 to LC_MAX_COLLOIDS
+ * colloids whose surfaces are at least LC_COLLOID_GAP lattice units apart
+ * (minimum image) at the start of every step: then no fluid node has links
+ * or faces to two colloids (no lubrication).  A step that starts with two
+ * colloids closer than that stops the context: the next getter returns
+ * LC_ESTATE.  Each colloid is rejected if it does not fit (2 a0 + 4 > min box
+ * edge) or a0 <= 1.  A box with several colloids runs on a 3D-tile shape (a
+ * context on a marching shape is moved to the first 3D tile).
+ *  lc_set_colloids: replaces the box's colloids with c[0..n-1] (all with
+ *    present = 1); colloid k keeps its force history if the box had a k-th
+ *    colloid before.  On an error the box keeps its colloids.
+ *  lc_set_colloid:  the one colloid c, or none if c->present is 0.
+ *  lc_num_colloids: the box's number of colloids (-1 on a bad box).
+ *  lc_get_colloids: the first n colloids, at their current positions (and a
+ *    free colloid's current velocities); lc_get_colloid: colloid 0, or
+ *    present = 0 if there is none. */
+#define LC_MAX_COLLOIDS 16
+#define LC_COLLOID_GAP 3.0
+int lc_set_colloids(lc_ctx* ctx, int box, int n, const lc_colloid* c);
 int lc_set_colloid(lc_ctx* ctx, int box, const lc_colloid* c);
+int lc_num_colloids(lc_ctx* ctx, int box);
+int lc_get_colloids(lc_ctx* ctx, int box, int n, lc_colloid* c);
 int lc_get_colloid(lc_ctx* ctx, int box, lc_colloid* c);
 
 /* Whole-box field transfers (FP64 host arrays, see conventions). */
@@ -160,23 +182,24 @@ int lc_get_u(lc_ctx* ctx, int box, double* u3);    /* velocity of the last colli
 /* Checkpoint and restart (the paper describes none; this is a plain save of
  * the evolving state).  The state holds both buffers of f, Q and u bit for
  * bit in the context's precision (a step leaves solid nodes untouched, so
- * the second buffer is kept too), every box's colloid at its current
- * position, the step count, the last-step forces and the force-history
- * rings.  Material parameters are not part of it: a context takes its own
+ * the second buffer is kept too), every colloid at its current position,
+ * the step count, the last-step forces and the force-history rings.  Material parameters are not part of it: a context takes its own
  * lc_params.  A context created with the same lc_params (and precision)
  * that is given the state continues exactly as the saved one would have:
  * every later getter returns the same bits.
- * The format is the library's own: a header (magic "LCSTATE1", version,
- * precision, box count, sites, step count), one record per box (shape,
- * history count, colloid), then raw arrays in native byte order.
+ * The format is the library's own: a header (magic "LCSTATE2", version,
+ * precision, box count, sites, step count, colloid count), one record per
+ * box (shape, colloid count), one per colloid (history count, colloid),
+ * then raw arrays in native byte order.
  *  lc_state_bytes: the size of this context's state in bytes.
  *  lc_get_state:   writes the state into caller-owned host memory buf of
  *                  `bytes` >= lc_state_bytes; synchronises the stream;
  *                  LC_ENUMERIC if a step was flagged.
- *  lc_set_state:   reads a state written by lc_get_state.  LC_EINVAL if buf
- *                  is NULL or short, or its precision, box count, box shapes
- *                  or colloids do not fit this context; the context is then
- *                  unchanged.  Clears the numeric flag. */
+ *  lc_set_state:   reads a state written by lc_get_state (its colloids
+ *                  replace the context's).  LC_EINVAL if buf is NULL or
+ *                  short, or its precision, box count, box shapes or
+ *                  colloids do not fit this context; the context is then
+ *                  unchanged.  Clears the error flags. */
 int lc_state_bytes(const lc_ctx* ctx, size_t* out);
 int lc_get_state(lc_ctx* ctx, void* buf, size_t bytes);
 int lc_set_state(lc_ctx* ctx, const void* buf, size_t bytes);
@@ -199,13 +222,24 @@ long lc_get_nstep(lc_ctx* ctx); /* steps taken (host count) */
 
 /* Colloid force and torque of the last step: F_bbl[3], F_stress[3],
  * T_bbl[3], T_stress[3] (Sec. 2.2: link momentum from bounce-back;
- * F^coll = sum of P.s over solid-fluid faces).  Momentum of fluid removed or
- * added by moving-boundary events is included in F_bbl and T_bbl. */
+ * F^coll = sum of P.s over solid-fluid faces), torques about the colloid's
+ * centre.  Momentum of fluid removed or added by moving-boundary events is
+ * included in F_bbl and T_bbl.  lc_get_colloid_force: colloid k of the box;
+ * lc_get_force: colloid 0 (zeros for a box without colloids). */
+int lc_get_colloid_force(lc_ctx* ctx, int box, int k, double out[12]);
 int lc_get_force(lc_ctx* ctx, int box, double out[12]);
-/* The last nsteps forces (oldest first), 12 doubles each; nsteps must not
- * exceed the steps taken nor the history capacity (lc_history_capacity). */
+/* The last nsteps forces (oldest first), 12 doubles each, of colloid k /
+ * colloid 0 (zeros for a box without colloids); nsteps must not exceed the
+ * steps the colloid has taken (lc_get_force_history: the context's steps)
+ * nor the history capacity (lc_history_capacity). */
+int lc_get_colloid_force_history(lc_ctx* ctx, int box, int k, int nsteps, double* out);
 int lc_get_force_history(lc_ctx* ctx, int box, int nsteps, double* out);
 int lc_history_capacity(const lc_ctx* ctx);
+
+/* Solid map of a box from the library's own sphere test (Sec. 2.2):
+ * id[s] = 1 + the index of the colloid holding site s, 0 at fluid sites
+ * (caller-owned, nx*ny*nz bytes, x fastest).  Synchronises the stream. */
+int lc_get_solid(lc_ctx* ctx, int box, unsigned char* id);
 
 int lc_get_diag(lc_ctx* ctx, int box, lc_diag* out);
 

@@ -11,25 +11,38 @@
 
 namespace lc {
 
-// One box of the batch.  Host and device share this layout; the colloid
-// position is advanced on the device by the post-step kernel.
+// One box of the batch.  Host and device share this layout.
 struct BoxDev {
   int nx, ny, nz, hydro;
   long long off;            // first site of the box in the concatenated arrays
   int tile_base, ntx, nty, ntz;          // fused-kernel tiles of this box
-  int ghost_base, ghost_ext;             // ghost launch: thread range, bbox edge
-  int event_ext, pad1_;                  // bbox edge of the moving-boundary events
-  int post_blk0, post_nblk;              // blocks of the post-step kernel for this box
+  int col0, ncol;                        // its colloids: entries col0 .. col0+ncol-1 of the table
   double tau, rho0, A0, gamma, K, q0, xi, Gamma;
   double itau, fsrc;                     // 1/tau and 1 - 1/(2 tau)
   double body[3];
   int adv, st27;                         // advection order (1..3); 27-point Q stencil
-  int present, motion, anchoring, pad_;
-  // colloid centre at the start of a step, by the step's buffer parity: the
+};
+
+// Colloids of a box keep their surfaces at least this far apart (lattice
+// units) at the start of every step: no fluid node then has links or faces
+// to two colloids, so each link, face, ghost node and moving-boundary event
+// belongs to one colloid.
+constexpr double kColloidGap = 3.0;
+constexpr int kMaxColloids = 16;   // per box
+
+// One colloid (Sec. 2.2).  Host and device share this layout; the position
+// (and a free colloid's velocities) advance on the device.
+struct ColDev {
+  int box, motion, anchoring, pad_;
+  // centre at the start of a step, by the step's buffer parity: the
   // post-step kernel of a step writes the other slot
   double pos[2][3];
   double a0, vel[3], omega[3], S0, W;
   double fext[3], mass, inertia;          // free motion (motion == 2)
+  int slot_base;                          // its fused-kernel slots: slot_base + tile (or column block + ncb * plane)
+  int ghost_base, ghost_ext;              // ghost launch: thread range, candidate cube edge
+  int event_ext;                          // candidate cube edge of the moving-boundary events
+  int post_blk0, post_nblk;               // blocks of the post-step kernel for this colloid
 };
 
 // D3Q19: rest, 6 axis links, 12 diagonal links; opposite links adjacent.
@@ -89,25 +102,25 @@ __device__ inline void rel_pos(const BoxDev& B, const double R[3], double px, do
 }
 
 // Solid iff |x - R|^2 < a0^2 with the nominal radius and position (Sec. 2.2).
-__device__ inline bool inside(const BoxDev& B, const double R[3], int x, int y, int z) {
+__device__ inline bool inside(const BoxDev& B, const ColDev& C, const double R[3], int x, int y, int z) {
   double r[3];
   rel_pos(B, R, (double)x, (double)y, (double)z, r);
   double d2 = __dadd_rn(__dadd_rn(__dmul_rn(r[0], r[0]), __dmul_rn(r[1], r[1])),
                         __dmul_rn(r[2], r[2]));
-  return d2 < __dmul_rn(B.a0, B.a0);
+  return d2 < __dmul_rn(C.a0, C.a0);
 }
 
 // Rigid-body velocity v + omega x r at displacement r from the centre.
-__device__ inline void rigid_vel(const BoxDev& B, const double r[3], double ub[3]) {
-  ub[0] = B.vel[0] + (B.omega[1] * r[2] - B.omega[2] * r[1]);
-  ub[1] = B.vel[1] + (B.omega[2] * r[0] - B.omega[0] * r[2]);
-  ub[2] = B.vel[2] + (B.omega[0] * r[1] - B.omega[1] * r[0]);
+__device__ inline void rigid_vel(const ColDev& C, const double r[3], double ub[3]) {
+  ub[0] = C.vel[0] + (C.omega[1] * r[2] - C.omega[2] * r[1]);
+  ub[1] = C.vel[1] + (C.omega[2] * r[0] - C.omega[0] * r[2]);
+  ub[2] = C.vel[2] + (C.omega[0] * r[1] - C.omega[1] * r[0]);
 }
 
 // Conservative integer test, one axis: can the colloid (radius + 3 sites)
 // reach [lo, lo+ext) along axis a in some periodic image?
-__device__ inline bool axis_near(const BoxDev& B, const double R[3], int a, int lo, int ext) {
-  const int ra = (int)ceil(B.a0) + 3;
+__device__ inline bool axis_near(const BoxDev& B, const ColDev& C, const double R[3], int a, int lo, int ext) {
+  const int ra = (int)ceil(C.a0) + 3;
   const int L = a == 0 ? B.nx : (a == 1 ? B.ny : B.nz);
   const int c = (int)floor(R[a]);
   int best = 1 << 30;
@@ -120,12 +133,34 @@ __device__ inline bool axis_near(const BoxDev& B, const double R[3], int a, int 
 }
 
 // Can any node of the block [lo, lo+ext) (per axis) lie within two lattice
-// spacings of the colloid surface?  Blocks for which this is false have no
-// solid node within reach of their stencils.
-__device__ inline bool block_near(const BoxDev& B, const double R[3], int x0, int y0, int z0,
+// spacings of the colloid's surface?  Blocks for which this is false have no
+// solid node of it within reach of their stencils.
+__device__ inline bool block_near(const BoxDev& B, const ColDev& C, const double R[3], int x0, int y0, int z0,
                                   int ex, int ey, int ez) {
-  if (!B.present) return false;
-  return axis_near(B, R, 0, x0, ex) && axis_near(B, R, 1, y0, ey) && axis_near(B, R, 2, z0, ez);
+  return axis_near(B, C, R, 0, x0, ex) && axis_near(B, C, R, 1, y0, ey) && axis_near(B, C, R, 2, z0, ez);
+}
+
+// Bit k set for each colloid k of the box (at buffer parity par) that can
+// reach the block.
+__device__ inline unsigned near_mask(const BoxDev& B, const ColDev* cols, int par, int x0, int y0, int z0, int ex,
+                                     int ey, int ez) {
+  unsigned m = 0u;
+  for (int k = 0; k < B.ncol; k++) {
+    const ColDev& C = cols[B.col0 + k];
+    if (block_near(B, C, C.pos[par], x0, y0, z0, ex, ey, ez)) m |= 1u << k;
+  }
+  return m;
+}
+
+// 1 + the index of the colloid (among those in mask) that holds node
+// (x, y, z), or 0 for a fluid node.
+__device__ inline int solid_id(const BoxDev& B, const ColDev* cols, unsigned mask, int par, int x, int y, int z) {
+  for (unsigned m = mask; m; m &= m - 1u) {
+    const int k = __builtin_ctz(m);
+    const ColDev& C = cols[B.col0 + k];
+    if (inside(B, C, C.pos[par], x, y, z)) return k + 1;
+  }
+  return 0;
 }
 
 // ---------------------------------------------------------------------
@@ -399,14 +434,14 @@ __device__ inline void principal_axis(const double A[3][3], double n[3]) {
 // (Sec. 2.2): n0 = outward normal (homeotropic) or the principal axis of
 // the neighbouring Q projected on the tangent plane (planar), with the
 // fallbacks s x z and s x x when the projection vanishes.
-__device__ inline void anchor_target(const BoxDev& B, const double R[3], int x, int y, int z,
+__device__ inline void anchor_target(const BoxDev& B, const ColDev& C, const double R[3], int x, int y, int z,
                                      const double qbar[3][3], double q0[3][3]) {
   double r[3], s[3], n0[3];
   rel_pos(B, R, (double)x, (double)y, (double)z, r);
   const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   if (rn < 1e-12) { s[0] = 0.0; s[1] = 0.0; s[2] = 1.0; }
   else { s[0] = r[0] / rn; s[1] = r[1] / rn; s[2] = r[2] / rn; }
-  if (B.anchoring == 2) {
+  if (C.anchoring == 2) {
     double n[3];
     principal_axis(qbar, n);
     const double ns = n[0] * s[0] + n[1] * s[1] + n[2] * s[2];
@@ -425,7 +460,7 @@ __device__ inline void anchor_target(const BoxDev& B, const double R[3], int x, 
     n0[0] = s[0]; n0[1] = s[1]; n0[2] = s[2];
   }
   for (int a = 0; a < 3; a++)
-    for (int b = 0; b < 3; b++) q0[a][b] = B.S0 * (n0[a] * n0[b] - (a == b ? 1.0 / 3.0 : 0.0));
+    for (int b = 0; b < 3; b++) q0[a][b] = C.S0 * (n0[a] * n0[b] - (a == b ? 1.0 / 3.0 : 0.0));
 }
 
 }  // namespace lc

@@ -214,8 +214,9 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
   const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
   const unsigned off = (unsigned)B.off;
   const long long NS = a.nsites;
-  const double Rc[3] = {B.pos[a.par][0], B.pos[a.par][1], B.pos[a.par][2]};
-  const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, TZ + 4);
+  // colloids that can reach the tile's stencils (bit k: colloid k of the box)
+  const unsigned nmask = near_mask(B, a.cols, a.par, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, TZ + 4);
+  const bool near = nmask != 0u;
   // a single conditional correction wraps every halo coordinate
   const bool wide = nx >= TX + 2 && ny >= TY + 2 && nz >= TZ + 2;
   const Mat<R> mp(B);
@@ -252,7 +253,7 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
     const unsigned gs = off + (unsigned)(wx + nx * wy + nxy * wz);
 #pragma unroll
     for (int c = 0; c < 5; c++) sQ[c * QN + s] = *at32(a.Qin + c * NS, gs);
-    sS[s] = near ? (unsigned char)inside(B, Rc, wx, wy, wz) : (unsigned char)0;
+    sS[s] = near ? (unsigned char)solid_id(B, a.cols, nmask, a.par, wx, wy, wz) : (unsigned char)0;
   }
   if (hydro) {
     for (int s = tid; s < PN; s += NT) {
@@ -345,12 +346,14 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
     if (near) {
       for (int s = tid; s < PN; s += NT) {
         const int uz = s / PSZ, rem = s - uz * PSZ, uy = rem / PX, ux = rem - uy * PX;
-        if (!sS[(uz + 1) * QSZ + (uy + 1) * QSY + (ux + 1)]) continue;
+        const int id = sS[(uz + 1) * QSZ + (uy + 1) * QSY + (ux + 1)];
+        if (!id) continue;
         int wx = x0 - 1 + ux, wy = y0 - 1 + uy, wz = z0 - 1 + uz;
         wrap3(wx, wy, wz);
+        const ColDev& C = a.cols[B.col0 + id - 1];
         double r[3], ub[3];
-        rel_pos(B, Rc, (double)wx, (double)wy, (double)wz, r);
-        rigid_vel(B, r, ub);
+        rel_pos(B, C.pos[a.par], (double)wx, (double)wy, (double)wz, r);
+        rigid_vel(C, r, ub);
 #pragma unroll
         for (int c = 0; c < 3; c++) sU[c * PN + s] = (R)ub[c];
       }
@@ -363,6 +366,7 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
   double part[12];
 #pragma unroll
   for (int k = 0; k < 12; k++) part[k] = 0.0;
+  int own = 0;   // 1 + colloid of this site's solid links (one by the separation of colloids)
 
   auto update = [&](auto near_tag) {
     constexpr bool NEAR = decltype(near_tag)::value;
@@ -376,7 +380,11 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
     R F[3] = {(R)0, (R)0, (R)0};
     bool solid_nb[19];
 #pragma unroll
-    for (int i = 0; i < 19; i++) solid_nb[i] = NEAR ? (bool)sS[qc + cx(i) + cy(i) * QSY + cz(i) * QSZ] : false;
+    for (int i = 0; i < 19; i++) {
+      const int id = NEAR ? (int)sS[qc + cx(i) + cy(i) * QSY + cz(i) * QSZ] : 0;
+      solid_nb[i] = id != 0;
+      own = id > own ? id : own;
+    }
     // solid-link sums of this site: stress-face force and its torque about
     // r_site, bounce-back momentum
     double fps[3] = {0.0, 0.0, 0.0}, fts[3] = {0.0, 0.0, 0.0}, bbp[3] = {0.0, 0.0, 0.0};
@@ -531,9 +539,10 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
       // projection equals that at the link midpoint, c.(w x c/2) = 0
       R ubs[3] = {(R)0, (R)0, (R)0};
       if (NEAR && anys) {
+        const ColDev& C = a.cols[B.col0 + own - 1];
         double r[3], ub[3];
-        rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
-        rigid_vel(B, r, ub);
+        rel_pos(B, C.pos[a.par], (double)gx, (double)gy, (double)gz, r);
+        rigid_vel(C, r, ub);
 #pragma unroll
         for (int c = 0; c < 3; c++) ubs[c] = (R)ub[c];
       }
@@ -560,7 +569,7 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
     }
     if (NEAR && anys) {
       double r[3];
-      rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
+      rel_pos(B, a.cols[B.col0 + own - 1].pos[a.par], (double)gx, (double)gy, (double)gz, r);
       part[0] += bbp[0]; part[1] += bbp[1]; part[2] += bbp[2];
       part[6] += r[1] * bbp[2] - r[2] * bbp[1];
       part[7] += r[2] * bbp[0] - r[0] * bbp[2];
@@ -578,13 +587,20 @@ __device__ __forceinline__ void step_tile(const BoxDev& B, const int2 tt, const 
     else update(std::false_type{});
   }
 
-  if (near) {
-    double red[12];
+  // one slot per colloid of the box, every slot written each step (zeros
+  // for colloids out of reach); a site's sums belong to its links' colloid
+  for (int k = 0; k < B.ncol; k++) {
+    double* out = a.part + a.cols[B.col0 + k].slot_base + tt.y;
+    if ((nmask >> k) & 1u) {
+      const bool mine = own == k + 1;
+      double red[12];
 #pragma unroll
-    for (int k = 0; k < 12; k++) red[k] = part[k];
-    block_sum<NT, 12>(red, sred, a.part + (B.tile_base + tt.y), a.nslot);
-  } else if (tid < 12) {
-    a.part[tid * a.nslot + B.tile_base + tt.y] = 0.0;   // every slot written each step
+      for (int c = 0; c < 12; c++) red[c] = mine ? part[c] : 0.0;
+      block_sum<NT, 12>(red, sred, out, a.nslot);
+      __syncthreads();   // sred serves the next colloid's sum
+    } else if (tid < 12) {
+      out[tid * a.nslot] = 0.0;
+    }
   }
 }
 
@@ -654,10 +670,14 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   static_assert(std::is_same<R, float>::value, "the marching kernel is FP32 only");
   const FieldBuf bfin(a.fin, NS, 19), bfout(a.fout, NS, 19), bqin(a.Qin, NS, 5), bqout(a.Qout, NS, 5),
       buin(a.uin, NS, 3), buout(a.uout, NS, 3);
-  const double Rc[3] = {B.pos[a.par][0], B.pos[a.par][1], B.pos[a.par][2]};
+  // boxes on the marching kernel hold at most one colloid (the runtime sends
+  // boxes with more to the 3D-tile kernel); the table has at least one entry
+  const bool has = B.ncol > 0;
+  const ColDev& C = a.cols[has ? B.col0 : 0];
+  const double Rc[3] = {C.pos[a.par][0], C.pos[a.par][1], C.pos[a.par][2]};
   // nominal extent (whole groups): every group's own test (in k_post)
   // covers a subset of this range, so a group counted there was written here
-  const bool near = block_near(B, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, ng * kGroup + 4);
+  const bool near = has && block_near(B, C, Rc, x0 - 2, y0 - 2, z0 - 2, TX + 4, TY + 4, ng * kGroup + 4);
   const Mat<R> mp(B);
   const int tid = threadIdx.x;
   const int lx = tid % TX, ly = tid / TX;
@@ -709,7 +729,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
       if (m < MQ - 1 || e < QP) {
 #pragma unroll
         for (int c = 0; c < 5; c++) sm.Q[slot][c * QP + e] = rq[m][c];
-        sm.S[slot][e] = near ? (unsigned char)inside(B, Rc, qwx[m], qwy[m], wz) : (unsigned char)0;
+        sm.S[slot][e] = near ? (unsigned char)inside(B, C, Rc, qwx[m], qwy[m], wz) : (unsigned char)0;
       }
     }
   };
@@ -732,7 +752,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
       if (!sm.S[qslot][(ey + 1) * QPX + ex + 1]) continue;
       double r[3], ub[3];
       rel_pos(B, Rc, (double)wrapn(x0 - 1 + ex, nx), (double)wrapn(y0 - 1 + ey, ny), (double)wz, r);
-      rigid_vel(B, r, ub);
+      rigid_vel(C, r, ub);
 #pragma unroll
       for (int c = 0; c < 3; c++) sm.U[uslot][c * UP + e] = (R)ub[c];
     }
@@ -815,7 +835,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
         t += r[w * 12 + tid];
         r[w * 12 + tid] = 0.0;
       }
-      a.part[tid * a.nslot + B.tile_base + cb + (long long)ncb * (g0 + g)] = t;
+      a.part[tid * a.nslot + C.slot_base + cb + (long long)ncb * (g0 + g)] = t;
     }
   };
 
@@ -891,7 +911,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
     const int iu = (ly + 1) * UPX + lx + 1;
     const bool fluid = !sm.S[qs_0][ic];
     // the solid-aware update only where plane k's links can reach the colloid
-    const bool pnear = near && block_near(B, Rc, x0 - 2, y0 - 2, k - 2, TX + 4, TY + 4, 5);
+    const bool pnear = near && block_near(B, C, Rc, x0 - 2, y0 - 2, k - 2, TX + 4, TY + 4, 5);
     auto update = [&](auto near_tag) {
       constexpr bool NEAR = decltype(near_tag)::value;
       R q5[5], dQ[5];
@@ -1050,7 +1070,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
         if (NEAR && anys) {
           double r[3], ub[3];
           rel_pos(B, Rc, (double)gx, (double)gy, (double)gz, r);
-          rigid_vel(B, r, ub);
+          rigid_vel(C, r, ub);
 #pragma unroll
           for (int c = 0; c < 3; c++) ubs[c] = (R)ub[c];
         }
@@ -1131,9 +1151,9 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   flush((zend - 1 - z0) / kGroup);
   // far from the colloid every group's sums are zero: write them, so that
   // k_post can add all slots without repeating the geometry test
-  if (!near && tid < 12)
+  if (has && !near && tid < 12)
     for (int g = 0; g < (zend - z0 + kGroup - 1) / kGroup; g++)
-      a.part[tid * a.nslot + B.tile_base + cb + (long long)ncb * (g0 + g)] = 0.0;
+      a.part[tid * a.nslot + C.slot_base + cb + (long long)ncb * (g0 + g)] = 0.0;
 }
 
 // ---------------------------------------------------------------------
@@ -1155,14 +1175,14 @@ __device__ inline long long site_of(const BoxDev& B, int x, int y, int z) {
 // face neighbours that are fluid before and after the move, rounded to the
 // storage precision.
 template <typename R>
-__device__ inline void exposed_q(const BoxDev& B, const double Rold[3], const double Rnew[3], int x, int y, int z,
-                                 const R* Q, long long NS, double q5[5]) {
+__device__ inline void exposed_q(const BoxDev& B, const ColDev& C, const double Rold[3], const double Rnew[3], int x,
+                                 int y, int z, const R* Q, long long NS, double q5[5]) {
   const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
   double qm[5] = {0, 0, 0, 0, 0};
   int nf = 0;
   for (int k = 0; k < 6; k++) {
     const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
-    if (inside(B, Rold, xn, yn, zn) || inside(B, Rnew, xn, yn, zn)) continue;
+    if (inside(B, C, Rold, xn, yn, zn) || inside(B, C, Rnew, xn, yn, zn)) continue;
     const long long gn = site_of(B, xn, yn, zn);
     for (int c = 0; c < 5; c++) qm[c] += (double)Q[c * NS + gn];
     nf++;
@@ -1171,18 +1191,20 @@ __device__ inline void exposed_q(const BoxDev& B, const double Rold[3], const do
 }
 
 template <typename R>
-__device__ inline void ghost_finish(const BoxDev& B, const double Rc[3], int x, int y, int z, double (&qbar)[3][3],
-                                    int nf, R* __restrict__ Q, long long NS);
+__device__ inline void ghost_finish(const BoxDev& B, const ColDev& C, const double Rc[3], int x, int y, int z,
+                                    double (&qbar)[3][3], int nf, R* __restrict__ Q, long long NS);
 
-// Anchoring at node (x, y, z) for the colloid at Rc: if the node is solid
+// Anchoring at node (x, y, z) for colloid C at Rc: if the node is solid
 // with at least one fluid face neighbour, Q there becomes Q^0 (or its blend
 // with the neighbours' mean for finite W).  When the colloid has just moved
 // from Rold, neighbours it uncovered get their Q in this same pass, so their
-// value is formed here by the same rule instead of being read.
+// value is formed here by the same rule instead of being read.  Other
+// colloids of the box stay out of reach (their surfaces are at least
+// kColloidGap away), so only C is tested.
 template <typename R>
-__device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const double Rc[3], bool moved, int x,
-                                  int y, int z, R* __restrict__ Q, long long NS) {
-  if (!inside(B, Rc, x, y, z)) return;
+__device__ inline void ghost_site(const BoxDev& B, const ColDev& C, const double Rold[3], const double Rc[3],
+                                  bool moved, int x, int y, int z, R* __restrict__ Q, long long NS) {
+  if (!inside(B, C, Rc, x, y, z)) return;
   double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   int nf = 0;
   if (B.st27) {
@@ -1193,11 +1215,11 @@ __device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const d
         for (int dx = -1; dx <= 1; dx++) {
           if (!(dx || dy || dz)) continue;
           const int xn = wrapc(x + dx, B.nx), yn = wrapc(y + dy, B.ny), zn = wrapc(z + dz, B.nz);
-          if (inside(B, Rc, xn, yn, zn)) continue;
+          if (inside(B, C, Rc, xn, yn, zn)) continue;
           double qq[3][3];
-          if (moved && inside(B, Rold, xn, yn, zn)) {
+          if (moved && inside(B, C, Rold, xn, yn, zn)) {
             double q5[5];
-            exposed_q<R>(B, Rold, Rc, xn, yn, zn, Q, NS, q5);
+            exposed_q<R>(B, C, Rold, Rc, xn, yn, zn, Q, NS, q5);
             qq[0][0] = q5[0]; qq[0][1] = q5[1]; qq[0][2] = q5[2];
             qq[1][0] = q5[1]; qq[1][1] = q5[3]; qq[1][2] = q5[4];
             qq[2][0] = q5[2]; qq[2][1] = q5[4]; qq[2][2] = -q5[0] - q5[3];
@@ -1208,7 +1230,7 @@ __device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const d
             for (int j = 0; j < 3; j++) qbar[i][j] += qq[i][j];
           nf++;
         }
-    ghost_finish<R>(B, Rc, x, y, z, qbar, nf, Q, NS);
+    ghost_finish<R>(B, C, Rc, x, y, z, qbar, nf, Q, NS);
     return;
   }
   const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
@@ -1220,15 +1242,15 @@ __device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const d
   for (int k = 0; k < 6; k++) {
     const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
     load_full(Q, NS, site_of(B, xn, yn, zn), qn[k]);
-    fl[k] = !inside(B, Rc, xn, yn, zn);
+    fl[k] = !inside(B, C, Rc, xn, yn, zn);
   }
   if (moved) {
 #pragma unroll
     for (int k = 0; k < 6; k++) {
       const int xn = wrapc(x + nb[k][0], B.nx), yn = wrapc(y + nb[k][1], B.ny), zn = wrapc(z + nb[k][2], B.nz);
-      if (!fl[k] || !inside(B, Rold, xn, yn, zn)) continue;
+      if (!fl[k] || !inside(B, C, Rold, xn, yn, zn)) continue;
       double q5[5];
-      exposed_q<R>(B, Rold, Rc, xn, yn, zn, Q, NS, q5);
+      exposed_q<R>(B, C, Rold, Rc, xn, yn, zn, Q, NS, q5);
       qn[k][0][0] = q5[0]; qn[k][0][1] = q5[1]; qn[k][0][2] = q5[2];
       qn[k][1][0] = q5[1]; qn[k][1][1] = q5[3]; qn[k][1][2] = q5[4];
       qn[k][2][0] = q5[2]; qn[k][2][1] = q5[4]; qn[k][2][2] = -q5[0] - q5[3];
@@ -1241,29 +1263,29 @@ __device__ inline void ghost_site(const BoxDev& B, const double Rold[3], const d
       for (int j = 0; j < 3; j++) qbar[i][j] += qn[k][i][j];
     nf++;
   }
-  ghost_finish<R>(B, Rc, x, y, z, qbar, nf, Q, NS);
+  ghost_finish<R>(B, C, Rc, x, y, z, qbar, nf, Q, NS);
 }
 
 // Ghost Q of a solid node from the sum qbar of its nf fluid neighbours:
 // nothing for an interior node (nf = 0), else Q^0 (fixed anchoring), its
 // blend with the neighbours' mean (finite W) or the mean (no anchoring).
 template <typename R>
-__device__ inline void ghost_finish(const BoxDev& B, const double Rc[3], int x, int y, int z, double (&qbar)[3][3],
-                                    int nf, R* __restrict__ Q, long long NS) {
+__device__ inline void ghost_finish(const BoxDev& B, const ColDev& C, const double Rc[3], int x, int y, int z,
+                                    double (&qbar)[3][3], int nf, R* __restrict__ Q, long long NS) {
   if (nf == 0) return;  // interior solid node
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) qbar[i][j] /= nf;
   double qs[3][3];
-  if (B.anchoring == 0) {
+  if (C.anchoring == 0) {
     for (int i = 0; i < 3; i++)
       for (int j = 0; j < 3; j++) qs[i][j] = qbar[i][j];
   } else {
     double q0[3][3];
-    anchor_target(B, Rc, x, y, z, qbar, q0);
-    const bool fixed = isinf(B.W);
+    anchor_target(B, C, Rc, x, y, z, qbar, q0);
+    const bool fixed = isinf(C.W);
     for (int i = 0; i < 3; i++)
       for (int j = 0; j < 3; j++)
-        qs[i][j] = fixed ? q0[i][j] : (B.K * qbar[i][j] + B.W * q0[i][j]) / (B.K + B.W);
+        qs[i][j] = fixed ? q0[i][j] : (B.K * qbar[i][j] + C.W * q0[i][j]) / (B.K + C.W);
   }
   const long long g = site_of(B, x, y, z);
   Q[g] = (R)qs[0][0]; Q[NS + g] = (R)qs[0][1]; Q[2 * NS + g] = (R)qs[0][2];
@@ -1279,47 +1301,48 @@ __device__ inline void cube_site(const BoxDev& B, const double R[3], int E, long
 }
 
 // Stand-alone anchoring pass over one Q buffer (colloids at their current
-// positions).
+// positions): one thread per ghost candidate of every colloid.
 template <typename R>
 __global__ void __launch_bounds__(256)
-    k_ghost(const BoxDev* __restrict__ boxes, int nbox, long long total, R* __restrict__ Q, long long NS, int par) {
+    k_ghost(const BoxDev* __restrict__ boxes, const ColDev* __restrict__ cols, int ncol, long long total,
+            R* __restrict__ Q, long long NS, int par) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
-  int b = 0;
-  for (int k = 1; k < nbox; k++)
-    if (t >= boxes[k].ghost_base) b = k;
-  const BoxDev& B = boxes[b];
-  if (!B.present) return;
-  const int E = B.ghost_ext;
-  const long long l = t - B.ghost_base;
+  int k = 0;
+  for (int j = 1; j < ncol; j++)
+    if (t >= cols[j].ghost_base) k = j;
+  const ColDev& C = cols[k];
+  const BoxDev& B = boxes[C.box];
+  const int E = C.ghost_ext;
+  const long long l = t - C.ghost_base;
   if (l >= (long long)E * E * E) return;
-  const double Rc[3] = {B.pos[par][0], B.pos[par][1], B.pos[par][2]};
+  const double Rc[3] = {C.pos[par][0], C.pos[par][1], C.pos[par][2]};
   int x, y, z;
   cube_site(B, Rc, E, l, x, y, z);
-  ghost_site<R>(B, Rc, Rc, false, x, y, z, Q, NS);
+  ghost_site<R>(B, C, Rc, Rc, false, x, y, z, Q, NS);
 }
 
 // ---------------------------------------------------------------------
 // moving-boundary events (prescribed motion)
 // ---------------------------------------------------------------------
-__device__ inline void advanced_pos(const BoxDev& B, int par, double Rn[3]) {
+__device__ inline void advanced_pos(const BoxDev& B, const ColDev& C, int par, double Rn[3]) {
   const int L[3] = {B.nx, B.ny, B.nz};
   for (int c = 0; c < 3; c++) {
-    double r = __dadd_rn(B.pos[par][c], B.vel[c]);
+    double r = __dadd_rn(C.pos[par][c], C.vel[c]);
     if (r >= L[c]) r = __dsub_rn(r, (double)L[c]);
     if (r < 0.0) r = __dadd_rn(r, (double)L[c]);
     Rn[c] = r;
   }
 }
 
-// Node (x, y, z) when the colloid moves Rc -> Rn: a node it uncovers gets
+// Node (x, y, z) when colloid C moves Rc -> Rn: a node it uncovers gets
 // fluid at rest in the wall frame and Q from its face neighbours; a node it
 // covers gives its fluid momentum to the colloid.  p and the torque about
-// Rn go to v[0..2] and v[6..8].
+// Rn go to v[0..2] and v[6..8].  Other colloids are out of reach (gap).
 template <typename R>
-__device__ inline void event_site(const BoxDev& B, const double Rc[3], const double Rn[3], int x, int y, int z,
-                                  const StepPtrs<R>& a, double v[12]) {
-  const bool was = inside(B, Rc, x, y, z), now = inside(B, Rn, x, y, z);
+__device__ inline void event_site(const BoxDev& B, const ColDev& C, const double Rc[3], const double Rn[3], int x,
+                                  int y, int z, const StepPtrs<R>& a, double v[12]) {
+  const bool was = inside(B, C, Rc, x, y, z), now = inside(B, C, Rn, x, y, z);
   if (was == now) return;
   const long long NS = a.nsites;
   const long long g = site_of(B, x, y, z);
@@ -1327,7 +1350,7 @@ __device__ inline void event_site(const BoxDev& B, const double Rc[3], const dou
   rel_pos(B, Rn, (double)x, (double)y, (double)z, r);
   if (was) {
     double ub[3];
-    rigid_vel(B, r, ub);
+    rigid_vel(C, r, ub);
     if (B.hydro) {
       const double usq = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
 #pragma unroll
@@ -1340,7 +1363,7 @@ __device__ inline void event_site(const BoxDev& B, const double Rc[3], const dou
       for (int c = 0; c < 3; c++) a.uout[c * NS + g] = (R)ub[c];
     }
     double q5[5];
-    exposed_q<R>(B, Rc, Rn, x, y, z, a.Qout, NS, q5);
+    exposed_q<R>(B, C, Rc, Rn, x, y, z, a.Qout, NS, q5);
     for (int c = 0; c < 5; c++) a.Qout[c * NS + g] = (R)q5[c];
   } else if (B.hydro) {
 #pragma unroll
@@ -1358,22 +1381,22 @@ __device__ inline void event_site(const BoxDev& B, const double Rc[3], const dou
 // ---------------------------------------------------------------------
 // post-step: events, next step's ghost Q, colloid sums, history, R += v
 // ---------------------------------------------------------------------
-// Force, torque and history entry of one finished step of box b: the block
-// vectors of its post-step kernel added in block order (nt threads).  Every
-// load (block vectors, step count, the pending flag when one is given) is
-// issued before the first sum, so the finish costs one memory round trip;
-// each thread still adds its vectors in increasing block order.  With a flag
-// that reads zero nothing is written.
+// Force, torque and history entry of one finished step of colloid g (table
+// index): the block vectors of its post-step kernel added in block order
+// (nt threads).  Every load (block vectors, step count, the pending flag
+// when one is given) is issued before the first sum, so the finish costs one
+// memory round trip; each thread still adds its vectors in increasing block
+// order.  With a flag that reads zero nothing is written.
 template <int NT>
-__device__ inline void finish_box(BoxDev& B, int b, const double* __restrict__ bpart, const double* __restrict__ fsum,
-                                  double* __restrict__ force, double* __restrict__ hist, int cap,
-                                  long long* __restrict__ count, double* sred, double* sres,
-                                  const int* __restrict__ pend = nullptr) {
+__device__ inline void finish_colloid(ColDev& C, int g, const double* __restrict__ bpart,
+                                      const double* __restrict__ fsum, double* __restrict__ force,
+                                      double* __restrict__ hist, int cap, long long* __restrict__ count, double* sred,
+                                      double* sres, const int* __restrict__ pend = nullptr) {
   constexpr int KB = 4;   // block vectors in flight per thread
   const bool go = pend == nullptr || *pend != 0;
-  const long long n = count[b];
-  const int nblk = B.post_nblk;
-  const double* p0 = bpart + 12LL * B.post_blk0;
+  const long long n = count[g];
+  const int nblk = C.post_nblk;
+  const double* p0 = bpart + 12LL * C.post_blk0;
   double w[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int k0 = 0; k0 < nblk; k0 += KB * NT) {
     double t[KB][12];
@@ -1396,34 +1419,35 @@ __device__ inline void finish_box(BoxDev& B, int b, const double* __restrict__ b
   // a free colloid: the link and stress sums were added before the move
   // (k_free); the block vectors hold the events' momentum, which also goes
   // to its velocity
-  const bool free_motion = B.present && B.motion == 2;
+  const bool free_motion = C.motion == 2;
   if (threadIdx.x < 12) {
-    const double val = !B.present ? 0.0 : (free_motion ? fsum[12 * b + threadIdx.x] + sres[threadIdx.x] : sres[threadIdx.x]);
-    force[12 * b + threadIdx.x] = val;
-    hist[((long long)b * cap + (n % cap)) * 12 + threadIdx.x] = val;
+    const double val = free_motion ? fsum[12 * g + threadIdx.x] + sres[threadIdx.x] : sres[threadIdx.x];
+    force[12 * g + threadIdx.x] = val;
+    hist[((long long)g * cap + (n % cap)) * 12 + threadIdx.x] = val;
   }
   if (threadIdx.x == 0) {
     if (free_motion)
       for (int k = 0; k < 3; k++) {
-        B.vel[k] += sres[k] / B.mass;
-        B.omega[k] += sres[6 + k] / B.inertia;
+        C.vel[k] += sres[k] / C.mass;
+        C.omega[k] += sres[6 + k] / C.inertia;
       }
-    count[b] = n + 1;
+    count[g] = n + 1;
   }
 }
 
-// Free colloids, one block per box, after the fused kernel: the step's link
-// and stress sums (all slots, fixed order) into fsum, then
-// vel += (F_bbl + F_stress + fext)/M, omega += (T_bbl + T_stress)/I and the
-// next position pos[par ^ 1] = pos[par] + vel.
+// Free colloids, one block per colloid of the table, after the fused
+// kernel: the step's link and stress sums (all its slots, fixed order) into
+// fsum, then vel += (F_bbl + F_stress + fext)/M, omega += (T_bbl + T_stress)/I
+// and the next position pos[par ^ 1] = pos[par] + vel.
 __global__ void __launch_bounds__(kFinishBlock)
-    k_free(BoxDev* __restrict__ boxes, const double* __restrict__ part, long long nslot, int par,
-           double* __restrict__ fsum) {
+    k_free(const BoxDev* __restrict__ boxes, ColDev* __restrict__ cols, const double* __restrict__ part,
+           long long nslot, int par, double* __restrict__ fsum) {
   __shared__ double sred[(kFinishBlock / 64) * 12];
   __shared__ double sres[12];
-  const int b = blockIdx.x;
-  BoxDev& B = boxes[b];
-  if (!(B.present && B.motion == 2)) return;
+  const int g = blockIdx.x;
+  ColDev& C = cols[g];
+  if (C.motion != 2) return;
+  const BoxDev& B = boxes[C.box];
   const long long nt = (long long)B.ntx * B.nty * B.ntz;
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // two slots per thread in flight (more would spill at 1024 threads),
@@ -1434,7 +1458,7 @@ __global__ void __launch_bounds__(kFinishBlock)
 #pragma unroll
     for (int j = 0; j < KS; j++) {
       const long long k = k0 + j * kFinishBlock + threadIdx.x;
-      const double* p = part + B.tile_base + (k < nt ? k : 0);
+      const double* p = part + C.slot_base + (k < nt ? k : 0);
 #pragma unroll
       for (int c = 0; c < 12; c++) t[j][c] = p[c * nslot];
     }
@@ -1446,73 +1470,76 @@ __global__ void __launch_bounds__(kFinishBlock)
   }
   block_sum<kFinishBlock, 12>(v, sred, sres);
   __syncthreads();
-  if (threadIdx.x < 12) fsum[12 * b + threadIdx.x] = sres[threadIdx.x];
+  if (threadIdx.x < 12) fsum[12 * g + threadIdx.x] = sres[threadIdx.x];
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; k++) {
-      B.vel[k] += (sres[k] + sres[3 + k] + B.fext[k]) / B.mass;
-      B.omega[k] += (sres[6 + k] + sres[9 + k]) / B.inertia;
+      C.vel[k] += (sres[k] + sres[3 + k] + C.fext[k]) / C.mass;
+      C.omega[k] += (sres[6 + k] + sres[9 + k]) / C.inertia;
     }
     double Rn[3];
-    advanced_pos(B, par, Rn);
-    B.pos[par ^ 1][0] = Rn[0]; B.pos[par ^ 1][1] = Rn[1]; B.pos[par ^ 1][2] = Rn[2];
+    advanced_pos(B, C, par, Rn);
+    C.pos[par ^ 1][0] = Rn[0]; C.pos[par ^ 1][1] = Rn[1]; C.pos[par ^ 1][2] = Rn[2];
   }
 }
 
-// Threads of box b, in three ranges: fused-kernel slot sums (kPostSlots
+// Threads of colloid g, in three ranges: fused-kernel slot sums (kPostSlots
 // consecutive slots each; every slot was written this step, zeros where the
 // colloid is out of reach, so all are added), then one thread per event
 // candidate, then one per ghost candidate.  Each thread has one role, so
 // the roles' memory latencies overlap.  Each block adds its threads'
 // 12-vectors (slot sums and event momenta) in thread order into its slot of
-// this step's half of bpart.  The last block of a box has no such role: it
-// finishes the previous step of the box if that is still pending (adding
-// the previous half's block vectors in block order) while the others work,
-// writes the next position and marks this step pending; the post-step
-// kernel of the next step (or k_finish, from the host) finishes it.
+// this step's half of bpart.  The last block of a colloid has no such role:
+// it finishes the previous step of the colloid if that is still pending
+// (adding the previous half's block vectors in block order) while the
+// others work, checks that the colloid started this step at least
+// kColloidGap (surface to surface) from the box's other colloids, writes
+// the next position and marks this step pending; the post-step kernel of the
+// next step (or k_finish, from the host) finishes it.
 template <typename R>
 __global__ void __launch_bounds__(kPostBlock)
-    k_post(BoxDev* __restrict__ boxes, int nbox, StepPtrs<R> a, double* __restrict__ bpart,
+    k_post(const BoxDev* __restrict__ boxes, int ncol, StepPtrs<R> a, double* __restrict__ bpart,
            int* __restrict__ pending, const double* __restrict__ fsum, double* __restrict__ force,
            double* __restrict__ hist, int cap, long long* __restrict__ count, int nblk_all) {
   __shared__ double sred[(kPostBlock / 64) * 12];
   __shared__ double sres[12];
-  int b = 0;
-  for (int k = 1; k < nbox; k++)
-    if ((int)blockIdx.x >= boxes[k].post_blk0) b = k;
-  BoxDev& B = boxes[b];
+  int g = 0;
+  for (int k = 1; k < ncol; k++)
+    if ((int)blockIdx.x >= a.cols[k].post_blk0) g = k;
+  ColDev& C = a.cols[g];
+  const BoxDev& B = boxes[C.box];
   const int par = a.par;
-  const bool finisher = (int)blockIdx.x == B.post_blk0 + B.post_nblk - 1;
+  const bool finisher = (int)blockIdx.x == C.post_blk0 + C.post_nblk - 1;
   // the positions first: the finish below changes only a free colloid's
   // velocity, which the next position (already formed by k_free) does not use
-  const double Rc[3] = {B.pos[par][0], B.pos[par][1], B.pos[par][2]};
-  const bool free_motion = B.present && B.motion == 2;
-  const bool moving = B.present && B.motion != 0;
+  const double Rc[3] = {C.pos[par][0], C.pos[par][1], C.pos[par][2]};
+  const bool free_motion = C.motion == 2;
+  const bool moving = C.motion != 0;
   double Rn[3] = {Rc[0], Rc[1], Rc[2]};
   if (free_motion) {
     // k_free has moved it already
-    Rn[0] = B.pos[par ^ 1][0]; Rn[1] = B.pos[par ^ 1][1]; Rn[2] = B.pos[par ^ 1][2];
+    Rn[0] = C.pos[par ^ 1][0]; Rn[1] = C.pos[par ^ 1][1]; Rn[2] = C.pos[par ^ 1][2];
   } else if (moving) {
-    advanced_pos(B, par, Rn);
+    advanced_pos(B, C, par, Rn);
   }
   if (finisher) {
-    finish_box<kPostBlock>(B, b, bpart + 12LL * nblk_all * (par ^ 1), fsum, force, hist, cap, count, sred, sres,
-                           pending + b);
+    finish_colloid<kPostBlock>(C, g, bpart + 12LL * nblk_all * (par ^ 1), fsum, force, hist, cap, count, sred, sres,
+                               pending + g);
     __syncthreads();
   }
-  long long l = (long long)((int)blockIdx.x - B.post_blk0) * kPostBlock + threadIdx.x;
+  long long l = (long long)((int)blockIdx.x - C.post_blk0) * kPostBlock + threadIdx.x;
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (B.present) {
+  {
     const long long nt = (long long)B.ntx * B.nty * B.ntz;
     const long long nst = free_motion ? 0 : (nt + kPostSlots - 1) / kPostSlots;
-    const long long ne = moving ? (long long)B.event_ext * B.event_ext * B.event_ext : 0;
-    const long long ng = (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
+    const long long ne = moving ? (long long)C.event_ext * C.event_ext * C.event_ext : 0;
+    const long long ng = (long long)C.ghost_ext * C.ghost_ext * C.ghost_ext;
     if (l < nst) {
       const long long k0 = l * kPostSlots;
       double t[kPostSlots][12];
 #pragma unroll
       for (int j = 0; j < kPostSlots; j++) {
         const bool ok = k0 + j < nt;
-        const double* p = a.part + B.tile_base + (ok ? k0 + j : 0);
+        const double* p = a.part + C.slot_base + (ok ? k0 + j : 0);
 #pragma unroll
         for (int c = 0; c < 12; c++) t[j][c] = ok ? p[c * a.nslot] : 0.0;
       }
@@ -1524,32 +1551,39 @@ __global__ void __launch_bounds__(kPostBlock)
       l -= nst;
       int x, y, z;
       if (l < ne) {
-        cube_site(B, Rc, B.event_ext, l, x, y, z);
-        event_site<R>(B, Rc, Rn, x, y, z, a, v);
+        cube_site(B, Rc, C.event_ext, l, x, y, z);
+        event_site<R>(B, C, Rc, Rn, x, y, z, a, v);
       } else if (l - ne < ng) {
-        cube_site(B, Rn, B.ghost_ext, l - ne, x, y, z);
-        ghost_site<R>(B, Rc, Rn, moving, x, y, z, a.Qout, a.nsites);
+        cube_site(B, Rn, C.ghost_ext, l - ne, x, y, z);
+        ghost_site<R>(B, C, Rc, Rn, moving, x, y, z, a.Qout, a.nsites);
       }
     }
   }
   block_sum<kPostBlock, 12>(v, sred, bpart + 12LL * nblk_all * par + 12LL * blockIdx.x);
   if (finisher && threadIdx.x == 0) {
-    B.pos[par ^ 1][0] = Rn[0]; B.pos[par ^ 1][1] = Rn[1]; B.pos[par ^ 1][2] = Rn[2];
-    pending[b] = 1;
+    for (int k = 0; k < B.ncol; k++) {
+      const ColDev& D = a.cols[B.col0 + k];
+      if (B.col0 + k == g) continue;
+      double r[3];
+      rel_pos(B, Rc, D.pos[par][0], D.pos[par][1], D.pos[par][2], r);
+      if (sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) < C.a0 + D.a0 + kColloidGap) atomicOr(a.flag, 2);
+    }
+    C.pos[par ^ 1][0] = Rn[0]; C.pos[par ^ 1][1] = Rn[1]; C.pos[par ^ 1][2] = Rn[2];
+    pending[g] = 1;
   }
 }
 
-// One block per box: finishes the pending step of buffer parity par.
+// One block per colloid: finishes the pending step of buffer parity par.
 __global__ void __launch_bounds__(kFinishBlock)
-    k_finish(BoxDev* __restrict__ boxes, int par, int nblk_all, const double* __restrict__ bpart,
+    k_finish(ColDev* __restrict__ cols, int par, int nblk_all, const double* __restrict__ bpart,
              int* __restrict__ pending, const double* __restrict__ fsum, double* __restrict__ force,
              double* __restrict__ hist, int cap, long long* __restrict__ count) {
   __shared__ double sred[(kFinishBlock / 64) * 12];
   __shared__ double sres[12];
-  const int b = blockIdx.x;
-  if (!pending[b]) return;
-  finish_box<kFinishBlock>(boxes[b], b, bpart + 12LL * nblk_all * par, fsum, force, hist, cap, count, sred, sres);
-  if (threadIdx.x == 0) pending[b] = 0;
+  const int g = blockIdx.x;
+  if (!pending[g]) return;
+  finish_colloid<kFinishBlock>(cols[g], g, bpart + 12LL * nblk_all * par, fsum, force, hist, cap, count, sred, sres);
+  if (threadIdx.x == 0) pending[g] = 0;
 }
 
 // ---------------------------------------------------------------------
@@ -1566,10 +1600,12 @@ __global__ void __launch_bounds__(256)
   double v[6] = {0, 0, 0, 0, 0, 0};
   if (t < nsite) {
     const int x = (int)(t % B.nx), y = (int)((t / B.nx) % B.ny), z = (int)(t / ((long long)B.nx * B.ny));
-    const double Rc[3] = {B.pos[a.par][0], B.pos[a.par][1], B.pos[a.par][2]};
-    auto solid = [&](int xx, int yy, int zz) {
-      return B.present && inside(B, Rc, wrapc(xx, B.nx), wrapc(yy, B.ny), wrapc(zz, B.nz));
+    const unsigned all = B.ncol >= 32 ? ~0u : (1u << B.ncol) - 1u;
+    // 1 + the colloid holding the node, 0 for fluid
+    auto sid = [&](int xx, int yy, int zz) {
+      return solid_id(B, a.cols, all, a.par, wrapc(xx, B.nx), wrapc(yy, B.ny), wrapc(zz, B.nz));
     };
+    auto solid = [&](int xx, int yy, int zz) { return sid(xx, yy, zz) != 0; };
     auto gidx = [&](int xx, int yy, int zz) {
       return B.off + wrapc(xx, B.nx) + (long long)B.nx * (wrapc(yy, B.ny) + (long long)B.ny * wrapc(zz, B.nz));
     };
@@ -1631,7 +1667,6 @@ __global__ void __launch_bounds__(256)
         v[5] = sqrt(u2);
       }
     }
-    const bool finiteW = B.present && B.anchoring != 0 && !isinf(B.W);
     for (int c = 0; c < 3; c++) {
       const int xn = x + (c == 0), yn = y + (c == 1), zn = z + (c == 2);
       const bool sn = solid(xn, yn, zn);
@@ -1641,9 +1676,10 @@ __global__ void __launch_bounds__(256)
       for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) dd += (qn[i][j] - q[i][j]) * (qn[i][j] - q[i][j]);
       v[0] += 0.5 * K * dd;
-      if (finiteW && sx != sn) {
+      const int xs = sx ? x : xn, ys = sx ? y : yn, zs = sx ? z : zn;
+      const ColDev* Cs = sx != sn ? &a.cols[B.col0 + sid(xs, ys, zs) - 1] : nullptr;
+      if (Cs && Cs->anchoring != 0 && !isinf(Cs->W)) {
         // W/2 |Qs - Q^0|^2 at the solid end of the face
-        const int xs = sx ? x : xn, ys = sx ? y : yn, zs = sx ? z : zn;
         const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
         double qbar[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, qs[3][3], qz[3][3];
         int nf = 0;
@@ -1670,12 +1706,12 @@ __global__ void __launch_bounds__(256)
         }
         for (int i = 0; i < 3; i++)
           for (int j = 0; j < 3; j++) qbar[i][j] /= nf;
-        anchor_target(B, Rc, wrapc(xs, B.nx), wrapc(ys, B.ny), wrapc(zs, B.nz), qbar, qz);
+        anchor_target(B, *Cs, Cs->pos[a.par], wrapc(xs, B.nx), wrapc(ys, B.ny), wrapc(zs, B.nz), qbar, qz);
         load_full(a.Qin, NS, gidx(xs, ys, zs), qs);
         double w2 = 0;
         for (int i = 0; i < 3; i++)
           for (int j = 0; j < 3; j++) w2 += (qs[i][j] - qz[i][j]) * (qs[i][j] - qz[i][j]);
-        v[0] += 0.5 * B.W * w2;
+        v[0] += 0.5 * Cs->W * w2;
       }
     }
   }
@@ -1728,22 +1764,35 @@ __device__ inline double lambda_max(const double q[3][3]) {
 
 template <typename R>
 __global__ void __launch_bounds__(256)
-    k_defects(const BoxDev* __restrict__ boxes, int box, const R* __restrict__ Q, long long NS, double thr,
-              unsigned char* __restrict__ mask, unsigned long long* __restrict__ count, int par) {
+    k_defects(const BoxDev* __restrict__ boxes, const ColDev* __restrict__ cols, int box, const R* __restrict__ Q,
+              long long NS, double thr, unsigned char* __restrict__ mask, unsigned long long* __restrict__ count,
+              int par) {
   const BoxDev& B = boxes[box];
   const long long nsite = (long long)B.nx * B.ny * B.nz;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nsite) return;
   const int x = (int)(t % B.nx), y = (int)((t / B.nx) % B.ny), z = (int)(t / ((long long)B.nx * B.ny));
-  const double Rc[3] = {B.pos[par][0], B.pos[par][1], B.pos[par][2]};
+  const unsigned all = (1u << B.ncol) - 1u;
   unsigned char m = 0;
-  if (!(B.present && inside(B, Rc, x, y, z))) {
+  if (!solid_id(B, cols, all, par, x, y, z)) {
     double q[3][3];
     load_full(Q, NS, B.off + t, q);
     m = 1.5 * lambda_max(q) < thr;
   }
   mask[t] = m;
   if (m) atomicAdd(count, 1ULL);
+}
+
+// Solid map of one box: 1 + the colloid holding the node, 0 for fluid.
+__global__ void __launch_bounds__(256)
+    k_solid(const BoxDev* __restrict__ boxes, const ColDev* __restrict__ cols, int box, unsigned char* __restrict__ id,
+            int par) {
+  const BoxDev& B = boxes[box];
+  const long long nsite = (long long)B.nx * B.ny * B.nz;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsite) return;
+  const int x = (int)(t % B.nx), y = (int)((t / B.nx) % B.ny), z = (int)(t / ((long long)B.nx * B.ny));
+  id[t] = (unsigned char)solid_id(B, cols, (1u << B.ncol) - 1u, par, x, y, z);
 }
 
 template <typename R>
@@ -1804,30 +1853,34 @@ int march_blocks_per_cu(int tile) {
 }
 
 template <typename R>
-hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, int par, hipStream_t s) {
-  if (total <= 0) return hipSuccess;
+hipError_t launch_ghost(const BoxDev* boxes, const ColDev* cols, int ncol, long long total, R* Q, long long NS, int par,
+                        hipStream_t s) {
+  if (total <= 0 || ncol <= 0) return hipSuccess;
   // small blocks: the few thousand boundary candidates spread over many CUs
-  k_ghost<R><<<(unsigned)((total + 63) / 64), 64, 0, s>>>(boxes, nbox, total, Q, NS, par);
+  k_ghost<R><<<(unsigned)((total + 63) / 64), 64, 0, s>>>(boxes, cols, ncol, total, Q, NS, par);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
+hipError_t launch_post(int nblk, int ncol, const BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
                        const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s) {
-  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, nbox, a, bpart, pending, fsum, force, hist, cap, count,
+  if (ncol <= 0 || nblk <= 0) return hipSuccess;
+  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, ncol, a, bpart, pending, fsum, force, hist, cap, count,
                                                   nblk);
   return hipGetLastError();
 }
 
-hipError_t launch_free(int nbox, BoxDev* boxes, const double* part, long long nslot, int par, double* fsum,
-                       hipStream_t s) {
-  k_free<<<(unsigned)nbox, kFinishBlock, 0, s>>>(boxes, part, nslot, par, fsum);
+hipError_t launch_free(int ncol, const BoxDev* boxes, ColDev* cols, const double* part, long long nslot, int par,
+                       double* fsum, hipStream_t s) {
+  if (ncol <= 0) return hipSuccess;
+  k_free<<<(unsigned)ncol, kFinishBlock, 0, s>>>(boxes, cols, part, nslot, par, fsum);
   return hipGetLastError();
 }
 
-hipError_t launch_finish(int nbox, int nblk, BoxDev* boxes, int par, const double* bpart, int* pending,
+hipError_t launch_finish(int ncol, int nblk, ColDev* cols, int par, const double* bpart, int* pending,
                          const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s) {
-  k_finish<<<(unsigned)nbox, kFinishBlock, 0, s>>>(boxes, par, nblk, bpart, pending, fsum, force, hist, cap, count);
+  if (ncol <= 0) return hipSuccess;
+  k_finish<<<(unsigned)ncol, kFinishBlock, 0, s>>>(cols, par, nblk, bpart, pending, fsum, force, hist, cap, count);
   return hipGetLastError();
 }
 
@@ -1844,9 +1897,16 @@ hipError_t launch_diag_total(const double* part, long long nb, double* out6, hip
 }
 
 template <typename R>
-hipError_t launch_defects(const BoxDev* boxes, int box, long long nsite, const R* Q, long long NS, double thr,
+hipError_t launch_defects(const BoxDev* boxes, const ColDev* cols, int box, long long nsite, const R* Q, long long NS,
+                          double thr,
                           unsigned char* mask, unsigned long long* count, int par, hipStream_t s) {
-  k_defects<R><<<(unsigned)((nsite + 255) / 256), 256, 0, s>>>(boxes, box, Q, NS, thr, mask, count, par);
+  k_defects<R><<<(unsigned)((nsite + 255) / 256), 256, 0, s>>>(boxes, cols, box, Q, NS, thr, mask, count, par);
+  return hipGetLastError();
+}
+
+hipError_t launch_solid(const BoxDev* boxes, const ColDev* cols, int box, long long nsite, unsigned char* id, int par,
+                        hipStream_t s) {
+  k_solid<<<(unsigned)((nsite + 255) / 256), 256, 0, s>>>(boxes, cols, box, id, par);
   return hipGetLastError();
 }
 
@@ -1859,11 +1919,12 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
 #define LC_INST(R)                                                                                        \
   template hipError_t launch_step<R>(int, int, const BoxDev*, const int2*, const int*, const StepPtrs<R>&,   \
                                      hipStream_t, hipEvent_t, hipEvent_t);                                  \
-  template hipError_t launch_ghost<R>(const BoxDev*, int, long long, R*, long long, int, hipStream_t);      \
-  template hipError_t launch_post<R>(int, int, BoxDev*, const StepPtrs<R>&, double*, int*, const double*,    \
+  template hipError_t launch_ghost<R>(const BoxDev*, const ColDev*, int, long long, R*, long long, int,     \
+                                      hipStream_t);                                                         \
+  template hipError_t launch_post<R>(int, int, const BoxDev*, const StepPtrs<R>&, double*, int*, const double*, \
                                      double*, double*, int, long long*, hipStream_t);                        \
   template hipError_t launch_diag<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*, hipStream_t); \
-  template hipError_t launch_defects<R>(const BoxDev*, int, long long, const R*, long long, double,         \
+  template hipError_t launch_defects<R>(const BoxDev*, const ColDev*, int, long long, const R*, long long, double, \
                                         unsigned char*, unsigned long long*, int, hipStream_t);             \
   template hipError_t launch_fill<R>(R*, long long, double, hipStream_t);
 LC_INST(float)

@@ -18,10 +18,12 @@ struct StepPtrs {
   R* uout;
   long long nsites;   // component stride (all boxes)
   double* part;       // colloid partial sums, component-major: part[c * nslot + slot],
-                      // one slot per 3D tile or per (column block, z group)
+                      // per colloid one slot per 3D tile or per (column block, z group)
+                      // of its box (ColDev::slot_base + tile)
   long long nslot;
-  int* flag;          // set to 1 on a non-finite value or |u| >= 0.3
-  int par;            // buffer parity of the step (slot of BoxDev::pos)
+  int* flag;          // bit 0: a non-finite value or |u| >= 0.3; bit 1: two colloids too close
+  int par;            // buffer parity of the step (slot of ColDev::pos)
+  ColDev* cols;       // colloid table (every box's colloids, box by box)
 };
 
 // Block shapes of the fused kernel, per precision: (id, TX, TY, TZ, kind).
@@ -79,26 +81,30 @@ int march_blocks_per_cu(int tile);
 // (before the first step and after any change made from the host), for the
 // colloids at pos[par].
 template <typename R>
-hipError_t launch_ghost(const BoxDev* boxes, int nbox, long long total, R* Q, long long NS, int par, hipStream_t s);
-// After the fused kernel: moving-boundary events, the next step's ghost Q,
-// per-block sums of the fused kernel's colloid slots and the event momenta
-// (nblk blocks, 12 doubles each, into bpart + 12 * nblk * a.par) and the
-// next position pos[a.par ^ 1].  The last block of each box first finishes
-// the previous step if pending[box] is set (its block sums are in the other
-// half of bpart): force, force history, count; then marks this step
-// pending.  A free colloid's slots were added by launch_free (fsum), which
-// also moved it; its block sums then hold only the event momenta.
+hipError_t launch_ghost(const BoxDev* boxes, const ColDev* cols, int ncol, long long total, R* Q, long long NS, int par,
+                        hipStream_t s);
+// After the fused kernel, per colloid of the table: moving-boundary events,
+// the next step's ghost Q, per-block sums of the fused kernel's colloid
+// slots and the event momenta (nblk blocks, 12 doubles each, into bpart +
+// 12 * nblk * a.par), a check of the gap to the box's other colloids (flag
+// bit 1) and the next position pos[a.par ^ 1].  The last block of each
+// colloid first finishes the colloid's previous step if pending[colloid] is
+// set (its block sums are in the other half of bpart): force, force
+// history, count; then marks this step pending.  A free colloid's slots were
+// added by launch_free (fsum), which also moved it; its block sums then hold
+// only the event momenta.
 template <typename R>
-hipError_t launch_post(int nblk, int nbox, BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
+hipError_t launch_post(int nblk, int ncol, const BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
                        const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s);
-// Free colloids (one block per box, others untouched): the step's slot sums
-// into fsum [12 per box], the velocity update and the next position.
-hipError_t launch_free(int nbox, BoxDev* boxes, const double* part, long long nslot, int par, double* fsum,
-                       hipStream_t s);
-// Finish a pending step of buffer parity par (one block per box; boxes with
-// pending[box] == 0 are left alone); a free colloid also receives the
-// events' momentum.
-hipError_t launch_finish(int nbox, int nblk, BoxDev* boxes, int par, const double* bpart, int* pending,
+// Free colloids (one block per colloid of the table, others untouched): the
+// step's slot sums into fsum [12 per colloid], the velocity update and the
+// next position.
+hipError_t launch_free(int ncol, const BoxDev* boxes, ColDev* cols, const double* part, long long nslot, int par,
+                       double* fsum, hipStream_t s);
+// Finish a pending step of buffer parity par (one block per colloid;
+// colloids with pending[k] == 0 are left alone); a free colloid also
+// receives the events' momentum.
+hipError_t launch_finish(int ncol, int nblk, ColDev* cols, int par, const double* bpart, int* pending,
                          const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s);
 template <typename R>
 hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const StepPtrs<R>& a, double* out,
@@ -108,8 +114,11 @@ hipError_t launch_diag(const BoxDev* boxes, int box, long long nsite, const Step
 // component 5.
 hipError_t launch_diag_total(const double* part, long long nb, double* out6, hipStream_t s);
 template <typename R>
-hipError_t launch_defects(const BoxDev* boxes, int box, long long nsite, const R* Q, long long NS, double thr,
-                          unsigned char* mask, unsigned long long* count, int par, hipStream_t s);
+hipError_t launch_defects(const BoxDev* boxes, const ColDev* cols, int box, long long nsite, const R* Q, long long NS,
+                          double thr, unsigned char* mask, unsigned long long* count, int par, hipStream_t s);
+// Solid map of box `box`: id[site] = 1 + the colloid holding it, 0 for fluid.
+hipError_t launch_solid(const BoxDev* boxes, const ColDev* cols, int box, long long nsite, unsigned char* id, int par,
+                        hipStream_t s);
 template <typename R>
 hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s);
 

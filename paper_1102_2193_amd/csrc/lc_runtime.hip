@@ -17,6 +17,7 @@
 #include "lc_kernels.hpp"
 
 using lc::BoxDev;
+using lc::ColDev;
 
 namespace {
 
@@ -84,8 +85,10 @@ struct lc_ctx {
   int prec = LC_FP32;
   size_t esz = 4;
   std::vector<lc_params> prm;
-  std::vector<lc_colloid> col;
+  std::vector<std::vector<lc_colloid>> col;   // per box, its colloids
   std::vector<BoxDev> hb;       // host copy of the descriptors
+  std::vector<ColDev> hc;       // host copy of the colloid table (box by box)
+  int ncol = 0;                 // colloids in all boxes (entries of the table)
   long long nsites = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -95,9 +98,12 @@ struct lc_ctx {
   bool own_buf = true;
   int cur = 0;                  // buffer index holding time n
   BoxDev* dbox = nullptr;
+  ColDev* dcol = nullptr;       // colloid table (at least one entry allocated)
+  size_t dcol_cap = 0;
   int tile = 0;
   int nblk = 0;                 // fused-kernel blocks (incl. XCD padding)
   int ntile = 0;                // real tiles
+  long long nslot = 1;          // colloid slots of the fused kernel (>= 1)
   int2* dtiles = nullptr;
   int* doffs = nullptr;         // marching shapes: item range of each persistent block
   double* dpart = nullptr;      // 12 per tile
@@ -105,13 +111,15 @@ struct lc_ctx {
   int npost = 0;                // blocks of the post-step kernel
   double* dbpart = nullptr;     // 12 per post-step block, one half per buffer parity
   size_t dbpart_cap = 0;
-  int* dpending = nullptr;      // per box: a step whose force sums are not yet added
-  double* dfsum = nullptr;      // 12 per box: link and stress sums of a free colloid's step
+  int* dpending = nullptr;      // per colloid: a step whose force sums are not yet added
+  double* dfsum = nullptr;      // 12 per colloid: link and stress sums of a free colloid's step
   bool maybe_pending = false;   // a step ran since the last finish from the host
   bool ghost_fresh = false;     // ghost Q of buffer cur matches the colloids
-  double* dforce = nullptr;     // 12 per box
-  double* dhist = nullptr;      // nbox * kHistCap * 12
-  long long* dcount = nullptr;  // steps per box on the device
+  double* dforce = nullptr;     // 12 per colloid
+  double* dhist = nullptr;      // colloids * kHistCap * 12
+  long long* dcount = nullptr;  // steps per colloid on the device
+  int col_cap = 0;              // colloids the per-colloid arrays above hold
+  std::vector<int> colbase;     // per box, its first entry of the colloid table
   int* dflag = nullptr;
   double* ddiag = nullptr;
   size_t ddiag_cap = 0;
@@ -154,19 +162,38 @@ void destroy_graph(lc_ctx* c) {
   c->graph_ok = false;
 }
 
-// Read the device copy of the descriptors back (the colloid position, and a
-// free colloid's velocities, change on the device) before the host rewrites
-// them.
+// Read the device copy of the colloid table back (positions, and a free
+// colloid's velocities, change on the device) before the host rewrites it.
 int pull_boxes(lc_ctx* c) {
-  HIPCHK(c, hipMemcpyAsync(c->hb.data(), c->dbox, sizeof(BoxDev) * c->nbox, hipMemcpyDeviceToHost, c->stream));
+  if (c->ncol == 0) return LC_OK;
+  HIPCHK(c, hipMemcpyAsync(c->hc.data(), c->dcol, sizeof(ColDev) * c->ncol, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int b = 0; b < c->nbox; b++)
+  for (const ColDev& C : c->hc) {
+    const int k = (int)(&C - c->hc.data()) - c->colbase[C.box];
+    lc_colloid& h = c->col[C.box][k];
     for (int a = 0; a < 3; a++) {
-      c->col[b].pos[a] = c->hb[b].pos[c->cur][a];
-      c->col[b].vel[a] = c->hb[b].vel[a];       // a free colloid's change on the device
-      c->col[b].omega[a] = c->hb[b].omega[a];
+      h.pos[a] = C.pos[c->cur][a];
+      h.vel[a] = C.vel[a];       // a free colloid's change on the device
+      h.omega[a] = C.omega[a];
     }
+  }
   return LC_OK;
+}
+
+int first_3d_tile(const lc_ctx* c) {
+  for (int t = 0; t < num_tiles(c); t++)
+    if (tile_shape(c, t).kind == 0) return t;
+  return 0;
+}
+
+// Contexts whose boxes hold several colloids, higher-order advection or the
+// 27-point stencil run on the 3D-tile kernel only.
+bool needs_3d(const lc_ctx* c) {
+  for (int b = 0; b < c->nbox; b++) {
+    const BoxDev& B = c->hb[b];
+    if (B.adv != 1 || B.st27 || c->col[b].size() > 1) return true;
+  }
+  return false;
 }
 
 // Can the colloid (radius + 3 + margin) reach the block [lo, lo + ext) in any
@@ -239,7 +266,10 @@ int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& 
   for (int b = 0; b < c->nbox; b++) {
     const BoxDev& B = c->hb[b];
     const lc_params& p = c->prm[b];
-    const lc_colloid& k = c->col[b];
+    lc_colloid none;
+    memset(&none, 0, sizeof(none));
+    // marching boxes hold at most one colloid
+    const lc_colloid& k = c->col[b].empty() ? none : c->col[b][0];
     const int ncb = B.ntx * B.nty;
     for (int cb = 0; cb < ncb; cb++) {
       const int x0 = (cb % B.ntx) * T.x, y0 = (cb / B.ntx) * T.y;
@@ -409,8 +439,9 @@ int march_schedule(lc_ctx* c, const TileShape& T, int slots, std::vector<int2>& 
 // (the next step's post-step kernel would otherwise do it).
 int flush(lc_ctx* c) {
   if (!c->maybe_pending) return LC_OK;
-  HIPCHK(c, lc::launch_finish(c->nbox, c->npost, c->dbox, c->cur ^ 1, c->dbpart, c->dpending, c->dfsum, c->dforce,
-                              c->dhist, kHistCap, c->dcount, c->stream));
+  if (c->ncol > 0)
+    HIPCHK(c, lc::launch_finish(c->ncol, c->npost, c->dcol, c->cur ^ 1, c->dbpart, c->dpending, c->dfsum, c->dforce,
+                                c->dhist, kHistCap, c->dcount, c->stream));
   c->maybe_pending = false;
   return LC_OK;
 }
@@ -420,12 +451,54 @@ int flush(lc_ctx* c) {
 // below 4 GiB.
 bool march_fits(const lc_ctx* c) { return 19.0 * 4.0 * (double)c->nsites < 4294967296.0; }
 
-// Boxes with higher-order advection or the 27-point stencil run on the
-// 3D-tile kernel only.
-bool has_variants(const lc_ctx* c) {
-  for (const BoxDev& B : c->hb)
-    if (B.adv != 1 || B.st27) return true;
-  return false;
+// The per-colloid device arrays (last force, history ring, step count,
+// pending flag, free-motion sums) for a new colloid table whose box b
+// starts at entry base[b] (total entries): colloid k of box b keeps its
+// entries across layouts; colloids a box gains start empty.  The caller has
+// flushed any pending step.
+int resize_colloid_arrays(lc_ctx* c, const std::vector<int>& base, int total) {
+  const int cap = std::max(1, total);
+  if (c->col_cap == cap && c->colbase == base) return LC_OK;
+  double *force = nullptr, *hist = nullptr, *fsum = nullptr;
+  long long* count = nullptr;
+  int* pend = nullptr;
+  const size_t hrow = (size_t)kHistCap * 12;
+  auto bail = [&](hipError_t e) {
+    hipFree(force); hipFree(hist); hipFree(fsum); hipFree(count); hipFree(pend);
+    return fail(c, LC_ENOMEM, std::string("per-colloid arrays: ") + hipGetErrorString(e));
+  };
+  hipError_t e = hipMalloc(&force, sizeof(double) * 12 * cap);
+  if (e == hipSuccess) e = hipMalloc(&hist, sizeof(double) * hrow * cap);
+  if (e == hipSuccess) e = hipMalloc(&fsum, sizeof(double) * 12 * cap);
+  if (e == hipSuccess) e = hipMalloc(&count, sizeof(long long) * cap);
+  if (e == hipSuccess) e = hipMalloc(&pend, sizeof(int) * cap);
+  if (e != hipSuccess) return bail(e);
+  HIPCHK(c, hipMemsetAsync(force, 0, sizeof(double) * 12 * cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(hist, 0, sizeof(double) * hrow * cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(fsum, 0, sizeof(double) * 12 * cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(count, 0, sizeof(long long) * cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(pend, 0, sizeof(int) * cap, c->stream));
+  if (c->col_cap > 0 && !c->colbase.empty()) {
+    for (int b = 0; b < c->nbox; b++) {
+      const int on = (b + 1 < c->nbox ? c->colbase[b + 1] : c->ncol) - c->colbase[b];
+      const int nn = (b + 1 < c->nbox ? base[b + 1] : total) - base[b];
+      const int m = std::min(on, nn);
+      if (m <= 0) continue;
+      const size_t o = c->colbase[b], n = base[b];
+      HIPCHK(c, hipMemcpyAsync(force + 12 * n, c->dforce + 12 * o, sizeof(double) * 12 * m, hipMemcpyDeviceToDevice,
+                               c->stream));
+      HIPCHK(c, hipMemcpyAsync(hist + hrow * n, c->dhist + hrow * o, sizeof(double) * hrow * m,
+                               hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(fsum + 12 * n, c->dfsum + 12 * o, sizeof(double) * 12 * m, hipMemcpyDeviceToDevice,
+                               c->stream));
+      HIPCHK(c, hipMemcpyAsync(count + n, c->dcount + o, sizeof(long long) * m, hipMemcpyDeviceToDevice, c->stream));
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  hipFree(c->dforce); hipFree(c->dhist); hipFree(c->dfsum); hipFree(c->dcount); hipFree(c->dpending);
+  c->dforce = force; c->dhist = hist; c->dfsum = fsum; c->dcount = count; c->dpending = pend;
+  c->col_cap = cap;
+  return LC_OK;
 }
 
 int layout(lc_ctx* c) {
@@ -434,20 +507,22 @@ int layout(lc_ctx* c) {
     if (rc != LC_OK) return rc;
   }
   const TileShape& T = tile_shape(c, c->tile);
-  long long tb = 0, gb = 0;
-  int pblk = 0;
+  long long tb = 0, gb = 0, sb = 0;
+  int pblk = 0, total = 0;
   c->any_colloid = c->any_moving = c->any_free = false;
   std::vector<int2> tiles;
+  std::vector<int> base(c->nbox, 0);
+  std::vector<ColDev> table;
   if (T.kind == 1 && c->nbox > lc::kMaxBoxes) return fail(c, LC_EINVAL, "too many boxes for the marching kernel");
   if (T.kind == 1 && !march_fits(c))
     return fail(c, LC_EINVAL, "context too large for the marching kernel (19 x sites x 4 bytes >= 4 GiB); use a 3D tile");
-  if (T.kind == 1 && has_variants(c))
+  if (T.kind == 1 && needs_3d(c))
     return fail(c, LC_EINVAL,
-                "the marching kernel has first-order advection and the 7-point stencil only; use a 3D tile");
+                "the marching kernel has one colloid per box, first-order advection and the 7-point stencil only; "
+                "use a 3D tile");
   for (int b = 0; b < c->nbox; b++) {
     BoxDev& B = c->hb[b];
     const lc_params& p = c->prm[b];
-    const lc_colloid& k = c->col[b];
     B.ntx = (p.nx + T.x - 1) / T.x;
     B.nty = (p.ny + T.y - 1) / T.y;
     B.tile_base = (int)tb;
@@ -464,48 +539,65 @@ int layout(lc_ctx* c) {
       for (int t = 0; t < nt; t++) tiles.push_back(make_int2(b, t));
       tb += nt;
     }
-    B.present = k.present;
-    B.motion = k.motion;
-    B.anchoring = k.anchoring;
-    for (int a = 0; a < 3; a++) {
-      B.pos[0][a] = B.pos[1][a] = k.pos[a];
-      B.vel[a] = k.vel[a];
-      B.omega[a] = k.omega[a];
-    }
-    B.a0 = k.a0;
-    B.S0 = k.S0;
-    B.W = k.W;
-    {
+    const long long nt = (long long)B.ntx * B.nty * B.ntz;   // slots per colloid of this box
+    base[b] = total;
+    B.col0 = total;
+    B.ncol = (int)c->col[b].size();
+    for (const lc_colloid& k : c->col[b]) {
+      ColDev C;
+      memset(&C, 0, sizeof(C));
+      C.box = b;
+      C.motion = k.motion;
+      C.anchoring = k.anchoring;
+      for (int a = 0; a < 3; a++) {
+        C.pos[0][a] = C.pos[1][a] = k.pos[a];
+        C.vel[a] = k.vel[a];
+        C.omega[a] = k.omega[a];
+        C.fext[a] = k.fext[a];
+      }
+      C.a0 = k.a0;
+      C.S0 = k.S0;
+      C.W = k.W;
       const double rc = k.rho_c > 0.0 ? k.rho_c : p.rho0;
-      const double M = 4.0 / 3.0 * acos(-1.0) * k.a0 * k.a0 * k.a0 * rc;
-      for (int a = 0; a < 3; a++) B.fext[a] = k.fext[a];
-      B.mass = M;
-      B.inertia = 0.4 * M * k.a0 * k.a0;
+      C.mass = 4.0 / 3.0 * acos(-1.0) * k.a0 * k.a0 * k.a0 * rc;
+      C.inertia = 0.4 * C.mass * k.a0 * k.a0;
+      C.slot_base = (int)sb;
+      sb += nt;
+      const int ca = (int)ceil(k.a0);
+      C.ghost_ext = 2 * ca + 3;
+      C.ghost_base = (int)gb;
+      gb += (long long)C.ghost_ext * C.ghost_ext * C.ghost_ext;
+      const bool moving = k.motion != LC_FIXED;
+      C.event_ext = moving ? 2 * ca + 5 : 0;
+      // post-step threads: slot sums (kPostSlots slots each), one per event
+      // candidate, one per ghost candidate, then one more block that only
+      // finishes the previous step (a free colloid's slots are added before
+      // the post-step kernel)
+      const long long nst = k.motion != LC_FREE ? (nt + lc::kPostSlots - 1) / lc::kPostSlots : 0;
+      const long long ne = (long long)C.event_ext * C.event_ext * C.event_ext;
+      const long long ng = (long long)C.ghost_ext * C.ghost_ext * C.ghost_ext;
+      C.post_blk0 = pblk;
+      C.post_nblk = (int)((nst + ne + ng + lc::kPostBlock - 1) / lc::kPostBlock) + 1;
+      if ((long long)pblk + C.post_nblk > (1LL << 30)) return fail(c, LC_EINVAL, "too many post-step blocks");
+      pblk += C.post_nblk;
+      c->any_colloid = true;
+      c->any_moving |= moving;
+      c->any_free |= k.motion == LC_FREE;
+      table.push_back(C);
+      total++;
     }
-    const int ca = k.present ? (int)ceil(k.a0) : 0;
-    B.ghost_ext = k.present ? 2 * ca + 3 : 0;
-    B.ghost_base = (int)gb;
-    gb += (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
-    const bool moving = k.present && k.motion != LC_FIXED;
-    B.event_ext = moving ? 2 * ca + 5 : 0;
-    // post-step threads: slot sums (kPostSlots slots each), one per event
-    // candidate, one per ghost candidate, then one more block that only
-    // finishes the previous step
-    const long long nt = (long long)B.ntx * B.nty * B.ntz;
-    // (a free colloid's slots are added before the post-step kernel)
-    const long long nst = k.present && k.motion != LC_FREE ? (nt + lc::kPostSlots - 1) / lc::kPostSlots : 0;
-    const long long ne = (long long)B.event_ext * B.event_ext * B.event_ext;
-    const long long ng = (long long)B.ghost_ext * B.ghost_ext * B.ghost_ext;
-    B.post_blk0 = pblk;
-    B.post_nblk = (int)((nst + ne + ng + lc::kPostBlock - 1) / lc::kPostBlock) + 1;
-    if ((long long)pblk + B.post_nblk > (1LL << 30)) return fail(c, LC_EINVAL, "too many post-step blocks");
-    pblk += B.post_nblk;
-    c->any_colloid |= (bool)k.present;
-    c->any_moving |= moving;
-    c->any_free |= k.present && k.motion == LC_FREE;
   }
   if (tb > (1LL << 30)) return fail(c, LC_EINVAL, "too many tiles");
+  if (sb > (1LL << 30)) return fail(c, LC_EINVAL, "too many colloid slots");
+  {
+    int rc = resize_colloid_arrays(c, base, total);
+    if (rc != LC_OK) return rc;
+  }
+  c->colbase = base;
+  c->ncol = total;
+  c->hc = table;
   c->ntile = (int)tb;
+  c->nslot = std::max<long long>(1, sb);
   c->ghost_total = gb;
   c->npost = pblk;
   c->ghost_fresh = false;
@@ -543,13 +635,26 @@ int layout(lc_ctx* c) {
     HIPCHK(c, hipMalloc(&c->doffs, sizeof(int) * offs.size()));
     HIPCHK(c, hipMemcpyAsync(c->doffs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice, c->stream));
   }
-  HIPCHK(c, hipMalloc(&c->dpart, sizeof(double) * 12 * std::max(1, c->ntile)));
-  HIPCHK(c, hipMemsetAsync(c->dpart, 0, sizeof(double) * 12 * std::max(1, c->ntile), c->stream));
+  HIPCHK(c, hipMalloc(&c->dpart, sizeof(double) * 12 * c->nslot));
+  HIPCHK(c, hipMemsetAsync(c->dpart, 0, sizeof(double) * 12 * c->nslot, c->stream));
   if ((size_t)pblk * 24 > c->dbpart_cap) {
     if (c->dbpart) hipFree(c->dbpart);
     c->dbpart = nullptr;
     c->dbpart_cap = std::max<size_t>(24, (size_t)pblk * 24);
     HIPCHK(c, hipMalloc(&c->dbpart, sizeof(double) * c->dbpart_cap));
+  }
+  // the colloid table (a zeroed entry when there is none: the marching
+  // kernel reads entry 0 of a box without colloids but uses nothing of it)
+  if ((size_t)std::max(1, total) > c->dcol_cap) {
+    if (c->dcol) hipFree(c->dcol);
+    c->dcol = nullptr;
+    c->dcol_cap = (size_t)std::max(1, total);
+    HIPCHK(c, hipMalloc(&c->dcol, sizeof(ColDev) * c->dcol_cap));
+  }
+  if (total > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->dcol, c->hc.data(), sizeof(ColDev) * total, hipMemcpyHostToDevice, c->stream));
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->dcol, 0, sizeof(ColDev), c->stream));
   }
   HIPCHK(c, hipMemcpyAsync(c->dtiles, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->dbox, c->hb.data(), sizeof(BoxDev) * c->nbox, hipMemcpyHostToDevice, c->stream));
@@ -569,9 +674,10 @@ lc::StepPtrs<R> ptrs(lc_ctx* c, int from) {
   a.uout = (R*)c->u[1 - from];
   a.nsites = c->nsites;
   a.part = c->dpart;
-  a.nslot = std::max(1, c->ntile);
+  a.nslot = c->nslot;
   a.flag = c->dflag;
   a.par = from;
+  a.cols = c->dcol;
   return a;
 }
 
@@ -583,16 +689,17 @@ hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t
   hipError_t e;
   lc::StepPtrs<R> a = ptrs<R>(c, from);
   e = lc::launch_step<R>(c->tile, c->nblk, c->dbox, c->dtiles, c->doffs, a, c->stream, k0, k1);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || c->ncol == 0) return e;
   c->maybe_pending = true;
   // a free colloid is moved by its own force: the slot sums come first, and
   // the step is finished at once (the next step reads the velocity)
-  if (c->any_free && (e = lc::launch_free(c->nbox, c->dbox, a.part, a.nslot, a.par, c->dfsum, c->stream)) != hipSuccess)
+  if (c->any_free &&
+      (e = lc::launch_free(c->ncol, c->dbox, c->dcol, a.part, a.nslot, a.par, c->dfsum, c->stream)) != hipSuccess)
     return e;
-  e = lc::launch_post<R>(c->npost, c->nbox, c->dbox, a, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
+  e = lc::launch_post<R>(c->npost, c->ncol, c->dbox, a, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
                          kHistCap, c->dcount, c->stream);
   if (e != hipSuccess || !c->any_free) return e;
-  return lc::launch_finish(c->nbox, c->npost, c->dbox, a.par, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
+  return lc::launch_finish(c->ncol, c->npost, c->dcol, a.par, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
                            kHistCap, c->dcount, c->stream);
 }
 
@@ -606,10 +713,10 @@ int ghost_pass(lc_ctx* c) {
   if (c->ghost_fresh) return LC_OK;
   if (c->any_colloid) {
     hipError_t e = c->prec == LC_FP32
-                       ? lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites,
-                                                 c->cur, c->stream)
-                       : lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites,
-                                                  c->cur, c->stream);
+                       ? lc::launch_ghost<float>(c->dbox, c->dcol, c->ncol, c->ghost_total, (float*)c->Q[c->cur],
+                                                 c->nsites, c->cur, c->stream)
+                       : lc::launch_ghost<double>(c->dbox, c->dcol, c->ncol, c->ghost_total, (double*)c->Q[c->cur],
+                                                  c->nsites, c->cur, c->stream);
     HIPCHK(c, e);
   }
   c->ghost_fresh = true;
@@ -723,10 +830,44 @@ int check_colloid(const lc_params& p, const lc_colloid& k, lc_colloid& v, std::s
   return LC_OK;
 }
 
+// n colloids for one box: each valid, present, and every pair at least
+// kColloidGap apart surface to surface (minimum image); v gets them with
+// the centres wrapped into the box.
+int check_colloids(const lc_params& p, int n, const lc_colloid* k, std::vector<lc_colloid>& v, std::string& why) {
+  if (n < 0 || n > lc::kMaxColloids) {
+    why = "a box holds 0 to " + std::to_string(lc::kMaxColloids) + " colloids";
+    return LC_EINVAL;
+  }
+  v.assign(n, lc_colloid());
+  for (int i = 0; i < n; i++) {
+    if (!k[i].present) { why = "colloid " + std::to_string(i) + " is not marked present"; return LC_EINVAL; }
+    if (check_colloid(p, k[i], v[i], why) != LC_OK) return LC_EINVAL;
+  }
+  const int L[3] = {p.nx, p.ny, p.nz};
+  for (int i = 0; i < n; i++)
+    for (int j = i + 1; j < n; j++) {
+      double d2 = 0.0;
+      for (int a = 0; a < 3; a++) {
+        double d = v[j].pos[a] - v[i].pos[a];
+        if (d > 0.5 * L[a]) d -= L[a];
+        else if (d < -0.5 * L[a]) d += L[a];
+        d2 += d * d;
+      }
+      if (sqrt(d2) < v[i].a0 + v[j].a0 + lc::kColloidGap) {
+        why = "colloids " + std::to_string(i) + " and " + std::to_string(j) + " are closer than " +
+              std::to_string(lc::kColloidGap) + " lattice units (surface to surface)";
+        return LC_EINVAL;
+      }
+    }
+  return LC_OK;
+}
+
 int check_flag(lc_ctx* c) {
   int flag = 0;
   HIPCHK(c, hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (flag & 2)
+    return fail(c, LC_ESTATE, "two colloids of a box started a step closer than 3 lattice units (surface to surface)");
   if (flag) return fail(c, LC_ENUMERIC, "a step produced a non-finite value or |u| >= 0.3");
   return LC_OK;
 }
@@ -768,8 +909,7 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
   c->prec = p[0].precision;
   c->esz = c->prec == LC_FP32 ? 4 : 8;
   c->prm.assign(p, p + nbox);
-  c->col.assign(nbox, lc_colloid());
-  for (auto& k : c->col) memset(&k, 0, sizeof(k));
+  c->col.assign(nbox, std::vector<lc_colloid>());
   c->hb.assign(nbox, BoxDev());
   long long off = 0;
   for (int b = 0; b < nbox; b++) {
@@ -815,13 +955,7 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
     if (e != hipSuccess)
       return bail(LC_ENOMEM, std::string("device allocation of the fields failed: ") + hipGetErrorString(e));
   }
-  if (hipMalloc(&c->dbox, sizeof(BoxDev) * nbox) != hipSuccess ||
-      hipMalloc(&c->dforce, sizeof(double) * 12 * nbox) != hipSuccess ||
-      hipMalloc(&c->dhist, sizeof(double) * 12 * (size_t)kHistCap * nbox) != hipSuccess ||
-      hipMalloc(&c->dcount, sizeof(long long) * nbox) != hipSuccess ||
-      hipMalloc(&c->dpending, sizeof(int) * nbox) != hipSuccess ||
-      hipMalloc(&c->dfsum, sizeof(double) * 12 * nbox) != hipSuccess ||
-      hipMalloc(&c->dflag, sizeof(int)) != hipSuccess)
+  if (hipMalloc(&c->dbox, sizeof(BoxDev) * nbox) != hipSuccess || hipMalloc(&c->dflag, sizeof(int)) != hipSuccess)
     return bail(LC_ENOMEM, "device allocation failed");
   {
     // the device the fields were allocated on (current), and its copy of the
@@ -835,11 +969,6 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
       c->scratch_err = std::string("device / static scratch address: ") + hipGetErrorString(e);
     }
   }
-  hipMemsetAsync(c->dforce, 0, sizeof(double) * 12 * nbox, c->stream);
-  hipMemsetAsync(c->dhist, 0, sizeof(double) * 12 * (size_t)kHistCap * nbox, c->stream);
-  hipMemsetAsync(c->dcount, 0, sizeof(long long) * nbox, c->stream);
-  hipMemsetAsync(c->dpending, 0, sizeof(int) * nbox, c->stream);
-  hipMemsetAsync(c->dfsum, 0, sizeof(double) * 12 * nbox, c->stream);
   hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream);
   for (int k = 0; k < 2; k++) {
     hipMemsetAsync(c->Q[k], 0, nq, c->stream);
@@ -852,7 +981,7 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
                                       : lc::launch_fill<double>((double*)c->f[k], c->nsites, p[0].rho0, c->stream);
     if (e != hipSuccess) return bail(LC_EDEVICE, std::string("init: ") + hipGetErrorString(e));
   }
-  if (!march_fits(c) || has_variants(c)) {   // default to the first 3D-tile shape
+  if (!march_fits(c) || needs_3d(c)) {   // default to the first 3D-tile shape
     for (int t = 0; t < num_tiles(c); t++)
       if (tile_shape(c, t).kind == 0) {
         c->tile = t;
@@ -895,7 +1024,7 @@ void lc_destroy(lc_ctx* c) {
       if (c->u[k]) hipFree(c->u[k]);
     }
   void* bufs[] = {c->dbox,  c->dtiles, c->doffs, c->dpart,  c->dbpart, c->dpending, c->dfsum,
-                  c->dforce, c->dhist,  c->dcount, c->dflag,  c->ddiag};
+                  c->dforce, c->dhist,  c->dcount, c->dflag,  c->ddiag,  c->dcol};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -944,25 +1073,60 @@ int lc_bind_buffers(lc_ctx* c, void* f0, void* f1, void* Q0, void* Q1, void* u0,
   return LC_OK;
 }
 
-int lc_set_colloid(lc_ctx* c, int box, const lc_colloid* k) {
+int lc_set_colloids(lc_ctx* c, int box, int n, const lc_colloid* k) {
   int rc = check_box(c, box);
   if (rc) return rc;
-  if (!k) return fail(c, LC_EINVAL, "colloid is NULL");
-  lc_colloid v;
+  if (n > 0 && !k) return fail(c, LC_EINVAL, "colloids are NULL");
+  std::vector<lc_colloid> v;
   std::string why;
-  if (check_colloid(c->prm[box], *k, v, why) != LC_OK) return fail(c, LC_EINVAL, why);
+  if (check_colloids(c->prm[box], n, k, v, why) != LC_OK) return fail(c, LC_EINVAL, why);
   if ((rc = pull_boxes(c)) != LC_OK) return rc;
+  const std::vector<lc_colloid> old = c->col[box];
+  const int old_tile = c->tile;
   c->col[box] = v;
-  return layout(c);
+  // several colloids in a box need the 3D-tile kernel
+  if (needs_3d(c) && tile_shape(c, c->tile).kind == 1) c->tile = first_3d_tile(c);
+  rc = layout(c);
+  if (rc != LC_OK) {   // keep the previous colloids
+    const std::string e = c->err;
+    c->col[box] = old;
+    c->tile = old_tile;
+    layout(c);
+    c->err = e;
+  }
+  return rc;
+}
+
+int lc_set_colloid(lc_ctx* c, int box, const lc_colloid* k) {
+  if (!c) return LC_EINVAL;
+  if (!k) return fail(c, LC_EINVAL, "colloid is NULL");
+  return lc_set_colloids(c, box, k->present ? 1 : 0, k);
+}
+
+int lc_num_colloids(lc_ctx* c, int box) {
+  if (check_box(c, box)) return -1;
+  return (int)c->col[box].size();
+}
+
+int lc_get_colloids(lc_ctx* c, int box, int n, lc_colloid* k) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (n < 0 || n > (int)c->col[box].size() || (n > 0 && !k))
+    return fail(c, LC_EINVAL, "n exceeds the box's colloids, or out is NULL");
+  if ((rc = pull_boxes(c)) != LC_OK) return rc;
+  for (int i = 0; i < n; i++) k[i] = c->col[box][i];
+  return LC_OK;
 }
 
 int lc_get_colloid(lc_ctx* c, int box, lc_colloid* k) {
   int rc = check_box(c, box);
   if (rc) return rc;
   if (!k) return fail(c, LC_EINVAL, "colloid is NULL");
-  if ((rc = pull_boxes(c)) != LC_OK) return rc;
-  *k = c->col[box];
-  return LC_OK;
+  if (c->col[box].empty()) {
+    memset(k, 0, sizeof(*k));
+    return LC_OK;
+  }
+  return lc_get_colloids(c, box, 1, k);
 }
 
 int lc_set_Q(lc_ctx* c, int box, const double* Q5) {
@@ -1012,21 +1176,26 @@ struct StateHeader {
   char magic[8];
   int version, precision, nbox, hist_cap;
   long long nsites, nstep;
+  int ncol, pad_;      // colloids in all boxes
 };
 struct StateBox {
-  int nx, ny, nz, pad_;
-  long long count;     // steps recorded in this box's history ring
+  int nx, ny, nz, ncol;
+};
+struct StateCol {
+  long long count;     // steps recorded in this colloid's history ring
   lc_colloid col;
 };
-const char kStateMagic[8] = {'L', 'C', 'S', 'T', 'A', 'T', 'E', '1'};
-const int kStateVersion = 1;
+const char kStateMagic[8] = {'L', 'C', 'S', 'T', 'A', 'T', 'E', '2'};
+const int kStateVersion = 2;
 
-size_t state_bytes(const lc_ctx* c) {
+size_t state_bytes_for(const lc_ctx* c, int ncol) {
   size_t sz[3];
   lc_buffer_bytes(c, sz);
-  return sizeof(StateHeader) + sizeof(StateBox) * c->nbox + sizeof(double) * 12 * c->nbox +
-         sizeof(double) * 12 * (size_t)kHistCap * c->nbox + 2 * (sz[0] + sz[1] + sz[2]);
+  return sizeof(StateHeader) + sizeof(StateBox) * c->nbox + sizeof(StateCol) * ncol + sizeof(double) * 12 * ncol +
+         sizeof(double) * 12 * (size_t)kHistCap * ncol + 2 * (sz[0] + sz[1] + sz[2]);
 }
+
+size_t state_bytes(const lc_ctx* c) { return state_bytes_for(c, c->ncol); }
 
 int lc_state_bytes(const lc_ctx* c, size_t* out) {
   if (!c || !out) return LC_EINVAL;
@@ -1051,27 +1220,40 @@ int lc_get_state(lc_ctx* c, void* buf, size_t bytes) {
   h.hist_cap = kHistCap;
   h.nsites = c->nsites;
   h.nstep = c->nstep;
+  h.ncol = c->ncol;
   memcpy(p, &h, sizeof(h));
   p += sizeof(h);
-  std::vector<long long> cnt(c->nbox);
-  HIPCHK(c, hipMemcpyAsync(cnt.data(), c->dcount, sizeof(long long) * c->nbox, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<long long> cnt(std::max(1, c->ncol));
+  if (c->ncol > 0) {
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), c->dcount, sizeof(long long) * c->ncol, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   for (int b = 0; b < c->nbox; b++) {
     StateBox r;
     memset(&r, 0, sizeof(r));
     r.nx = c->prm[b].nx; r.ny = c->prm[b].ny; r.nz = c->prm[b].nz;
-    r.count = cnt[b];
-    r.col = c->col[b];
+    r.ncol = (int)c->col[b].size();
     memcpy(p, &r, sizeof(r));
     p += sizeof(r);
   }
+  for (int b = 0; b < c->nbox; b++)
+    for (size_t k = 0; k < c->col[b].size(); k++) {
+      StateCol r;
+      memset(&r, 0, sizeof(r));
+      r.count = cnt[c->colbase[b] + k];
+      r.col = c->col[b][k];
+      memcpy(p, &r, sizeof(r));
+      p += sizeof(r);
+    }
   size_t sz[3];
   lc_buffer_bytes(c, sz);
-  const size_t nforce = sizeof(double) * 12 * c->nbox, nhist = sizeof(double) * 12 * (size_t)kHistCap * c->nbox;
-  HIPCHK(c, hipMemcpyAsync(p, c->dforce, nforce, hipMemcpyDeviceToHost, c->stream));
-  p += nforce;
-  HIPCHK(c, hipMemcpyAsync(p, c->dhist, nhist, hipMemcpyDeviceToHost, c->stream));
-  p += nhist;
+  const size_t nforce = sizeof(double) * 12 * c->ncol, nhist = sizeof(double) * 12 * (size_t)kHistCap * c->ncol;
+  if (c->ncol > 0) {
+    HIPCHK(c, hipMemcpyAsync(p, c->dforce, nforce, hipMemcpyDeviceToHost, c->stream));
+    p += nforce;
+    HIPCHK(c, hipMemcpyAsync(p, c->dhist, nhist, hipMemcpyDeviceToHost, c->stream));
+    p += nhist;
+  }
   void* const* fld[3] = {c->f, c->Q, c->u};
   for (int k = 0; k < 3; k++)
     for (int j = 0; j < 2; j++) {
@@ -1093,35 +1275,66 @@ int lc_set_state(lc_ctx* c, const void* buf, size_t bytes) {
     return fail(c, LC_EINVAL, "not a state written by lc_get_state (magic or version)");
   if (h.precision != c->prec || h.nbox != c->nbox || h.nsites != c->nsites || h.hist_cap != kHistCap)
     return fail(c, LC_EINVAL, "state precision, box count or size does not match the context");
-  if (bytes < state_bytes(c)) return fail(c, LC_EINVAL, "state buffer is smaller than lc_state_bytes");
-  if (h.nstep < 0) return fail(c, LC_EINVAL, "negative step count in the state");
+  if (h.nstep < 0 || h.ncol < 0 || h.ncol > lc::kMaxColloids * c->nbox)
+    return fail(c, LC_EINVAL, "bad step or colloid count in the state");
+  if (bytes < state_bytes_for(c, h.ncol)) return fail(c, LC_EINVAL, "state buffer is smaller than the state it holds");
   // validate everything before changing the context
-  std::vector<long long> cnt(c->nbox);
-  std::vector<lc_colloid> col(c->nbox);
+  std::vector<int> nb(c->nbox);
+  int total = 0;
   for (int b = 0; b < c->nbox; b++) {
     StateBox r;
     memcpy(&r, p, sizeof(r));
     p += sizeof(r);
     if (r.nx != c->prm[b].nx || r.ny != c->prm[b].ny || r.nz != c->prm[b].nz)
       return fail(c, LC_EINVAL, "box " + std::to_string(b) + " of the state has another shape");
-    if (r.count < 0) return fail(c, LC_EINVAL, "negative history count in the state");
+    if (r.ncol < 0 || r.ncol > lc::kMaxColloids) return fail(c, LC_EINVAL, "bad colloid count in the state");
+    nb[b] = r.ncol;
+    total += r.ncol;
+  }
+  if (total != h.ncol) return fail(c, LC_EINVAL, "colloid counts of the state do not add up");
+  std::vector<long long> cnt(std::max(1, total));
+  std::vector<std::vector<lc_colloid>> col(c->nbox);
+  for (int b = 0, g = 0; b < c->nbox; b++) {
+    std::vector<lc_colloid> raw(nb[b]);
+    for (int k = 0; k < nb[b]; k++, g++) {
+      StateCol r;
+      memcpy(&r, p, sizeof(r));
+      p += sizeof(r);
+      if (r.count < 0) return fail(c, LC_EINVAL, "negative history count in the state");
+      cnt[g] = r.count;
+      raw[k] = r.col;
+    }
     std::string why;
-    if (check_colloid(c->prm[b], r.col, col[b], why) != LC_OK)
+    if (check_colloids(c->prm[b], nb[b], raw.data(), col[b], why) != LC_OK)
       return fail(c, LC_EINVAL, "box " + std::to_string(b) + " of the state: " + why);
-    cnt[b] = r.count;
+  }
+  int frc = flush(c);   // a pending step of this context must not land in the restored history
+  if (frc != LC_OK) return frc;
+  if ((frc = pull_boxes(c)) != LC_OK) return frc;
+  const std::vector<std::vector<lc_colloid>> old = c->col;
+  const int old_tile = c->tile;
+  c->col = col;
+  if (needs_3d(c) && tile_shape(c, c->tile).kind == 1) c->tile = first_3d_tile(c);
+  int rc = layout(c);
+  if (rc != LC_OK) {
+    const std::string e = c->err;
+    c->col = old;
+    c->tile = old_tile;
+    layout(c);
+    c->err = e;
+    return rc;
   }
   size_t sz[3];
   lc_buffer_bytes(c, sz);
-  const size_t nforce = sizeof(double) * 12 * c->nbox, nhist = sizeof(double) * 12 * (size_t)kHistCap * c->nbox;
-  int frc = flush(c);   // a pending step of this context must not land in the restored history
-  if (frc != LC_OK) return frc;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, hipMemsetAsync(c->dpending, 0, sizeof(int) * c->nbox, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->dcount, cnt.data(), sizeof(long long) * c->nbox, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->dforce, p, nforce, hipMemcpyHostToDevice, c->stream));
-  p += nforce;
-  HIPCHK(c, hipMemcpyAsync(c->dhist, p, nhist, hipMemcpyHostToDevice, c->stream));
-  p += nhist;
+  const size_t nforce = sizeof(double) * 12 * total, nhist = sizeof(double) * 12 * (size_t)kHistCap * total;
+  if (total > 0) {
+    HIPCHK(c, hipMemsetAsync(c->dpending, 0, sizeof(int) * total, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dcount, cnt.data(), sizeof(long long) * total, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dforce, p, nforce, hipMemcpyHostToDevice, c->stream));
+    p += nforce;
+    HIPCHK(c, hipMemcpyAsync(c->dhist, p, nhist, hipMemcpyHostToDevice, c->stream));
+    p += nhist;
+  }
   void* const* fld[3] = {c->f, c->Q, c->u};
   for (int k = 0; k < 3; k++)
     for (int j = 0; j < 2; j++) {
@@ -1130,9 +1343,8 @@ int lc_set_state(lc_ctx* c, const void* buf, size_t bytes) {
     }
   HIPCHK(c, hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->col = col;
   c->nstep = (long)h.nstep;
-  return layout(c);
+  return LC_OK;
 }
 
 int lc_step(lc_ctx* c, int nsteps) {
@@ -1178,34 +1390,78 @@ int lc_sync(lc_ctx* c) {
 
 long lc_get_nstep(lc_ctx* c) { return c ? c->nstep : -1; }
 
-int lc_get_force(lc_ctx* c, int box, double out[12]) {
+int lc_get_colloid_force(lc_ctx* c, int box, int k, double out[12]) {
   int rc = check_box(c, box);
   if (rc) return rc;
   if (!out) return fail(c, LC_EINVAL, "out is NULL");
+  if (k < 0 || k >= (int)c->col[box].size()) return fail(c, LC_EINVAL, "colloid index out of range");
   if ((rc = flush(c)) != LC_OK) return rc;
-  HIPCHK(c, hipMemcpyAsync(out, c->dforce + 12 * box, sizeof(double) * 12, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, c->dforce + 12 * (c->colbase[box] + k), sizeof(double) * 12, hipMemcpyDeviceToHost,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LC_OK;
 }
 
+int lc_get_force(lc_ctx* c, int box, double out[12]) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!out) return fail(c, LC_EINVAL, "out is NULL");
+  if (c->col[box].empty()) {
+    for (int i = 0; i < 12; i++) out[i] = 0.0;
+    return LC_OK;
+  }
+  return lc_get_colloid_force(c, box, 0, out);
+}
+
 int lc_history_capacity(const lc_ctx* c) { return c ? kHistCap : 0; }
+
+int lc_get_colloid_force_history(lc_ctx* c, int box, int k, int nsteps, double* out) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (k < 0 || k >= (int)c->col[box].size()) return fail(c, LC_EINVAL, "colloid index out of range");
+  if (!out || nsteps < 0 || nsteps > kHistCap)
+    return fail(c, LC_EINVAL, "nsteps exceeds the history capacity, or out is NULL");
+  if ((rc = flush(c)) != LC_OK) return rc;
+  const int g = c->colbase[box] + k;
+  long long cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, c->dcount + g, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (nsteps > cnt) return fail(c, LC_EINVAL, "nsteps exceeds the steps this colloid has taken");
+  std::vector<double> h((size_t)kHistCap * 12);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->dhist + (size_t)g * kHistCap * 12, sizeof(double) * h.size(),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int j = 0; j < nsteps; j++) {
+    const long long n = cnt - nsteps + j;
+    memcpy(out + 12 * j, h.data() + 12 * (n % kHistCap), sizeof(double) * 12);
+  }
+  return LC_OK;
+}
 
 int lc_get_force_history(lc_ctx* c, int box, int nsteps, double* out) {
   int rc = check_box(c, box);
   if (rc) return rc;
   if (!out || nsteps < 0 || nsteps > kHistCap || nsteps > c->nstep)
     return fail(c, LC_EINVAL, "nsteps exceeds the steps taken or the history capacity");
-  if ((rc = flush(c)) != LC_OK) return rc;
-  long long cnt = 0;
-  HIPCHK(c, hipMemcpyAsync(&cnt, c->dcount + box, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
-  std::vector<double> h((size_t)kHistCap * 12);
-  HIPCHK(c, hipMemcpyAsync(h.data(), c->dhist + (size_t)box * kHistCap * 12, sizeof(double) * h.size(),
-                           hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int k = 0; k < nsteps; k++) {
-    const long long n = cnt - nsteps + k;
-    memcpy(out + 12 * k, h.data() + 12 * (n % kHistCap), sizeof(double) * 12);
+  if (c->col[box].empty()) {   // no colloid: no force
+    for (long j = 0; j < 12L * nsteps; j++) out[j] = 0.0;
+    return LC_OK;
   }
+  return lc_get_colloid_force_history(c, box, 0, nsteps, out);
+}
+
+int lc_get_solid(lc_ctx* c, int box, unsigned char* id) {
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!id) return fail(c, LC_EINVAL, "out is NULL");
+  const long long n = box_sites(c->prm[box]);
+  unsigned char* d = nullptr;
+  HIPCHK(c, hipMalloc(&d, n));
+  hipError_t e = lc::launch_solid(c->dbox, c->dcol, box, n, d, c->cur, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(id, d, n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(d);
+  HIPCHK(c, e);
   return LC_OK;
 }
 
@@ -1226,12 +1482,14 @@ int lc_get_diag(lc_ctx* c, int box, lc_diag* out) {
   if (c->prec == LC_FP32) {
     lc::StepPtrs<float> a = ptrs<float>(c, c->cur);
     if (c->any_colloid)
-      lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->cur, c->stream);
+      lc::launch_ghost<float>(c->dbox, c->dcol, c->ncol, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->cur,
+                              c->stream);
     e = lc::launch_diag<float>(c->dbox, box, n, a, c->ddiag, c->stream);
   } else {
     lc::StepPtrs<double> a = ptrs<double>(c, c->cur);
     if (c->any_colloid)
-      lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->cur, c->stream);
+      lc::launch_ghost<double>(c->dbox, c->dcol, c->ncol, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->cur,
+                               c->stream);
     e = lc::launch_diag<double>(c->dbox, box, n, a, c->ddiag, c->stream);
   }
   HIPCHK(c, e);
@@ -1263,14 +1521,14 @@ int lc_get_diag_noalloc(lc_ctx* c, int box, lc_diag* out) {
   if (c->prec == LC_FP32) {
     lc::StepPtrs<float> a = ptrs<float>(c, c->cur);
     if (c->any_colloid &&
-        (e = lc::launch_ghost<float>(c->dbox, c->nbox, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->cur,
+        (e = lc::launch_ghost<float>(c->dbox, c->dcol, c->ncol, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->cur,
                                      c->stream)) != hipSuccess)
       return fail(c, LC_EDEVICE, std::string("ghost launch: ") + hipGetErrorString(e));
     e = lc::launch_diag<float>(c->dbox, box, n, a, c->scratch_dev, c->stream);
   } else {
     lc::StepPtrs<double> a = ptrs<double>(c, c->cur);
     if (c->any_colloid &&
-        (e = lc::launch_ghost<double>(c->dbox, c->nbox, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->cur,
+        (e = lc::launch_ghost<double>(c->dbox, c->dcol, c->ncol, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->cur,
                                       c->stream)) != hipSuccess)
       return fail(c, LC_EDEVICE, std::string("ghost launch: ") + hipGetErrorString(e));
     e = lc::launch_diag<double>(c->dbox, box, n, a, c->scratch_dev, c->stream);
@@ -1301,9 +1559,9 @@ int lc_defects(lc_ctx* c, int box, double threshold, unsigned char* mask, long* 
   }
   hipMemsetAsync(dc, 0, sizeof(unsigned long long), c->stream);
   hipError_t e = c->prec == LC_FP32
-                     ? lc::launch_defects<float>(c->dbox, box, n, (const float*)c->Q[c->cur] + 0, c->nsites,
-                                                 threshold, dm + 0, dc, c->cur, c->stream)
-                     : lc::launch_defects<double>(c->dbox, box, n, (const double*)c->Q[c->cur], c->nsites,
+                     ? lc::launch_defects<float>(c->dbox, c->dcol, box, n, (const float*)c->Q[c->cur], c->nsites,
+                                                 threshold, dm, dc, c->cur, c->stream)
+                     : lc::launch_defects<double>(c->dbox, c->dcol, box, n, (const double*)c->Q[c->cur], c->nsites,
                                                   threshold, dm, dc, c->cur, c->stream);
   unsigned long long cnt = 0;
   if (e == hipSuccess) {

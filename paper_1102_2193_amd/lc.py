@@ -23,7 +23,8 @@ STATUS = {0: "LC_OK", 1: "LC_EINVAL", 2: "LC_ENOMEM", 3: "LC_EDEVICE", 4: "LC_EN
 
 EXPORTS = [
     "lc_create", "lc_create_batch", "lc_destroy", "lc_last_error", "lc_buffer_bytes", "lc_bind_buffers",
-    "lc_set_colloid", "lc_get_colloid", "lc_set_Q", "lc_set_f", "lc_set_u", "lc_get_Q", "lc_get_f",
+    "lc_set_colloid", "lc_get_colloid", "lc_set_colloids", "lc_get_colloids", "lc_num_colloids",
+    "lc_get_colloid_force", "lc_get_colloid_force_history", "lc_get_solid", "lc_set_Q", "lc_set_f", "lc_set_u", "lc_get_Q", "lc_get_f",
     "lc_get_u", "lc_state_bytes", "lc_get_state", "lc_set_state", "lc_step", "lc_sync", "lc_get_nstep", "lc_prepare",
     "lc_get_force", "lc_get_force_history",
     "lc_history_capacity", "lc_get_diag", "lc_get_diag_noalloc", "lc_defects", "lc_num_tiles", "lc_tile_shape", "lc_set_tile",
@@ -88,6 +89,12 @@ def load():
     L.lc_bind_buffers.argtypes = [vp] + [vp] * 6
     L.lc_set_colloid.argtypes = [vp, ip, ctypes.POINTER(Colloid)]
     L.lc_get_colloid.argtypes = [vp, ip, ctypes.POINTER(Colloid)]
+    L.lc_set_colloids.argtypes = [vp, ip, ip, ctypes.POINTER(Colloid)]
+    L.lc_get_colloids.argtypes = [vp, ip, ip, ctypes.POINTER(Colloid)]
+    L.lc_num_colloids.argtypes = [vp, ip]
+    L.lc_get_colloid_force.argtypes = [vp, ip, ip, dp]
+    L.lc_get_colloid_force_history.argtypes = [vp, ip, ip, ip, dp]
+    L.lc_get_solid.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_ubyte)]
     for n in ("lc_set_Q", "lc_set_f", "lc_set_u", "lc_get_Q", "lc_get_f", "lc_get_u", "lc_get_force"):
         getattr(L, n).argtypes = [vp, ip, dp]
     L.lc_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -207,6 +214,39 @@ class Context:
         c = Colloid()
         self._chk(self._L.lc_get_colloid(self._h, box, ctypes.byref(c)))
         return c
+
+    def set_colloids(self, box, specs):
+        """specs: list of dicts with pos, a0 and make_colloid's keywords."""
+        arr = (Colloid * max(1, len(specs)))()
+        for k, sp in enumerate(specs):
+            sp = dict(sp)
+            arr[k] = make_colloid(sp.pop("pos"), sp.pop("a0"), **sp)
+        self._chk(self._L.lc_set_colloids(self._h, box, len(specs), arr))
+
+    def num_colloids(self, box=0):
+        return int(self._L.lc_num_colloids(self._h, box))
+
+    def get_colloids(self, box=0):
+        n = self.num_colloids(box)
+        arr = (Colloid * max(1, n))()
+        self._chk(self._L.lc_get_colloids(self._h, box, n, arr))
+        return [arr[k] for k in range(n)]
+
+    def colloid_force(self, box, k):
+        out = np.zeros(12)
+        self._chk(self._L.lc_get_colloid_force(self._h, box, k, _dp(out)))
+        return out
+
+    def colloid_force_history(self, box, k, n):
+        out = np.zeros((n, 12))
+        self._chk(self._L.lc_get_colloid_force_history(self._h, box, k, int(n), _dp(out)))
+        return out
+
+    def solid_id(self, box=0):
+        """The library's solid map: 1 + colloid index, 0 at fluid sites."""
+        out = np.zeros(self.shapes[box], dtype=np.uint8)
+        self._chk(self._L.lc_get_solid(self._h, box, out.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))))
+        return out
 
     def _put(self, fn, box, arr, ncomp):
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape((ncomp,) + self.shapes[box])

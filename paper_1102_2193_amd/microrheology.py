@@ -36,13 +36,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def fluid_nodes(L, a):
-    """Nodes outside the sphere |x - c|^2 < a^2 centred at (L/2)^3."""
-    x = np.arange(L) - 0.5 * L
-    d2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
-    return int(np.sum(d2 >= a * a))
-
-
 def pull(L=128, a=16.0, f=0.09, settle=2000, steps=16000, every=500, tile=None):
     """Speed of the pulled colloid along and perpendicular to the director:
     {"along": [(step, v)], "perp": [...]}, with the settled state shared."""
@@ -57,8 +50,8 @@ def pull(L=128, a=16.0, f=0.09, settle=2000, steps=16000, every=500, tile=None):
     log("settling %d steps (fixed colloid)" % settle)
     ctx.step(settle)
     state = ctx.get_state()
+    nf = int((ctx.solid_id(0) == 0).sum())   # fluid nodes, from the library's solid map
     ctx.close()
-    nf = fluid_nodes(L, a)
     out = {}
     for name, axis in (("along", 2), ("perp", 0)):
         fext = [0.0, 0.0, 0.0]

@@ -72,11 +72,22 @@ def helix(c, L):
     return inputs.helix_q(L, L, L, 2 * math.pi / c["pitch"], inputs.Q_INIT)
 
 
+def fluid_masks(cases, L, chunk=32):
+    """Fluid sites (1) of each case's colloid (radius c["a"], centred at
+    (L/2)^3), from the library's own solid map (lc_get_solid)."""
+    out = []
+    for i in range(0, len(cases), chunk):
+        part = cases[i:i + chunk]
+        ctx = lc.Context([dict(nx=L, precision="fp32", hydro=0, **PARAMS) for _ in part])
+        for b, c in enumerate(part):
+            ctx.set_colloid(b, (0.5 * L,) * 3, c["a"], anchoring="normal", W=math.inf, S0=Q_EQ)
+        out.extend((ctx.solid_id(b) == 0).astype(np.uint8) for b in range(len(part)))
+        ctx.close()
+    return out
+
+
 def fluid_mask(c, L):
-    """Fluid sites of a centred colloid: |x - R|^2 >= a^2 (R = L/2)."""
-    x = np.arange(L, dtype=np.float64) - 0.5 * L
-    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
-    return (r2 >= c["a"] ** 2).astype(np.uint8)
+    return fluid_masks([c], L)[0]
 
 
 def make_context(cases, L=64, hydro=0, tile=None):
@@ -203,7 +214,7 @@ def prediction_error(net, d, L):
 
 def train(net, data, L, epochs, lr0, lr1, seed, held=()):
     """Adam on one case per step, cosine learning-rate decay lr0 -> lr1."""
-    fluid = [fluid_mask(d, L) for d in data]
+    fluid = fluid_masks(data, L)
     total = epochs * len(data)
     hist = []
     it = 0

@@ -32,3 +32,16 @@ def test_warm_start_reaches_the_relaxed_free_energy_sooner():
         assert r["n_warm"] < r["n_plain"]
         assert r["q_err_warm"] < 0.5 * r["q_err_helix"]
     assert ws.summary(rows)["ratio_of_means"] < 0.25
+
+
+def test_fluid_masks_count_lattice_points_outside_the_sphere():
+    """The warm start's loss mask comes from the library's solid map; it
+    counts the lattice points with |x - R|^2 >= a^2 (brute force)."""
+    import numpy as np
+    from paper_1102_2193_amd import warmstart as ws
+    print("case: fluid masks of three radii on 32^3", flush=True)
+    masks = ws.fluid_masks([{"a": a} for a in (3.0, 4.5, 7.3)], 32)
+    r = np.arange(-16, 16)
+    for a, m in zip((3.0, 4.5, 7.3), masks):
+        inside = sum(1 for x in r for y in r for z in r if x * x + y * y + z * z < a * a)
+        assert m.size - int(m.sum()) == inside

@@ -72,14 +72,6 @@ def test_q_error_is_the_full_tensor_frobenius_norm():
     assert ws.q_error(d, 0 * d, fluid) == pytest.approx(ref, rel=1e-14)
 
 
-def test_fluid_mask_counts_lattice_points_outside_the_sphere():
-    for a in (3.0, 4.5, 7.3):
-        m = ws.fluid_mask({"a": a}, 32)
-        r = np.arange(-16, 16)
-        inside = sum(1 for x in r for y in r for z in r if x * x + y * y + z * z < a * a)
-        assert m.size - int(m.sum()) == inside
-
-
 def test_summary_charges_fallbacks():
     rows = [{"n_plain": 1000, "n_warm_charged": 100, "fallback": False, "q_err_helix": 1e-2, "q_err_warm": 1e-3},
             {"n_plain": 500, "n_warm_charged": 9500, "fallback": True, "q_err_helix": 1e-2, "q_err_warm": 1e-3},
