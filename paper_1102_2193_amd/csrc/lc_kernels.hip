@@ -1497,14 +1497,12 @@ __global__ void __launch_bounds__(kFinishBlock)
 // next step (or k_finish, from the host) finishes it.
 template <typename R>
 __global__ void __launch_bounds__(kPostBlock)
-    k_post(const BoxDev* __restrict__ boxes, int ncol, StepPtrs<R> a, double* __restrict__ bpart,
+    k_post(const BoxDev* __restrict__ boxes, const int* __restrict__ owner, StepPtrs<R> a, double* __restrict__ bpart,
            int* __restrict__ pending, const double* __restrict__ fsum, double* __restrict__ force,
            double* __restrict__ hist, int cap, long long* __restrict__ count, int nblk_all) {
   __shared__ double sred[(kPostBlock / 64) * 12];
   __shared__ double sres[12];
-  int g = 0;
-  for (int k = 1; k < ncol; k++)
-    if ((int)blockIdx.x >= a.cols[k].post_blk0) g = k;
+  const int g = owner[blockIdx.x];   // the colloid this block serves
   ColDev& C = a.cols[g];
   const BoxDev& B = boxes[C.box];
   const int par = a.par;
@@ -1862,10 +1860,11 @@ hipError_t launch_ghost(const BoxDev* boxes, const ColDev* cols, int ncol, long 
 }
 
 template <typename R>
-hipError_t launch_post(int nblk, int ncol, const BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
-                       const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s) {
-  if (ncol <= 0 || nblk <= 0) return hipSuccess;
-  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, ncol, a, bpart, pending, fsum, force, hist, cap, count,
+hipError_t launch_post(int nblk, const int* owner, const BoxDev* boxes, const StepPtrs<R>& a, double* bpart,
+                       int* pending, const double* fsum, double* force, double* hist, int cap, long long* count,
+                       hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  k_post<R><<<(unsigned)nblk, kPostBlock, 0, s>>>(boxes, owner, a, bpart, pending, fsum, force, hist, cap, count,
                                                   nblk);
   return hipGetLastError();
 }
@@ -1921,7 +1920,8 @@ hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
                                      hipStream_t, hipEvent_t, hipEvent_t);                                  \
   template hipError_t launch_ghost<R>(const BoxDev*, const ColDev*, int, long long, R*, long long, int,     \
                                       hipStream_t);                                                         \
-  template hipError_t launch_post<R>(int, int, const BoxDev*, const StepPtrs<R>&, double*, int*, const double*, \
+  template hipError_t launch_post<R>(int, const int*, const BoxDev*, const StepPtrs<R>&, double*, int*,           \
+                                     const double*,                                                         \
                                      double*, double*, int, long long*, hipStream_t);                        \
   template hipError_t launch_diag<R>(const BoxDev*, int, long long, const StepPtrs<R>&, double*, hipStream_t); \
   template hipError_t launch_defects<R>(const BoxDev*, const ColDev*, int, long long, const R*, long long, double, \

@@ -93,9 +93,11 @@ hipError_t launch_ghost(const BoxDev* boxes, const ColDev* cols, int ncol, long 
 // history, count; then marks this step pending.  A free colloid's slots were
 // added by launch_free (fsum), which also moved it; its block sums then hold
 // only the event momenta.
+// owner[blk] = the colloid (table index) post-step block blk serves.
 template <typename R>
-hipError_t launch_post(int nblk, int ncol, const BoxDev* boxes, const StepPtrs<R>& a, double* bpart, int* pending,
-                       const double* fsum, double* force, double* hist, int cap, long long* count, hipStream_t s);
+hipError_t launch_post(int nblk, const int* owner, const BoxDev* boxes, const StepPtrs<R>& a, double* bpart,
+                       int* pending, const double* fsum, double* force, double* hist, int cap, long long* count,
+                       hipStream_t s);
 // Free colloids (one block per colloid of the table, others untouched): the
 // step's slot sums into fsum [12 per colloid], the velocity update and the
 // next position.

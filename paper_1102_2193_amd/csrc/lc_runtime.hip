@@ -110,6 +110,7 @@ struct lc_ctx {
   long long ghost_total = 0;
   int npost = 0;                // blocks of the post-step kernel
   double* dbpart = nullptr;     // 12 per post-step block, one half per buffer parity
+  int* dpostmap = nullptr;      // per post-step block, the colloid it serves
   size_t dbpart_cap = 0;
   int* dpending = nullptr;      // per colloid: a step whose force sums are not yet added
   double* dfsum = nullptr;      // 12 per colloid: link and stress sums of a free colloid's step
@@ -639,9 +640,19 @@ int layout(lc_ctx* c) {
   HIPCHK(c, hipMemsetAsync(c->dpart, 0, sizeof(double) * 12 * c->nslot, c->stream));
   if ((size_t)pblk * 24 > c->dbpart_cap) {
     if (c->dbpart) hipFree(c->dbpart);
+    if (c->dpostmap) hipFree(c->dpostmap);
     c->dbpart = nullptr;
+    c->dpostmap = nullptr;
     c->dbpart_cap = std::max<size_t>(24, (size_t)pblk * 24);
     HIPCHK(c, hipMalloc(&c->dbpart, sizeof(double) * c->dbpart_cap));
+    HIPCHK(c, hipMalloc(&c->dpostmap, sizeof(int) * (c->dbpart_cap / 24)));
+  }
+  if (pblk > 0) {
+    std::vector<int> owner((size_t)pblk);
+    for (int g = 0; g < total; g++)
+      for (int k = 0; k < table[g].post_nblk; k++) owner[(size_t)table[g].post_blk0 + k] = g;
+    HIPCHK(c, hipMemcpyAsync(c->dpostmap, owner.data(), sizeof(int) * pblk, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   // the colloid table (a zeroed entry when there is none: the marching
   // kernel reads entry 0 of a box without colloids but uses nothing of it)
@@ -696,7 +707,7 @@ hipError_t enqueue_step(lc_ctx* c, int from, hipEvent_t k0 = nullptr, hipEvent_t
   if (c->any_free &&
       (e = lc::launch_free(c->ncol, c->dbox, c->dcol, a.part, a.nslot, a.par, c->dfsum, c->stream)) != hipSuccess)
     return e;
-  e = lc::launch_post<R>(c->npost, c->ncol, c->dbox, a, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
+  e = lc::launch_post<R>(c->npost, c->dpostmap, c->dbox, a, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
                          kHistCap, c->dcount, c->stream);
   if (e != hipSuccess || !c->any_free) return e;
   return lc::launch_finish(c->ncol, c->npost, c->dcol, a.par, c->dbpart, c->dpending, c->dfsum, c->dforce, c->dhist,
@@ -1024,7 +1035,7 @@ void lc_destroy(lc_ctx* c) {
       if (c->u[k]) hipFree(c->u[k]);
     }
   void* bufs[] = {c->dbox,  c->dtiles, c->doffs, c->dpart,  c->dbpart, c->dpending, c->dfsum,
-                  c->dforce, c->dhist,  c->dcount, c->dflag,  c->ddiag,  c->dcol};
+                  c->dforce, c->dhist,  c->dcount, c->dflag,  c->ddiag,  c->dcol, c->dpostmap};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
