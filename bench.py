@@ -78,7 +78,7 @@ def workload(name):
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("lc_kernels.hip", "lc_dev.hpp", "lc_kernels.hpp"):
+    for f in ("lc_kernels.hip", "lc_dev.hpp", "lc_kernels.hpp", "lc_march.hpp", "lc_arch.hpp", "lc_reduce.hpp"):
         with open(os.path.join(ROOT, "paper_1102_2193_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

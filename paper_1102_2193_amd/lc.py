@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblc.so")
+# LC_LIBRARY: another build of the same library (e.g. the host-sanitizer
+# build made by build.py --host-sanitize)
+LIB_PATH = os.environ.get("LC_LIBRARY") or os.path.join(HERE, "liblc.so")
 
 FP32, FP64 = 0, 1
 ANCHOR_NONE, ANCHOR_NORMAL, ANCHOR_PLANAR = 0, 1, 2

@@ -14,7 +14,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
-SOURCES = ("lc_kernels.hip", "lc_kernels.hpp", "lc_dev.hpp", "lc_runtime.hip")
+SOURCES = ("lc_kernels.hip", "lc_kernels.hpp", "lc_dev.hpp", "lc_march.hpp", "lc_arch.hpp", "lc_reduce.hpp",
+           "lc_runtime.hip")
 
 
 def sources_hash():

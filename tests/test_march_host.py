@@ -1,0 +1,259 @@
+"""The marching kernel's own source, run on the CPU, against the oracle.
+
+The fused z-marching kernel (``paper_1102_2193_amd/csrc/lc_march.hpp``) is
+plain C++ over a small architecture layer (LDS barrier, buffer-resource
+field access, LDS component pointer, keep-alive).  ``tests/hostsim`` gives a
+host version of that layer and runs each GPU thread of a block as a host
+thread, with real barriers and wave shuffles.  One step of one box is then
+compared with one oracle step (Sec. 2.1-2.2: Q update, LB collision and
+streaming, bounce-back, colloid force and torque) and checked for:
+
+* every global load and store inside its array, with the 32-bit byte offset
+  formed as on the device and inside the buffer resource's range;
+* every LDS read through a component pointer inside that component, every
+  direct LDS subscript inside its array (bounds sanitizer), no heap access
+  outside an allocation (address sanitizer);
+* LDS filled with 0xff bytes before each block, so that a read of LDS the
+  block has not written turns the result into NaN (or a node into a solid
+  one);
+* every population, Q and velocity of a fluid node stored exactly once and
+  nothing stored at solid nodes; every colloid slot written;
+* in the thread-sanitizer build no data race between the threads of a
+  block (a missing barrier), in the memory-sanitizer build no read of an
+  uninitialised value.
+
+Every marching shape of the FP32 shape table and the 16 x 8 shape the FP64
+marching kernel once had, FP32 and FP64, work items of 1, 2 and 8 planes,
+one item per block (LDS poisoned for each) and several (LDS reused as on the
+GPU).
+"""
+import concurrent.futures as cf
+import math
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_1102_2193_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HOSTSIM = os.path.join(ROOT, "tests", "hostsim")
+CSRC = os.path.join(ROOT, "paper_1102_2193_amd", "csrc")
+# clang places the kernel's __shared__ objects in a named section (the
+# driver poisons it); GCC ignores section attributes on template statics
+CLANG = "/opt/rocm/llvm/bin/clang++"
+LDS_BYTES = 160 * 1024
+
+SAN = {
+    "asan": ["-fsanitize=address,undefined", "-fsanitize=array-bounds", "-fno-sanitize-recover=all"],
+    "tsan": ["-fsanitize=thread"],
+    "msan": ["-fsanitize=memory", "-fsanitize-memory-track-origins=2", "-fno-omit-frame-pointer"],
+}
+
+
+def marching_shapes():
+    """(TX, TY) of every marching entry of the FP32 shape table, and 16 x 8."""
+    text = open(os.path.join(CSRC, "lc_kernels.hpp")).read()
+    table = text[text.index("#define LC_TILES_F32"):text.index("#define LC_TILES_F64")]
+    shapes = []
+    for tx, ty, kind in re.findall(r"X\(\d+,\s*(\d+),\s*(\d+),\s*\d+,\s*(\d)\)", table):
+        if kind == "1" and (int(tx), int(ty)) not in shapes:
+            shapes.append((int(tx), int(ty)))
+    assert len(shapes) >= 5
+    return shapes + [(16, 8)]
+
+
+SHAPES = marching_shapes()
+
+
+@pytest.fixture(scope="module")
+def builds(tmp_path_factory):
+    """Address/UB-sanitizer builds of every shape, thread- and
+    memory-sanitizer builds of two, compiled in parallel."""
+    if not os.path.exists(CLANG):
+        pytest.fail("clang++ not found at %s" % CLANG)
+    out = str(tmp_path_factory.mktemp("hostsim"))
+    jobs = [(s, "asan") for s in SHAPES] + [(s, san) for s in ((16, 8), (32, 16)) for san in ("tsan", "msan")]
+    procs = {}
+    for (tx, ty), san in jobs:
+        exe = os.path.join(out, "march_%dx%d_%s" % (tx, ty, san))
+        cmd = [CLANG, "-std=c++17", "-O1", "-g", "-pthread", "-ffp-contract=off", "-Wno-unknown-pragmas",
+               "-Wno-pass-failed", "-DHOSTSIM_TX=%d" % tx, "-DHOSTSIM_TY=%d" % ty] + SAN[san] + \
+              ["-I", HOSTSIM, "-I", CSRC, os.path.join(HOSTSIM, "march_host.cpp"), "-o", exe]
+        procs[((tx, ty), san)] = (subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True), exe)
+    exes = {}
+    for key, (p, exe) in procs.items():
+        _, err = p.communicate()
+        assert p.returncode == 0, "host build %s failed:\n%s" % (key, err[-4000:])
+        exes[key] = exe
+    yield exes
+    shutil.rmtree(out, ignore_errors=True)
+
+
+def oracle_case(L, prm, col, warm=3, seed=5):
+    """Oracle box after `warm` steps (flow and Q both away from rest)."""
+    from oracle import lco
+    s = lco.Sim(*L, **prm)
+    if col is not None:
+        c = dict(col)
+        c["anchoring"] = {"none": lco.ANCHOR_NONE, "normal": lco.ANCHOR_NORMAL,
+                          "planar": lco.ANCHOR_PLANAR}[c.get("anchoring", "normal")]
+        s.set_colloid(c.pop("pos"), c.pop("a0"), **c)
+    s.set_Q(inputs.noisy_nematic_q(L[0], L[1], L[2], inputs.Q_INIT, seed=seed, noise=0.02, director=(1, 0.3, 0.5)))
+    s.step(warm)
+    return s
+
+
+def write_case(d, s, prm, col):
+    from oracle import lco
+    _, w = lco.lattice()
+    (s.get_f() - w.reshape(19, 1, 1, 1)).tofile(os.path.join(d, "f.bin"))
+    s.ghost().tofile(os.path.join(d, "Q.bin"))
+    s.get_u().tofile(os.path.join(d, "u.bin"))
+    nz, ny, nx = s.shape
+    p = dict(nx=nx, ny=ny, nz=nz, hydro=prm.get("hydro", 1), tau=prm.get("tau", 1.0), rho0=prm.get("rho0", 1.0),
+             A0=prm["A0"], gamma=prm["gamma"], K=prm["K"], q0=prm.get("q0", 0.0), xi=prm["xi"], Gamma=prm["Gamma"],
+             body0=0.0, body1=0.0, body2=0.0, ncol=0 if col is None else 1)
+    if col is not None:
+        p.update(motion=col.get("motion", 0), anchoring={"none": 0, "normal": 1, "planar": 2}[col.get("anchoring", "normal")],
+                 a0=col["a0"], S0=col.get("S0", 0.5), W=col.get("W", math.inf))
+        pos = s.get_colloid().pos   # where the warm-up steps left it
+        for k in range(3):
+            p["pos%d" % k] = pos[k]
+            p["vel%d" % k] = col.get("vel", (0, 0, 0))[k]
+            p["omega%d" % k] = col.get("omega", (0, 0, 0))[k]
+    with open(os.path.join(d, "params.txt"), "w") as fh:
+        for k, v in p.items():
+            fh.write("%s %r\n" % (k, float(v)))
+
+
+def run_host(exe, s, prm, col, shape, prec, planes, per_block):
+    from oracle import lco
+    _, w = lco.lattice()
+    with tempfile.TemporaryDirectory() as tmp:
+        case, out = os.path.join(tmp, "case"), os.path.join(tmp, "out")
+        os.makedirs(case)
+        os.makedirs(out)
+        write_case(case, s, prm, col)
+        r = subprocess.run([exe, case, out, str(shape[0]), str(shape[1]), prec, str(planes), str(per_block)],
+                           capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, "host run %s %s %dx%d planes=%d failed (rc %d):\n%s" % (
+            os.path.basename(exe), prec, shape[0], shape[1], planes, r.returncode, r.stderr[-6000:])
+        dims = s.shape
+        rd = lambda n, c, dt=np.float64: np.fromfile(os.path.join(out, n), dtype=dt).reshape((c,) + dims)
+        res = dict(f=rd("f.bin", 19) + w.reshape(19, 1, 1, 1), Q=rd("Q.bin", 5), u=rd("u.bin", 3),
+                   sf=rd("stores_f.bin", 19, np.uint8), sq=rd("stores_Q.bin", 5, np.uint8),
+                   su=rd("stores_u.bin", 3, np.uint8), force=np.fromfile(os.path.join(out, "force.bin")))
+        res["report"] = {k: int(v) for k, v in (l.split() for l in open(os.path.join(out, "report.txt")))}
+    return res
+
+
+TOL = {"f64": dict(Q=1e-13, f=1e-13, u=1e-12, force=1e-11), "f32": dict(Q=1e-6, f=1e-7, u=5e-6, force=5e-6)}
+
+
+def rel_err(a, b, m):
+    d = np.max(np.abs(a[:, m] - b[:, m]))
+    return d / np.max(np.abs(b[:, m])) if np.isfinite(d) else math.inf
+
+
+def check_step(res, ref_state, col, prec, label):
+    """res: host run from the oracle state before the step; ref_state: the
+    oracle after its step (Q, f, u, force, solid before the step)."""
+    Qr, fr, ur, Fr, solid = ref_state
+    fluid = ~solid
+    t = TOL[prec]
+    e = dict(Q=rel_err(res["Q"], Qr, fluid), f=rel_err(res["f"], fr, fluid), u=rel_err(res["u"], ur, fluid))
+    if col is not None:
+        e["force"] = np.max(np.abs(res["force"] - Fr)) / np.max(np.abs(Fr))
+    for k, v in e.items():
+        assert v < t[k], "%s: %s rel err %.3e (bound %.1e)" % (label, k, v, t[k])
+    # stores: exactly once at fluid nodes, never at solid nodes
+    for name in ("sf", "sq", "su"):
+        cnt = res[name]
+        assert np.all(cnt[:, fluid] == 1), "%s: %s stored %s times at some fluid node" % (
+            label, name, sorted(set(np.unique(cnt[:, fluid])) - {1}))
+        assert np.all(cnt[:, solid] == 0), "%s: %s stored at a solid node" % (label, name)
+    rep = res["report"]
+    assert rep["slots_unwritten"] == 0, "%s: %d colloid slots not written" % (label, rep["slots_unwritten"])
+    assert rep["flag"] == 0
+    return e
+
+
+def reference_after_step(s, col):
+    solid = s.solid()
+    s.step(1)
+    F = s.force() if col is not None else None
+    return s.get_Q(), s.get_f(), s.get_u(), F, solid
+
+
+CHIRAL = dict(inputs.NEMATIC, q0=0.2)
+PLANAR = dict(pos=(5.7, 6.2, 5.9), a0=3.1, anchoring="planar", W=0.02, S0=0.5)
+
+
+def _cases_for(shape):
+    # (precision, planes per item, items per block): one item per block
+    # (each with poisoned LDS) and several items per block (LDS reused)
+    return [(prec, planes, per) for prec in ("f64", "f32") for planes, per in ((1, 1), (2, 3), (8, 1))]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d" % s)
+def test_every_shape_and_item_length_12cubed(builds, shape):
+    """Chiral branch next to a planar colloid (weak anchoring) on 12^3: the
+    box is smaller than most tiles (ragged column blocks), the colloid's
+    stencils reach across the periodic boundaries."""
+    L = (12, 12, 12)
+    exe = builds[(shape, "asan")]
+    cases = _cases_for(shape)
+    states = [oracle_case(L, CHIRAL, PLANAR) for _ in cases]
+    with cf.ThreadPoolExecutor(4) as pool:
+        futs = [pool.submit(run_host, exe, st, CHIRAL, PLANAR, shape, prec, planes, per)
+                for st, (prec, planes, per) in zip(states, cases)]
+        results = [f.result() for f in futs]
+    for st, res, (prec, planes, per) in zip(states, results, cases):
+        label = "%dx%d %s planes=%d per_block=%d" % (shape + (prec, planes, per))
+        e = check_step(res, reference_after_step(st, PLANAR), PLANAR, prec, label)
+        print(label, " ".join("%s %.2e" % kv for kv in e.items()))
+        lds = res["report"]["lds_bytes"]
+        if prec == "f32" and shape != (16, 8):
+            assert lds <= LDS_BYTES, "FP32 %dx%d needs %d bytes of LDS" % (shape + (lds,))
+
+
+@pytest.mark.parametrize("shape", [(16, 8), (64, 4), (32, 16)], ids=lambda s: "%dx%d" % s)
+def test_wrapping_box_moving_wall_nematic(builds, shape):
+    """40 x 36 x 12 (several column blocks per axis, ragged in x and y) with a
+    normal-anchoring colloid across the periodic corner, moving slowly
+    (bounce-back with the wall velocity, no node changes side in the step),
+    nematic branch; and a box without colloid."""
+    L = (40, 36, 12)
+    prm = dict(inputs.NEMATIC)
+    col = dict(pos=(38.3, 1.0, 11.1), a0=3.7, anchoring="normal", W=math.inf, S0=0.5, motion=1,
+               vel=(0.004, -0.003, 0.002), omega=(0.0, 0.0015, -0.001))
+    exe = builds[(shape, "asan")]
+    cases = [(prec, c) for prec in ("f64", "f32") for c in (col, None)]
+    states = [oracle_case(L, prm, c, warm=2, seed=7) for _, c in cases]
+    with cf.ThreadPoolExecutor(4) as pool:
+        futs = [pool.submit(run_host, exe, st, prm, c, shape, prec, 2, 2) for st, (prec, c) in zip(states, cases)]
+        results = [f.result() for f in futs]
+    for st, res, (prec, c) in zip(states, results, cases):
+        before = st.solid()
+        ref = reference_after_step(st, c)
+        assert np.array_equal(before, st.solid()), "the colloid crossed a node: events in the oracle step"
+        check_step(res, ref, c, prec, "%dx%d %s colloid=%s" % (shape + (prec, c is not None)))
+
+
+@pytest.mark.parametrize("san", ["tsan", "msan"])
+@pytest.mark.parametrize("shape", [(16, 8), (32, 16)], ids=lambda s: "%dx%d" % s)
+def test_no_race_no_uninitialised_read(builds, san, shape):
+    """Thread sanitizer (a race between the threads of a block: a missing or
+    misplaced barrier) and memory sanitizer (a read of an uninitialised
+    value), FP64 and FP32, two-plane items reusing LDS."""
+    L = (12, 12, 12)
+    exe = builds[(shape, san)]
+    for prec in ("f64", "f32"):
+        st = oracle_case(L, CHIRAL, PLANAR)
+        res = run_host(exe, st, CHIRAL, PLANAR, shape, prec, 2, 3)
+        check_step(res, reference_after_step(st, PLANAR), PLANAR, prec, "%s %dx%d %s" % ((san,) + shape + (prec,)))
