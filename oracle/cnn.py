@@ -42,21 +42,29 @@ def shift(x, d):
 
 
 def conv3d(x, W, b):
-    """x (C, Z, Y, X), W (O, C, 27), b (O,) -> (O, Z, Y, X)."""
-    y = np.zeros((W.shape[0],) + x.shape[1:])
+    """x (C, Z, Y, X), W (O, C, 27), b (O,) -> (O, Z, Y, X).
+
+    Per tap, the channel contraction is a matrix product of W[:, :, t]
+    (O x C) with the shifted input seen as C x sites."""
+    C = x.shape[0]
+    Wt = np.ascontiguousarray(W.transpose(2, 0, 1))   # (27, O, C)
+    y = np.zeros((W.shape[0], x[0].size))
     for t, d in enumerate(TAPS):
-        y += np.einsum("oc,czyx->ozyx", W[:, :, t], shift(x, d))
-    return y + b[:, None, None, None]
+        y += Wt[t] @ shift(x, d).reshape(C, -1)
+    return y.reshape((W.shape[0],) + x.shape[1:]) + b[:, None, None, None]
 
 
 def conv3d_backward(x, W, dy):
     """Gradients of sum(dy * conv3d(x, W, b)) with respect to x, W and b."""
+    C, O = x.shape[0], dy.shape[0]
     dW = np.zeros_like(W)
-    dx = np.zeros_like(x)
+    dx = np.zeros((C, x[0].size))
+    g = dy.reshape(O, -1)
+    WT = np.ascontiguousarray(W.transpose(2, 1, 0))   # (27, C, O)
     for t, d in enumerate(TAPS):
-        dW[:, :, t] = np.einsum("ozyx,czyx->oc", dy, shift(x, d))
-        dx += np.einsum("oc,ozyx->czyx", W[:, :, t], shift(dy, (-d[0], -d[1], -d[2])))
-    return dx, dW, dy.sum(axis=(1, 2, 3))
+        dW[:, :, t] = g @ shift(x, d).reshape(C, -1).T
+        dx += WT[t] @ shift(dy, (-d[0], -d[1], -d[2])).reshape(O, -1)
+    return dx.reshape(x.shape), dW, dy.sum(axis=(1, 2, 3))
 
 
 def sigmoid(z):

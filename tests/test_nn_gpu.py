@@ -3,8 +3,12 @@
 The oracle rounds the operands to bfloat16 exactly as the kernels do and
 accumulates in FP64; the kernels accumulate in FP32 on the matrix cores, so
 layer outputs and gradients agree to FP32 accumulation error (norm-relative
-1e-5).  A chained forward pass can differ by one bfloat16 rounding of an
-intermediate activation, so it is compared at 2e-2.
+1e-5), at 16^3 and at the training size 64^3.  A chained forward pass can
+differ by one bfloat16 rounding of an intermediate activation, so it is
+compared at 2e-2, and so are the losses of chained training steps; the loss
+kernel alone is compared on the GPU's own network output (1e-6), and two
+Adam steps against the oracle's to 2% of the learning rate on the weights
+whose gradients stand far above Adam's epsilon.
 """
 import math
 import sys
@@ -141,3 +145,108 @@ def test_training_step_follows_gradient(net):
         say("   layer %d: sign agreement %.4f, |step| %.3e" % (l, agree, np.abs(step[big]).mean()))
         assert agree > 0.97
         np.testing.assert_allclose(np.abs(step[big]), lr, rtol=1e-2)
+
+
+@pytest.fixture(scope="module")
+def net64():
+    from paper_1102_2193_amd import nn
+    say("case: network on a 64^3 grid (the training size)")
+    return nn.Net(64, seed=4)
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 3])
+def test_layer_forward_backward_64cubed(net64, l):
+    """Layer parity at the training size: 262,144 sites per layer, the
+    weight gradient summed by 256 blocks and then across blocks."""
+    from oracle import cnn
+    from paper_1102_2193_amd import nn
+    say("case: layer %d forward and backward at 64^3" % l)
+    n = 64
+    rng = np.random.default_rng(40 + l)
+    W, b = rand_layer(rng, l)
+    net64.set_layer(l, W, b)
+    x = rng.normal(size=(nn.CIN[l], n, n, n)).astype(np.float32)
+    z = net64.layer_forward(l, x)
+    xr, Wr = cnn.bf16_round(x), cnn.bf16_round(W)
+    ez = nrel(z, cnn.conv3d(xr, Wr, b.astype(np.float64)))
+    dz = rng.normal(size=(nn.COUT[l], n, n, n)).astype(np.float32)
+    dW, db, dx = net64.layer_backward(l, x, dz)
+    rdx, rdW, rdb = cnn.conv3d_backward(xr, Wr, cnn.bf16_round(dz))
+    e = (ez, nrel(dW, rdW), nrel(db, rdb), nrel(dx, rdx))
+    say("   rel err z %.3e dW %.3e db %.3e dx %.3e" % e)
+    assert max(e) < 1e-5
+
+
+def _two_step_case(L, seed):
+    from oracle import cnn
+    from paper_1102_2193_amd import inputs, nn
+    rng = np.random.default_rng(seed)
+    pitch = 16.0
+    pos = (L / 2, L / 2 - 0.3, L / 2 + 0.2)
+    c = nn.make_case(pos, 3.5, pitch, "normal", 0.495, 0.5)
+    qh = inputs.helix_q(L, L, L, 2 * math.pi / pitch, 1.0)
+    target = 0.495 * qh + 0.05 * rng.normal(size=(5, L, L, L))
+    fluid = rng.uniform(size=(L, L, L)) > 0.1
+    x = cnn.features(L, pos, 3.5, pitch, 1.0, qh)
+    return c, qh, target, fluid, x
+
+
+def test_loss_of_the_gpu_output():
+    """k_loss alone: the loss the training step reports equals the FP64 loss
+    of the network output the GPU itself produced (lr = 0: no update)."""
+    from oracle import cnn
+    from paper_1102_2193_amd import nn
+    say("case: loss kernel on the GPU's own output")
+    net = nn.Net(L, seed=5)
+    params = cnn.init_params(13)
+    for l, (W, b) in enumerate(params):
+        net.set_layer(l, W.astype(np.float32), b.astype(np.float32))
+    c, qh, target, fluid, _ = _two_step_case(L, 7)
+    dq = net.predict(c)
+    ref, _ = cnn.loss_and_grad(dq, 0.495 * qh, target, fluid, 0.5)
+    loss = net.train_step(c, target, fluid, 0.0)
+    say("   loss %.9e vs FP64 of the same output %.9e" % (loss, ref))
+    # FP32 residuals, FP64 sums: a few FP32 roundings of each term
+    assert loss == pytest.approx(ref, rel=1e-6)
+    net.close()
+
+
+def test_two_adam_steps_match_oracle():
+    """Two training steps on one case against the oracle's forward, backward
+    and Adam in FP64 (bfloat16 operands as on the GPU).  The second Adam step
+    mixes both gradients through the moments and the bias corrections
+    (t = 2), so the weights after it test k_adam's arithmetic, not only the
+    signs of a first step."""
+    from oracle import cnn
+    from paper_1102_2193_amd import nn
+    say("case: two training steps against the oracle's Adam")
+    net = nn.Net(L, seed=6)   # fresh Adam state (t = 0, zero moments)
+    params = cnn.init_params(14)
+    for l, (W, b) in enumerate(params):
+        net.set_layer(l, W.astype(np.float32), (np.full(b.shape, 0.01)).astype(np.float32))
+    p0 = [(net.get_layer(l)[0].astype(np.float64), net.get_layer(l)[1].astype(np.float64)) for l in range(4)]
+    c, qh, target, fluid, x = _two_step_case(L, 8)
+    lr = 1e-3
+    losses = [net.train_step(c, target, fluid, lr) for _ in range(2)]
+    p, state, ref_losses, grads_all = p0, cnn.adam_init(p0), [], []
+    for _ in range(2):
+        out, cache = cnn.forward(p, x, bf16=True)
+        loss, g = cnn.loss_and_grad(out, 0.495 * qh, target, fluid, 0.5)
+        grads = cnn.backward(p, cache, g, bf16=True)
+        ref_losses.append(loss)
+        grads_all.append(grads)
+        p, state = cnn.adam_step(p, grads, state, lr)
+    say("   losses %s vs oracle %s" % (losses, ref_losses))
+    for a, r in zip(losses, ref_losses):
+        assert a == pytest.approx(r, rel=1e-2)
+    for l in range(4):
+        W2, b2 = (v.astype(np.float64) for v in net.get_layer(l))
+        for name, got, ref, start, k in (("W", W2, p[l][0], p0[l][0], 0), ("b", b2, p[l][1], p0[l][1], 1)):
+            g1, g2 = grads_all[0][l][k], grads_all[1][l][k]
+            # elements whose gradients are far above Adam's epsilon in both steps
+            big = (np.abs(g1) > 1e-3 * np.abs(g1).max()) & (np.abs(g2) > 1e-3 * np.abs(g2).max())
+            d = np.abs((got - start) - (ref - start))[big]
+            say("   layer %d %s: %d elements, max |step - oracle step| / lr %.3e" % (l, name, big.sum(), d.max() / lr))
+            assert big.sum() > 0.5 * big.size
+            assert d.max() < 0.02 * lr
+    net.close()
