@@ -196,17 +196,28 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------
 // weight gradient: dW[t][o][c] = sum_p dz[p][o] x[p + d_t][c]
 // ---------------------------------------------------------------------
+// An implicit GEMM with K = voxels, on v_mfma_f32_16x16x32_bf16: the 32
+// voxels of one instruction are four x-rows of the 8x8x4 tile, lane group
+// kq taking row 4 ks + kq (8 voxels per lane), so both operands of a lane
+// are eight consecutive voxels of one channel.  dz is staged as rows
+// sd[o][p]; the input halo is staged three times, shifted by dx = -1, 0, +1
+// (sxs[dx+1][c][halo row][i] = x at halo x = i + 1 + dx), so that for every
+// tap the eight voxels of a lane are one aligned 16-byte LDS read.  The
+// channel stride 488 puts the 16 lanes of a row group on distinct banks.
+// Staging loads four voxels (eight channels each) per item and writes one
+// 64-bit row segment per channel.
 // Block b accumulates over tiles [b*tpb, (b+1)*tpb) and writes its partial
 // sums part[b][27][COUT][CIN]; wave w of the kWgThreads / 64 owns taps
-// w, w + 8, ... (at most four: the accumulators stay small enough for two
-// waves per SIMD)
+// w, w + 8, ... (at most four).
 constexpr int kWgThreads = 512;
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(kWgThreads)
     k_wgrad(int L, int tpb, const uint16_t* __restrict__ dz, const uint16_t* __restrict__ x, float* __restrict__ part) {
-  constexpr int PS = TV + 8, XS = HV + 8;   // LDS row strides
-  __shared__ uint16_t sd[COUT * PS];        // [o][p]
-  __shared__ uint16_t sx[CIN * XS];         // [c][halo voxel]
+  constexpr int NROW = HY * HZ;           // halo x-rows of a tile
+  constexpr int PS = TV + 8;              // sd row stride (elements)
+  constexpr int CSTR = NROW * 8 + 8;      // sxs channel stride (elements)
+  __shared__ __align__(16) uint16_t sd[COUT * PS];           // [o][p]
+  __shared__ __align__(16) uint16_t sxs[3 * CIN * CSTR];    // [dx+1][c][halo row][i]
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int ri = lane & 15, kq = lane >> 4;
   const int ntx = L / TX, nty = L / TY, ntz = L / TZ, ntile = ntx * nty * ntz;
@@ -218,57 +229,64 @@ __global__ void __launch_bounds__(kWgThreads)
     for (int m = 0; m < COUT / 16; m++)
 #pragma unroll
       for (int n = 0; n < CIN / 16; n++) acc[a][m][n] = f4{0.f, 0.f, 0.f, 0.f};
+  // staging items: (voxel quad, channel octet) of dz; (copy, halo row, quad,
+  // channel octet) of the input
+  constexpr int DO = COUT / 8, XO = CIN / 8;
+  constexpr int NDZ = (TV / 4) * DO, NXS = 3 * NROW * 2 * XO;
+  constexpr int NID = (NDZ + kWgThreads - 1) / kWgThreads, NIX = (NXS + kWgThreads - 1) / kWgThreads;
+  // element k (0..7) of four voxels' octets as one 64-bit row segment
+  auto seg = [](const u4 (&v)[4], int k) {
+    const int d = k >> 1, sh = 16 * (k & 1);
+    const unsigned e0 = (v[0][d] >> sh) & 0xffffu, e1 = (v[1][d] >> sh) & 0xffffu;
+    const unsigned e2 = (v[2][d] >> sh) & 0xffffu, e3 = (v[3][d] >> sh) & 0xffffu;
+    return uint2{e0 | (e1 << 16), e2 | (e3 << 16)};
+  };
   for (int tile = blockIdx.x * tpb; tile < (blockIdx.x + 1) * tpb && tile < ntile; tile++) {
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-    // staged transposed ([channel][voxel]), eight channels per 16-byte
-    // load; every load of the tile is issued before the first LDS store
-    constexpr int DC = COUT / 8, XC = CIN / 8;
-    constexpr int NID = (TV * DC + kWgThreads - 1) / kWgThreads, NIX = (HV * XC + kWgThreads - 1) / kWgThreads;
-    u4 td[NID], tx[NIX];
+    // every global load of the tile is issued before the first LDS store
+    u4 td[NID][4], tx[NIX][4];
 #pragma unroll
     for (int it = 0; it < NID; it++) {
       const int e = tid + it * kWgThreads;
-      if (e < TV * DC) {
-        const int p = e / DC, o = 8 * (e - p * DC);
+      if (e < NDZ) {
+        const int oc = e % DO, p = 4 * (e / DO);   // four voxels along x in one row
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
         const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + lz));
-        td[it] = *(const u4*)(dz + gv * COUT + o);
+#pragma unroll
+        for (int j = 0; j < 4; j++) td[it][j] = *(const u4*)(dz + (gv + j) * COUT + 8 * oc);
       }
     }
 #pragma unroll
     for (int it = 0; it < NIX; it++) {
       const int e = tid + it * kWgThreads;
-      if (e < HV * XC) {
-        const int v = e / XC, c = 8 * (e - v * XC);
-        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
-        const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
-        const long long gv = gx + (long long)L * (gy + (long long)L * gz);
-        tx[it] = *(const u4*)(x + gv * CIN + c);
+      if (e < NXS) {
+        const int oc = e % XO, r = e / XO, quad = r % 2, row = (r / 2) % NROW, cp = r / (2 * NROW);
+        const int hy = row % HY, hz = row / HY;
+        const long long gyz = (long long)L * (wrap1(y0 - 1 + hy, L) + (long long)L * wrap1(z0 - 1 + hz, L));
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int gx = wrap1(x0 - 1 + 4 * quad + cp + j, L);   // halo x = element + cp
+          tx[it][j] = *(const u4*)(x + (gx + gyz) * CIN + 8 * oc);
+        }
       }
     }
     __syncthreads();   // the previous tile's LDS reads are done
 #pragma unroll
     for (int it = 0; it < NID; it++) {
       const int e = tid + it * kWgThreads;
-      if (e < TV * DC) {
-        const int p = e / DC, o = 8 * (e - p * DC);
+      if (e < NDZ) {
+        const int oc = e % DO, p = 4 * (e / DO);
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-          sd[(o + 2 * q) * PS + p] = (uint16_t)(td[it][q] & 0xffffu);
-          sd[(o + 2 * q + 1) * PS + p] = (uint16_t)(td[it][q] >> 16);
-        }
+        for (int k = 0; k < 8; k++) *(uint2*)(sd + (8 * oc + k) * PS + p) = seg(td[it], k);
       }
     }
 #pragma unroll
     for (int it = 0; it < NIX; it++) {
       const int e = tid + it * kWgThreads;
-      if (e < HV * XC) {
-        const int v = e / XC, c = 8 * (e - v * XC);
+      if (e < NXS) {
+        const int oc = e % XO, r = e / XO, quad = r % 2, row = (r / 2) % NROW, cp = r / (2 * NROW);
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-          sx[(c + 2 * q) * XS + v] = (uint16_t)(tx[it][q] & 0xffffu);
-          sx[(c + 2 * q + 1) * XS + v] = (uint16_t)(tx[it][q] >> 16);
-        }
+        for (int k = 0; k < 8; k++) *(uint2*)(sxs + (cp * CIN + 8 * oc + k) * CSTR + row * 8 + 4 * quad) = seg(tx[it], k);
       }
     }
     __syncthreads();
@@ -277,22 +295,21 @@ __global__ void __launch_bounds__(kWgThreads)
       const int t = wv + NW * a;
       if (t >= 27) break;
       const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dzz = t / 9 - 1;
-      for (int ks = 0; ks < TV / 16; ks++) {
-        const int p0 = ks * 16 + 4 * kq;   // four voxels along x in one row
-        const int lx = p0 % TX, ly = (p0 / TX) % TY, lz = p0 / (TX * TY);
-        const int hv = (lx + 1 + dx) + HX * ((ly + 1 + dy) + HY * (lz + 1 + dzz));
-        s4 bfr[CIN / 16];
+#pragma unroll 2
+      for (int ks = 0; ks < TV / 32; ks++) {
+        const int r = 4 * ks + kq;   // x-row of the tile: voxels 8r .. 8r+7
+        const int hrow = (r % TY + 1 + dy) + HY * (r / TY + 1 + dzz);
+        u4 bq[CIN / 16];
 #pragma unroll
-        for (int n = 0; n < CIN / 16; n++) {
-          const uint16_t* q = sx + (n * 16 + ri) * XS + hv;
-          bfr[n] = s4{(short)q[0], (short)q[1], (short)q[2], (short)q[3]};
-        }
+        for (int n = 0; n < CIN / 16; n++)
+          bq[n] = *(const u4*)(sxs + ((dx + 1) * CIN + n * 16 + ri) * CSTR + hrow * 8);
 #pragma unroll
         for (int m = 0; m < COUT / 16; m++) {
-          const s4 af = *(const s4*)(sd + (m * 16 + ri) * PS + ks * 16 + 4 * kq);
+          const u4 af = *(const u4*)(sd + (m * 16 + ri) * PS + 8 * r);
 #pragma unroll
           for (int n = 0; n < CIN / 16; n++)
-            acc[a][m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bfr[n], acc[a][m][n], 0, 0, 0);
+            acc[a][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, af),
+                                                                __builtin_bit_cast(bf8, bq[n]), acc[a][m][n], 0, 0, 0);
         }
       }
     }
