@@ -113,6 +113,28 @@ def pick_tile(n, L=64, hydro=0):
     return min(res, key=res.get), res
 
 
+class Track:
+    """F samples of one run (one every EVERY steps, the first at step 0) and
+    its convergence step (definitions above)."""
+
+    def __init__(self, F0):
+        self.F = [F0]
+        self.held = 0
+        self.conv = None
+        self.n = 0
+
+    def add(self, f):
+        self.n += EVERY
+        self.F.append(f)
+        k, lag = len(self.F) - 1, CONV_WINDOW // EVERY
+        if k >= lag and abs(self.F[k] - self.F[k - lag]) < CONV_TOL * abs(self.F[k]):
+            self.held += 1
+        else:
+            self.held = 0
+        if self.conv is None and (self.held - 1) * EVERY >= CONV_HOLD:
+            self.conv = self.n
+
+
 def relax(cases, L=64, cap=60000, hydro=0, net=None, horizon=None, tile=None, label="relax"):
     """Run the boxes of ``cases`` together from the helix (net None) or
     from the network's prediction.  Stops when every box has converged (or,
@@ -127,10 +149,7 @@ def relax(cases, L=64, cap=60000, hydro=0, net=None, horizon=None, tile=None, la
         else:
             net.warm_start(nn_case(c, L), ctx, b)
     nb = len(cases)
-    F = [[ctx.diag(b)["free_energy"]] for b in range(nb)]
-    conv = [None] * nb
-    held = [0] * nb
-    lag = CONV_WINDOW // EVERY
+    tr = [Track(ctx.diag(b)["free_energy"]) for b in range(nb)]
     n, t0, last = 0, time.time(), time.time()
     ok = True
     end = cap if horizon is None else min(cap, max(horizon))
@@ -143,22 +162,123 @@ def relax(cases, L=64, cap=60000, hydro=0, net=None, horizon=None, tile=None, la
             break
         n += EVERY
         for b in range(nb):
-            F[b].append(ctx.diag(b)["free_energy"])
-            k = len(F[b]) - 1
-            if k >= lag and abs(F[b][k] - F[b][k - lag]) < CONV_TOL * abs(F[b][k]):
-                held[b] += 1
-            else:
-                held[b] = 0
-            if conv[b] is None and (held[b] - 1) * EVERY >= CONV_HOLD:
-                conv[b] = n
-        done = n >= end or (horizon is None and all(s is not None for s in conv))
+            tr[b].add(ctx.diag(b)["free_energy"])
+        done = n >= end or (horizon is None and all(t.conv is not None for t in tr))
         if time.time() - last > 30 or done:
             last = time.time()
-            log("  %s: step %d, %d/%d converged, %.0f s" % (label, n, sum(s is not None for s in conv), nb,
+            log("  %s: step %d, %d/%d converged, %.0f s" % (label, n, sum(t.conv is not None for t in tr), nb,
                                                               time.time() - t0))
         if done:
             break
-    return ctx, [np.array(f) for f in F], conv, ok
+    return ctx, [np.array(t.F) for t in tr], [t.conv for t in tr], ok
+
+
+def box_counts(pitches, nbox):
+    """Boxes per pitch for a pool of nbox boxes: proportional to the number
+    of cases of each pitch (largest remainders), at least one and at most
+    that number.  pitches: the case pitches (one entry per case)."""
+    kinds = sorted(set(pitches))
+    count = {p: pitches.count(p) for p in kinds}
+    nbox = max(len(kinds), min(nbox, len(pitches)))
+    share = {p: nbox * count[p] / len(pitches) for p in kinds}
+    out = {p: max(1, min(count[p], int(share[p]))) for p in kinds}
+    for p in sorted(kinds, key=lambda p: share[p] - int(share[p]), reverse=True):
+        if sum(out.values()) >= nbox:
+            break
+        if out[p] < count[p]:
+            out[p] += 1
+    return out
+
+
+def stream(cases, L, cap, nbox, hydro, tile, label, net=None, horizons=None, keep_Q=True):
+    """Relax every case on a pool of boxes of one context, each box taking
+    the next case of its pitch (the material of a box is fixed) as soon as
+    its run ends: converged, at the case's horizon (if given) or at the cap.
+    A box gives the same bits alone or in a batch and a new case starts from
+    a fresh state (helix or prediction; fluid at rest), so each result is the
+    one a batched run gives.  If a step fails (non-finite values flag the
+    whole context), the running cases are marked failed and the pool goes on
+    in a new context; plain runs (net None) raise instead.  Returns one dict
+    per case, in input order: F samples, convergence step, ok, and the
+    final Q with keep_Q."""
+    pitches = [c["pitch"] for c in cases]
+    counts = box_counts(pitches, nbox)
+    queue = {p: [i for i, c in enumerate(cases) if c["pitch"] == p] for p in counts}
+    box_pitch = [p for p in sorted(counts) for _ in range(counts[p])]
+    nb = len(box_pitch)
+    results = [None] * len(cases)
+    t0, last = time.time(), time.time()
+
+    def new_context():
+        firsts = [cases[queue[p][0]] if queue[p] else {"pitch": p, "a": 4.0, "anchoring": "normal"} for p in box_pitch]
+        return make_context(firsts, L, hydro, tile)
+
+    ctx = new_context()
+    run = [None] * nb      # (case index, Track, end step)
+    rest = None
+
+    def start(b):
+        p = box_pitch[b]
+        if not queue[p]:
+            run[b] = None
+            return
+        i = queue[p].pop(0)
+        c = cases[i]
+        ctx.set_colloid(b, (0.5 * L,) * 3, c["a"], anchoring=c["anchoring"], W=math.inf, S0=Q_EQ)
+        if net is None:
+            ctx.set_Q(b, helix(c, L))
+        else:
+            net.warm_start(nn_case(c, L), ctx, b)
+        if hydro:
+            nonlocal rest
+            if rest is None:
+                # fluid at rest, f = w_i rho0 (D3Q19 weights in the order of lc.h)
+                w = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
+                rest = np.broadcast_to(w.reshape(19, 1, 1, 1) * PARAMS.get("rho0", 1.0), (19, L, L, L)).copy()
+            ctx.set_f(b, rest)
+            ctx.set_u(b, np.zeros((3, L, L, L)))
+        end = cap if horizons is None else min(cap, horizons[i])
+        run[b] = (i, Track(ctx.diag(b)["free_energy"]), end)
+
+    def finish(b, ok):
+        i, tr, _ = run[b]
+        res = {"F": np.array(tr.F), "conv": tr.conv, "ok": ok}
+        if keep_Q and ok:
+            res["Q"] = ctx.get_Q(b)
+        results[i] = res
+
+    for b in range(nb):
+        start(b)
+    while any(r is not None for r in run):
+        try:
+            ctx.step(EVERY)
+        except lc.LCError as e:
+            if net is None:
+                raise RuntimeError("%s: a plain relaxation failed (%s)" % (label, e))
+            log("  %s: step failed (%s); %d running cases marked failed" % (label, e, sum(r is not None for r in run)))
+            for b in range(nb):
+                if run[b] is not None:
+                    finish(b, False)
+            ctx.close()
+            ctx = new_context()
+            for b in range(nb):
+                start(b)
+            continue
+        for b in range(nb):
+            if run[b] is None:
+                continue
+            i, tr, end = run[b]
+            tr.add(ctx.diag(b)["free_energy"])
+            if tr.n >= end or (horizons is None and tr.conv is not None):
+                finish(b, True)
+                start(b)
+        if time.time() - last > 30:
+            last = time.time()
+            log("  %s: %d/%d done, %d running, %.0f s" % (label, sum(r is not None for r in results), len(cases),
+                                                         sum(r is not None for r in run), time.time() - t0))
+    ctx.close()
+    log("  %s: %d cases in %.0f s" % (label, len(cases), time.time() - t0))
+    return results
 
 
 def steps_to_band(F, Fstar, end_step):
@@ -193,18 +313,10 @@ def load_weights(net, path):
 
 
 def relaxed_states(cases, L, cap, batch, hydro, tile, label):
-    """Plain relaxations of the cases, ``batch`` boxes per context: the
+    """Plain relaxations of the cases on a pool of ``batch`` boxes: the
     relaxed Q (FP64 host arrays), F samples and convergence steps."""
-    out = []
-    for i in range(0, len(cases), batch):
-        part = cases[i:i + batch]
-        ctx, F, conv, ok = relax(part, L, cap, hydro, tile=tile, label="%s %d-%d" % (label, i, i + len(part) - 1))
-        if not ok:
-            raise RuntimeError("a plain relaxation failed")
-        for b, c in enumerate(part):
-            out.append(dict(c, Q=ctx.get_Q(b), F=F[b], conv=conv[b]))
-        ctx.close()
-    return out
+    res = stream(cases, L, cap, batch, hydro, tile, label)
+    return [dict(c, Q=r["Q"], F=r["F"], conv=r["conv"]) for c, r in zip(cases, res)]
 
 
 def prediction_error(net, d, L):
@@ -235,32 +347,29 @@ def train(net, data, L, epochs, lr0, lr1, seed, held=()):
 
 
 def compare(net, held, L, cap, hydro, tile, batch):
-    """Warm runs of the held-out cases against their plain relaxations."""
+    """Warm runs of the held-out cases against their plain relaxations, each
+    warm run as long as its plain run took to converge (cap if it did not)."""
+    horizons = [d["conv"] if d["conv"] is not None else cap for d in held]
+    warm = stream(held, L, cap, batch, hydro, tile, "warm", net=net, horizons=horizons, keep_Q=False)
     rows = []
-    for i in range(0, len(held), batch):
-        part = held[i:i + batch]
-        horizon = [d["conv"] if d["conv"] is not None else cap for d in part]
-        ctx, Fw, _, ok = relax(part, L, cap, hydro, net=net, horizon=horizon, tile=tile,
-                               label="warm %d-%d" % (i, i + len(part) - 1))
-        ctx.close()
-        for b, d in enumerate(part):
-            row = {k: d[k] for k in ("seed", "a", "pitch", "anchoring", "conv")}
-            row["q_err_helix"] = q_error(helix(d, L), d["Q"], fluid_mask(d, L))
-            row["q_err_warm"] = prediction_error(net, d, L)
-            row["F_plain"] = d["F"].tolist()
-            row["F_warm"] = Fw[b].tolist()
-            if d["conv"] is not None:
-                Fstar = d["F"][d["conv"] // EVERY]
-                n_plain = steps_to_band(d["F"], Fstar, d["conv"])
-                n_warm = steps_to_band(Fw[b], Fstar, d["conv"]) if ok else None
-                row.update(F_star=float(Fstar), n_plain=n_plain, n_warm=n_warm, fallback=n_warm is None,
-                           n_warm_charged=(n_warm if n_warm is not None else d["conv"] + n_plain),
-                           err0_plain=float(abs(d["F"][0] - Fstar) / abs(Fstar)),
-                           err0_warm=float(abs(Fw[b][0] - Fstar) / abs(Fstar)))
-            rows.append(row)
-            log("  seed %d a %.2f p %.2f %s: plain %s warm %s%s (Q err helix %.3e warm %.3e)" % (
-                d["seed"], d["a"], d["pitch"], d["anchoring"], row.get("n_plain"), row.get("n_warm"),
-                " FALLBACK" if row.get("fallback") else "", row["q_err_helix"], row["q_err_warm"]))
+    for d, w in zip(held, warm):
+        row = {k: d[k] for k in ("seed", "a", "pitch", "anchoring", "conv")}
+        row["q_err_helix"] = q_error(helix(d, L), d["Q"], fluid_mask(d, L))
+        row["q_err_warm"] = prediction_error(net, d, L)
+        row["F_plain"] = d["F"].tolist()
+        row["F_warm"] = w["F"].tolist()
+        if d["conv"] is not None:
+            Fstar = d["F"][d["conv"] // EVERY]
+            n_plain = steps_to_band(d["F"], Fstar, d["conv"])
+            n_warm = steps_to_band(w["F"], Fstar, d["conv"]) if w["ok"] else None
+            row.update(F_star=float(Fstar), n_plain=n_plain, n_warm=n_warm, fallback=n_warm is None,
+                       n_warm_charged=(n_warm if n_warm is not None else d["conv"] + n_plain),
+                       err0_plain=float(abs(d["F"][0] - Fstar) / abs(Fstar)),
+                       err0_warm=float(abs(w["F"][0] - Fstar) / abs(Fstar)))
+        rows.append(row)
+        log("  seed %d a %.2f p %.2f %s: plain %s warm %s%s (Q err helix %.3e warm %.3e)" % (
+            d["seed"], d["a"], d["pitch"], d["anchoring"], row.get("n_plain"), row.get("n_warm"),
+            " FALLBACK" if row.get("fallback") else "", row["q_err_helix"], row["q_err_warm"]))
     return rows
 
 

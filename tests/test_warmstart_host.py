@@ -50,6 +50,64 @@ def test_convergence_must_hold_for_the_whole_window(monkeypatch):
     assert conv[1] is None
 
 
+class _FakePool:
+    """A context whose box b follows F = seq(case)(steps since its case was
+    set); the case is identified by its radius."""
+
+    def __init__(self, seqs):
+        self.seqs, self.case, self.n, self.closed = seqs, {}, {}, False
+
+    def set_colloid(self, b, pos, a, **kw):
+        self.case[b] = a
+
+    def set_Q(self, b, q):
+        self.n[b] = 0
+
+    def step(self, n):
+        for b in self.n:
+            self.n[b] += n
+
+    def diag(self, b):
+        return {"free_energy": self.seqs[self.case[b]](self.n[b])}
+
+    def get_Q(self, b):
+        return np.full(2, self.case[b])
+
+    def close(self):
+        self.closed = True
+
+
+def test_box_counts_follow_the_case_mix():
+    assert ws.box_counts([16.0] * 30 + [32.0] * 10, 8) == {16.0: 6, 32.0: 2}
+    assert ws.box_counts([16.0] * 3 + [32.0] * 1, 32) == {16.0: 3, 32.0: 1}   # never more boxes than cases
+    c = ws.box_counts([16.0] * 50 + [21.0] + [32.0] * 49, 6)
+    assert c[21.0] == 1 and sum(c.values()) == 6
+
+
+def test_streamed_runs_equal_runs_alone(monkeypatch):
+    """Each case's samples and convergence step in a pool of two boxes (boxes
+    taking new cases as runs end) equal those of the case run alone."""
+    seqs = {float(k): (lambda k: lambda n: -1000.0 - math.exp(-n / (800.0 * k)))(k) for k in range(1, 8)}
+    seqs[9.0] = lambda n: -1000.0 - 0.01 * math.sin(n / 3000.0)   # never converges: runs to the cap
+    cases = [{"a": a, "pitch": 16.0 if a % 2 else 32.0, "anchoring": "normal"} for a in sorted(seqs)]
+    monkeypatch.setattr(ws, "make_context", lambda cs, L, hydro, tile: _FakePool(seqs))
+    monkeypatch.setattr(ws, "helix", lambda c, L: None)
+    res = ws.stream(cases, 8, 30000, 2, 0, None, "test")
+    for c, r in zip(cases, res):
+        alone = _FakeContext([seqs[c["a"]]])
+        monkeypatch.setattr(ws, "make_context", lambda cs, L, hydro, tile: alone)
+        _, F, conv, ok = ws.relax([c], cap=30000)
+        assert r["ok"] and r["conv"] == conv[0]
+        np.testing.assert_array_equal(r["F"], F[0])
+        assert r["Q"][0] == c["a"]
+    assert res[-1]["conv"] is None and len(res[-1]["F"]) == 30000 // ws.EVERY + 1
+    # horizons: each run stops at its own horizon
+    monkeypatch.setattr(ws, "make_context", lambda cs, L, hydro, tile: _FakePool(seqs))
+    hz = [1000 * (i + 1) for i in range(len(cases))]
+    res = ws.stream(cases, 8, 30000, 3, 0, None, "test", net=None, horizons=hz, keep_Q=False)
+    assert [len(r["F"]) - 1 for r in res] == [h // ws.EVERY for h in hz]
+
+
 def test_steps_to_band():
     E = ws.EVERY
     F = np.array([10, 5, 2, 1.0002, 1.00005, 0.99999, 1.00001, 1.0])
