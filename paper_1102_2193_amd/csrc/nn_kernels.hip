@@ -207,8 +207,10 @@ __global__ void __launch_bounds__(256)
 // Staging loads four voxels (eight channels each) per item and writes one
 // 64-bit row segment per channel.
 // Block b accumulates over tiles [b*tpb, (b+1)*tpb) and writes its partial
-// sums part[b][27][COUT][CIN]; wave w of the kWgThreads / 64 owns taps
-// w, w + 8, ... (at most four).
+// sums part[b][27][COUT][CIN] followed by the bias-gradient partials
+// part[b][27 COUT CIN + o] = sum of dz[p][o] over its voxels (row sums of
+// the staged dz, 16 threads per channel); wave w of the kWgThreads / 64
+// owns taps w, w + 8, ... (at most four).
 constexpr int kWgThreads = 512;
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(kWgThreads)
@@ -229,6 +231,8 @@ __global__ void __launch_bounds__(kWgThreads)
     for (int m = 0; m < COUT / 16; m++)
 #pragma unroll
       for (int n = 0; n < CIN / 16; n++) acc[a][m][n] = f4{0.f, 0.f, 0.f, 0.f};
+  static_assert(COUT * 16 <= kWgThreads && TV == 16 * 16, "16 threads of 16 voxels per dz row");
+  float bacc = 0.f;   // bias gradient: this thread's 16 voxels of row tid / 16, over the tiles
   // staging items: (voxel quad, channel octet) of dz; (copy, halo row, quad,
   // channel octet) of the input
   constexpr int DO = COUT / 8, XO = CIN / 8;
@@ -290,6 +294,17 @@ __global__ void __launch_bounds__(kWgThreads)
       }
     }
     __syncthreads();
+    if (tid < COUT * 16) {
+      const u4* r = (const u4*)(sd + (tid >> 4) * PS + 16 * (tid & 15));
+      float t = 0.f;
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const u4 v = r[h];
+#pragma unroll
+        for (int d = 0; d < 4; d++) t += bf2f((uint16_t)(v[d] & 0xffffu)) + bf2f((uint16_t)(v[d] >> 16));
+      }
+      bacc += t;
+    }
 #pragma unroll
     for (int a = 0; a < NTAP; a++) {
       const int t = wv + NW * a;
@@ -314,7 +329,11 @@ __global__ void __launch_bounds__(kWgThreads)
       }
     }
   }
-  float* out = part + (long long)blockIdx.x * 27 * COUT * CIN;
+  float* out = part + (long long)blockIdx.x * (27 * COUT * CIN + COUT);
+  // bias: the 16 threads of a row are 16 consecutive lanes of one wave
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) bacc += __shfl_xor(bacc, o, 16);
+  if (tid < COUT * 16 && (tid & 15) == 0) out[27 * COUT * CIN + (tid >> 4)] = bacc;
 #pragma unroll
   for (int a = 0; a < NTAP; a++) {
     const int t = wv + NW * a;
@@ -332,16 +351,17 @@ __global__ void __launch_bounds__(kWgThreads)
 }
 
 // Sum of the weight-gradient block partials part[k][t][o][c] (padded
-// COUTP x CINP) into dW[o][c][t] for the real channel counts.  A workgroup
+// COUTP x CINP) into dW[o][c][t] for the real channel counts, and of the
+// bias partials that follow them into db[o].  A workgroup
 // takes 64 consecutive partial entries (coalesced rows); wave w sums blocks
 // w, w+4, ... and the four wave sums are added in wave order, so the result
 // does not depend on timing.
 __global__ void __launch_bounds__(256)
     k_wgrad_reduce(int nblk, int COUTP, int CINP, int cout, int cin, const float* __restrict__ part,
-                   float* __restrict__ dW) {
+                   float* __restrict__ dW, float* __restrict__ db) {
   __shared__ float s[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int np = 27 * COUTP * CINP;
+  const int nw = 27 * COUTP * CINP, np = nw + COUTP;   // weight entries, then the biases
   const int i = blockIdx.x * 64 + lane;
   float acc = 0.f;
   if (i < np)
@@ -360,59 +380,12 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   if (w == 0 && i < np) {
     const float t4 = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
-    const int c = i % CINP, o = (i / CINP) % COUTP, t = i / (CINP * COUTP);
-    if (o < cout && c < cin) dW[(o * cin + c) * 27 + t] = t4;
-  }
-}
-
-// Bias gradient partials: part[b][o] = sum of dz over voxels [b*chunk, ...).
-// A thread reads eight channels (16 bytes) of one voxel per load, four
-// voxels in flight; the voxel lanes are then added in lane order.
-__global__ void __launch_bounds__(256)
-    k_bgrad(long long V, int chunk, int COUTP, const uint16_t* __restrict__ dz, float* __restrict__ part) {
-  __shared__ float s[256 * 8];
-  const int ng = COUTP / 8, cg = threadIdx.x % ng, lane = threadIdx.x / ng, nl = 256 / ng;
-  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  const long long v0 = (long long)blockIdx.x * chunk, v1 = v0 + chunk < V ? v0 + chunk : V;
-  for (long long v = v0 + lane; v < v1; v += 4LL * nl) {
-    u4 t[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const long long vj = v + (long long)j * nl;
-      t[j] = vj < v1 ? *(const u4*)(dz + vj * COUTP + 8 * cg) : u4{0u, 0u, 0u, 0u};
+    if (i < nw) {
+      const int c = i % CINP, o = (i / CINP) % COUTP, t = i / (CINP * COUTP);
+      if (o < cout && c < cin) dW[(o * cin + c) * 27 + t] = t4;
+    } else if (i - nw < cout) {
+      db[i - nw] = t4;
     }
-#pragma unroll
-    for (int j = 0; j < 4; j++)
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        acc[2 * q] += bf2f((uint16_t)(t[j][q] & 0xffffu));
-        acc[2 * q + 1] += bf2f((uint16_t)(t[j][q] >> 16));
-      }
-  }
-#pragma unroll
-  for (int q = 0; q < 8; q++) s[lane * COUTP + 8 * cg + q] = acc[q];
-  __syncthreads();
-  if (threadIdx.x < COUTP) {
-    float t = 0.f;
-    for (int k = 0; k < nl; k++) t += s[k * COUTP + threadIdx.x];
-    part[(long long)blockIdx.x * COUTP + threadIdx.x] = t;
-  }
-}
-
-// db[o] = sum of the bias partials; thread group g sums blocks g, g+ng, ...
-// and the group sums are added in group order.
-__global__ void __launch_bounds__(1024)
-    k_bgrad_reduce(int nblk, int COUTP, int cout, const float* __restrict__ part, float* __restrict__ db) {
-  __shared__ float s[1024];
-  const int o = threadIdx.x % COUTP, g = threadIdx.x / COUTP, ng = 1024 / COUTP;
-  float acc = 0.f;
-  for (int k = g; k < nblk; k += ng) acc += part[k * COUTP + o];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < cout) {
-    float t = 0.f;
-    for (int k = 0; k < ng; k++) t += s[k * COUTP + threadIdx.x];
-    db[threadIdx.x] = t;
   }
 }
 
@@ -567,17 +540,9 @@ hipError_t launch_wgrad(int cinp, int coutp, int L, int nblk, int tpb, const uin
 }
 
 hipError_t launch_wgrad_reduce(int nblk, int coutp, int cinp, int cout, int cin, const float* part, float* dW,
-                               hipStream_t s) {
-  const int np = 27 * coutp * cinp;
-  k_wgrad_reduce<<<(np + 63) / 64, 256, 0, s>>>(nblk, coutp, cinp, cout, cin, part, dW);
-  return hipGetLastError();
-}
-
-hipError_t launch_bgrad(long long V, int nblk, int coutp, int cout, const uint16_t* dz, float* part, float* db,
-                        hipStream_t s) {
-  const int chunk = (int)((V + nblk - 1) / nblk);
-  k_bgrad<<<nblk, 256, 0, s>>>(V, chunk, coutp, dz, part);
-  k_bgrad_reduce<<<1, 1024, 0, s>>>(nblk, coutp, cout, part, db);
+                               float* db, hipStream_t s) {
+  const int np = 27 * coutp * cinp + coutp;
+  k_wgrad_reduce<<<(np + 63) / 64, 256, 0, s>>>(nblk, coutp, cinp, cout, cin, part, dW, db);
   return hipGetLastError();
 }
 

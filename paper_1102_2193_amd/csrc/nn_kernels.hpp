@@ -21,12 +21,13 @@ hipError_t launch_features(int L, const Case& c, uint16_t* x0, float* f32, hipSt
 // silu'(zprev), bf16 out; 3: FP32 out
 hipError_t launch_conv(int cinp, int coutp, int mode, int L, const uint16_t* x, const uint16_t* w, const float* bias,
                        const float* zprev, float* zout, uint16_t* aout, hipStream_t s);
+// Weight and bias gradients of a layer: per-block partials (nblk blocks of
+// tpb tiles; 27 coutp cinp + coutp floats each), then their fixed-order sum
+// into dW [cout][cin][27] and db [cout].
 hipError_t launch_wgrad(int cinp, int coutp, int L, int nblk, int tpb, const uint16_t* dz, const uint16_t* x,
                         float* part, hipStream_t s);
 hipError_t launch_wgrad_reduce(int nblk, int coutp, int cinp, int cout, int cin, const float* part, float* dW,
-                               hipStream_t s);
-hipError_t launch_bgrad(long long V, int nblk, int coutp, int cout, const uint16_t* dz, float* part, float* db,
-                        hipStream_t s);
+                               float* db, hipStream_t s);
 hipError_t launch_loss(int L, const Case& c, const float* out, const float* Qt, const uint8_t* fluid, double inv_nf,
                        uint16_t* dz, double* part, hipStream_t s);
 template <typename R>

@@ -40,10 +40,8 @@ struct lc_nn {
   float* out = nullptr;                // dQ [V][16]
   uint16_t* g4 = nullptr;              // d loss / d out [V][16]
   uint16_t* g[3] = {};                 // d loss / d z_l [V][32]
-  float* wpart = nullptr;
+  float* wpart = nullptr;               // weight- and bias-gradient block partials
   int wblk = 0, tpb = 0;
-  float* bpart = nullptr;
-  int bblk = 0;
   double* lpart = nullptr;
   int lblk = 0;
   float* Qt = nullptr;
@@ -110,8 +108,8 @@ int forward(lc_nn* n, const lcnn::Case& k, bool keep) {
 // gradients of layer l from dz (bf16 [V][COUTP]) and its input x
 int layer_grads(lc_nn* n, int l, const uint16_t* dz, const uint16_t* x) {
   NNCHK(n, lcnn::launch_wgrad(CINP[l], COUTP[l], n->L, n->wblk, n->tpb, dz, x, n->wpart, n->stream));
-  NNCHK(n, lcnn::launch_wgrad_reduce(n->wblk, COUTP[l], CINP[l], COUT[l], CIN[l], n->wpart, n->dW[l], n->stream));
-  NNCHK(n, lcnn::launch_bgrad(n->V, n->bblk, COUTP[l], COUT[l], dz, n->bpart, n->db[l], n->stream));
+  NNCHK(n, lcnn::launch_wgrad_reduce(n->wblk, COUTP[l], CINP[l], COUT[l], CIN[l], n->wpart, n->dW[l], n->db[l],
+                                     n->stream));
   return LC_OK;
 }
 
@@ -186,7 +184,6 @@ int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out) 
   const int ntile = (L / 8) * (L / 8) * (L / 4);
   n->tpb = (ntile + 255) / 256;
   n->wblk = (ntile + n->tpb - 1) / n->tpb;
-  n->bblk = 512;
   n->lblk = (int)((V + 255) / 256);
   bool ok = true;
   auto dmalloc = [&](void** p, size_t sz) {
@@ -214,8 +211,7 @@ int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out) 
   }
   dmalloc((void**)&n->out, V * 16 * 4);
   dmalloc((void**)&n->g4, V * 16 * 2);
-  dmalloc((void**)&n->wpart, (size_t)n->wblk * 27 * 32 * 32 * 4);
-  dmalloc((void**)&n->bpart, (size_t)n->bblk * 32 * 4);
+  dmalloc((void**)&n->wpart, (size_t)n->wblk * (27 * 32 * 32 + 32) * 4);
   dmalloc((void**)&n->lpart, (size_t)n->lblk * 8);
   dmalloc((void**)&n->Qt, V * 5 * 4);
   dmalloc((void**)&n->fluid, V);
@@ -251,7 +247,7 @@ void lc_nn_destroy(lc_nn* n) {
       if (q) hipFree(q);
   }
   void* q[] = {n->x0, n->z[0], n->z[1], n->z[2], n->a[0], n->a[1], n->a[2], n->g[0], n->g[1], n->g[2], n->out,
-               n->g4, n->wpart, n->bpart, n->lpart, n->Qt, n->fluid, n->tmpf, n->tmph, n->tmph2};
+               n->g4, n->wpart, n->lpart, n->Qt, n->fluid, n->tmpf, n->tmph, n->tmph2};
   for (void* p : q)
     if (p) hipFree(p);
   if (n->own_stream && n->stream) hipStreamDestroy(n->stream);
