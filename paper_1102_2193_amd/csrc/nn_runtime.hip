@@ -196,7 +196,8 @@ int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out) 
     dmalloc((void**)&n->mW[l], nw * 4);
     dmalloc((void**)&n->vW[l], nw * 4);
     dmalloc((void**)&n->dW[l], nw * 4);
-    dmalloc((void**)&n->b[l], COUT[l] * 4);
+    // the convolution epilogues read the bias at every padded channel (zero there)
+    dmalloc((void**)&n->b[l], COUTP[l] * 4);
     dmalloc((void**)&n->mb[l], COUT[l] * 4);
     dmalloc((void**)&n->vb[l], COUT[l] * 4);
     dmalloc((void**)&n->db[l], COUT[l] * 4);
