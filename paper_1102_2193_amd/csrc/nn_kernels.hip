@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_features(int L, Case c, uint16_t* __res
 // MODE 3: acc stored as FP32 (plain data gradient); MODE 4: as MODE 0
 // without keeping z (inference).
 template <int CIN, int COUT, int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(COUT == 32 ? 4 : 1)))
     k_conv(int L, const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias,
            const float* __restrict__ zprev, float* __restrict__ zout, uint16_t* __restrict__ aout) {
   // K of one matrix-core instruction: 32 input channels at once
@@ -87,12 +87,20 @@ __global__ void __launch_bounds__(256)
   // 16.  Each lane's A and B fragments hold the same KI/4 consecutive
   // channels, so the products pair up whatever order the instruction
   // assigns to them within a K block.
-  constexpr int KI = CIN % 32 == 0 ? 32 : 16;
-  // LDS voxel stride (spread over the banks; 16-byte aligned fragments for
-  // K = 32) and staging chunk (elements)
-  constexpr int CS = CIN + (KI == 32 ? 8 : 4), SB = KI == 32 ? 8 : 4;
+  static_assert(CIN == 16 || CIN == 32, "16 or 32 input channels");
+  constexpr int KI = CIN;
+  // LDS layout of the halo: voxel (hx, hy, hz) at hx CIN + hy RS + hz PZ
+  // elements, the voxels of an x-row packed, rows 10.5 voxels apart.  A
+  // 16-byte LDS read serves 16 lanes per cycle, lane groups {0-3, 12-15,
+  // 20-23, 24-27}, {4-7, 8-11, 16-19, 28-31} and the same in 32-63
+  // (measured on gfx950 with the bank-conflict counter); each group reads
+  // all 16 voxels of a fragment, half at channel chunk kq and half at
+  // kq + 1, and with these strides the 16 addresses fall in distinct banks.
+  // For 16 channels (8-byte reads) lanes 0-31 fall in distinct banks.  The
+  // packed rows also keep four blocks' halos within one CU's LDS.
+  constexpr int RS = HX * CIN + CIN / 2, PZ = HY * RS, SB = KI == 32 ? 8 : 4;
   using Chunk = typename std::conditional<SB == 8, u4, uint2>::type;
-  __shared__ __align__(16) uint16_t sx[HV * CS];
+  __shared__ __align__(16) uint16_t sx[HZ * PZ];
   const int tid = threadIdx.x;
   const int ntx = L / TX, nty = L / TY;
   const int b = blockIdx.x;
@@ -102,6 +110,7 @@ __global__ void __launch_bounds__(256)
   constexpr int CH = CIN / SB, NIT = (HV * CH + 255) / 256;
   {
     Chunk tmp[NIT];
+    int soff[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; it++) {
       const int e = tid + it * 256;
@@ -111,15 +120,13 @@ __global__ void __launch_bounds__(256)
         const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
         const long long gv = gx + (long long)L * (gy + (long long)L * gz);
         tmp[it] = *(const Chunk*)(x + gv * CIN + SB * c);
+        soff[it] = hx * CIN + hy * RS + hz * PZ + SB * c;
       }
     }
 #pragma unroll
     for (int it = 0; it < NIT; it++) {
       const int e = tid + it * 256;
-      if (e < HV * CH) {
-        const int v = e / CH, c = e - v * CH;
-        *(Chunk*)(sx + v * CS + SB * c) = tmp[it];
-      }
+      if (e < HV * CH) *(Chunk*)(sx + soff[it]) = tmp[it];
     }
   }
   __syncthreads();
@@ -152,8 +159,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int m = 0; m < 4; m++) {
         const int lx = ri & 7, ly = 2 * m + (ri >> 3);
-        const int hv = (lx + 1 + dx) + HX * ((ly + 1 + dy) + HY * (wv + 1 + dz));
-        const Frag af = *(const Frag*)(sx + hv * CS + kc * KI + (KI / 4) * kq);
+        const Frag af = *(const Frag*)(sx + (lx + 1 + dx) * CIN + (ly + 1 + dy) * RS + (wv + 1 + dz) * PZ + kc * KI +
+                                       (KI / 4) * kq);
 #pragma unroll
         for (int n = 0; n < NN; n++) {
           if constexpr (KI == 32)
@@ -202,10 +209,16 @@ __global__ void __launch_bounds__(256)
 // are eight consecutive voxels of one channel.  dz is staged as rows
 // sd[o][p]; the input halo is staged three times, shifted by dx = -1, 0, +1
 // (sxs[dx+1][c][halo row][i] = x at halo x = i + 1 + dx), so that for every
-// tap the eight voxels of a lane are one aligned 16-byte LDS read.  The
-// channel stride 488 puts the 16 lanes of a row group on distinct banks.
-// Staging loads four voxels (eight channels each) per item and writes one
-// 64-bit row segment per channel.
+// tap the eight voxels of a lane are one aligned 16-byte LDS read.  A
+// 16-byte LDS read serves the lane groups {0-3, 12-15, 20-23, 24-27},
+// {4-7, 8-11, 16-19, 28-31} (and the same in 32-63) one per cycle: with
+// row strides of 34 and 62 16-byte chunks (2 mod 4) the eight lanes of
+// each row half that a group holds fall in distinct banks.  Staging loads
+// four voxels (eight channels each) per item and writes one 64-bit row
+// segment per channel; item oc of an octet writes its channels rotated by
+// 8 oc / octets (the load's dwords rotated in registers), so that the
+// lanes of one 64-bit store, which hold all octets, write banks 64 or 128
+// bytes apart instead of the same ones.
 // Block b accumulates over tiles [b*tpb, (b+1)*tpb) and writes its partial
 // sums part[b][27][COUT][CIN] followed by the bias-gradient partials
 // part[b][27 COUT CIN + o] = sum of dz[p][o] over its voxels (row sums of
@@ -216,8 +229,8 @@ template <int CIN, int COUT>
 __global__ void __launch_bounds__(kWgThreads)
     k_wgrad(int L, int tpb, const uint16_t* __restrict__ dz, const uint16_t* __restrict__ x, float* __restrict__ part) {
   constexpr int NROW = HY * HZ;           // halo x-rows of a tile
-  constexpr int PS = TV + 8;              // sd row stride (elements)
-  constexpr int CSTR = NROW * 8 + 8;      // sxs channel stride (elements)
+  constexpr int PS = TV + 16;             // sd row stride (elements)
+  constexpr int CSTR = NROW * 8 + 16;     // sxs channel stride (elements)
   __shared__ __align__(16) uint16_t sd[COUT * PS];           // [o][p]
   __shared__ __align__(16) uint16_t sxs[3 * CIN * CSTR];    // [dx+1][c][halo row][i]
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -245,6 +258,18 @@ __global__ void __launch_bounds__(kWgThreads)
     const unsigned e2 = (v[2][d] >> sh) & 0xffffu, e3 = (v[3][d] >> sh) & 0xffffu;
     return uint2{e0 | (e1 << 16), e2 | (e3 << 16)};
   };
+  // the four voxels' octets with dword d taken from dword (d + r) & 3:
+  // element k is then channel (k + 2 r) & 7 of the octet
+  auto rot = [](const u4 (&v)[4], int r, u4 (&o)[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+      for (int d = 0; d < 4; d++) {
+        const int q = (d + r) & 3;
+        o[j][d] = q == 0 ? v[j][0] : q == 1 ? v[j][1] : q == 2 ? v[j][2] : v[j][3];
+      }
+  };
+  static_assert((DO == 2 || DO == 4) && (XO == 2 || XO == 4), "16 or 32 channels");
   for (int tile = blockIdx.x * tpb; tile < (blockIdx.x + 1) * tpb && tile < ntile; tile++) {
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
     // every global load of the tile is issued before the first LDS store
@@ -279,9 +304,11 @@ __global__ void __launch_bounds__(kWgThreads)
     for (int it = 0; it < NID; it++) {
       const int e = tid + it * kWgThreads;
       if (e < NDZ) {
-        const int oc = e % DO, p = 4 * (e / DO);
+        const int oc = e % DO, p = 4 * (e / DO), r = (4 / DO) * oc;
+        u4 v[4];
+        rot(td[it], r, v);
 #pragma unroll
-        for (int k = 0; k < 8; k++) *(uint2*)(sd + (8 * oc + k) * PS + p) = seg(td[it], k);
+        for (int k = 0; k < 8; k++) *(uint2*)(sd + (8 * oc + ((k + 2 * r) & 7)) * PS + p) = seg(v, k);
       }
     }
 #pragma unroll
@@ -289,8 +316,12 @@ __global__ void __launch_bounds__(kWgThreads)
       const int e = tid + it * kWgThreads;
       if (e < NXS) {
         const int oc = e % XO, r = e / XO, quad = r % 2, row = (r / 2) % NROW, cp = r / (2 * NROW);
+        const int rr = (4 / XO) * oc;
+        u4 v[4];
+        rot(tx[it], rr, v);
 #pragma unroll
-        for (int k = 0; k < 8; k++) *(uint2*)(sxs + (cp * CIN + 8 * oc + k) * CSTR + row * 8 + 4 * quad) = seg(tx[it], k);
+        for (int k = 0; k < 8; k++)
+          *(uint2*)(sxs + (cp * CIN + 8 * oc + ((k + 2 * rr) & 7)) * CSTR + row * 8 + 4 * quad) = seg(v, k);
       }
     }
     __syncthreads();
