@@ -20,7 +20,7 @@
  * Conventions as in lc.h: int status codes (LC_OK ...), FP64 or FP32 host
  * arrays in [component][z][y][x] order, work on the stream given at
  * creation, getters synchronise.  The grid is one cubic box of edge L, a
- * multiple of 8.
+ * multiple of 8 from 8 to 1024.
  */
 #ifndef LC_NN_H
 #define LC_NN_H
@@ -48,7 +48,7 @@ typedef struct lc_nn_case {
 
 /* Create a network for an L^3 grid with weights from a seeded generator:
  * W ~ U(-s, s), s = sqrt(6 / (27 C_in)), b = 0 (splitmix64 stream of seed).
- * L must be a multiple of 8 and at least 8. */
+ * L must be a multiple of 8 in [8, 1024] (else LC_EINVAL). */
 int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out);
 void lc_nn_destroy(lc_nn* nn);
 const char* lc_nn_last_error(const lc_nn* nn);

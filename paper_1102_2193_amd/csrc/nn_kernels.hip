@@ -4,9 +4,8 @@
 // A 3x3x3 periodic convolution is an implicit GEMM: M = voxels of an
 // 8x8x4 tile, N = output channels, K = 27 taps x input channels.  Each
 // wave owns one z-layer of the tile (64 voxels = four 16-row M tiles) and
-// multiplies BF16 fragments on the matrix cores (v_mfma_f32_16x16x32_bf16
-// for 32-channel inputs, v_mfma_f32_16x16x16_bf16 for 16, FP32
-// accumulation).  Fragment layout for a wave of 64 lanes: A[i][k] -> lane
+// multiplies BF16 fragments on the matrix cores (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation; a 16-channel input takes two taps per instruction).  Fragment layout for a wave of 64 lanes: A[i][k] -> lane
 // i + 16*(k/KB), element k%KB; B[k][j] -> lane j + 16*(k/KB), element
 // k%KB (KB = K/4 consecutive k per lane); D[i][j] -> lane j + 16*(i/4),
 // element i%4.
@@ -19,7 +18,6 @@
 
 namespace lcnn {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -31,7 +29,9 @@ __device__ inline uint16_t f2bf(float x) {
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ inline float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function with the hardware reciprocal (within 1 ulp; the result
+// is rounded to BF16 or enters a derivative factor)
+__device__ inline float sigmoidf_(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 constexpr int TX = 8, TY = 8, TZ = 4, TV = TX * TY * TZ;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HV = HX * HY * HZ;
@@ -41,32 +41,62 @@ __device__ inline int wrap1(int v, int L) { return v < 0 ? v + L : (v >= L ? v -
 // ---------------------------------------------------------------------
 // input features
 // ---------------------------------------------------------------------
+// The 16 input channels of voxel (x, y, z) (Sec. 3 geometry of the case:
+// clipped signed distance to the surface, outward normal, unit helix of
+// the pitch, radius, pitch and anchoring sign, four zeros) in FP64 (the
+// reference values, also written as FP32 when f32 is requested) or FP32,
+// which the BF16 rounding cannot tell apart except at rounding ties.
+template <typename R>
+__device__ inline void features_at(int L, const Case& c, int x, int y, int z, R f[16]) {
+  const R h = (R)0.5 * (R)L;
+  R r[3] = {(R)x - (R)c.pos[0], (R)y - (R)c.pos[1], (R)z - (R)c.pos[2]};
+  for (int k = 0; k < 3; k++) r[k] = r[k] > h ? r[k] - (R)L : (r[k] < -h ? r[k] + (R)L : r[k]);
+  const R rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const R sd = (rn - (R)c.a0) * (R)0.125;
+  f[0] = sd < (R)-1 ? (R)-1 : (sd > (R)2 ? (R)2 : sd);
+  const R irn = rn > (R)0 ? (R)1 / rn : (R)0;
+  for (int k = 0; k < 3; k++) f[1 + k] = r[k] * irn;
+  // helix phase 2 pi z / pitch, reduced exactly in units of pi
+  R sz, cz;
+  if constexpr (sizeof(R) == 8)
+    sincospi(2.0 * z / c.pitch, &sz, &cz);
+  else
+    sincospif((float)(2 * z) / (float)c.pitch, &sz, &cz);
+  const R third = (R)1 / (R)3;
+  f[4] = cz * cz - third;
+  f[5] = cz * sz;
+  f[6] = 0;
+  f[7] = sz * sz - third;
+  f[8] = 0;
+  f[9] = (R)c.a0 / (R)16;
+  f[10] = (R)32 / (R)c.pitch;
+  f[11] = c.anchoring == 2 ? (R)-1 : (R)1;
+  for (int k = 12; k < 16; k++) f[k] = 0;
+}
+// the 16 channels as BF16 pairs
+template <typename R>
+__device__ inline void pack16(const R f[16], unsigned pk[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; k++) pk[k] = (unsigned)f2bf((float)f[2 * k]) | ((unsigned)f2bf((float)f[2 * k + 1]) << 16);
+}
+
+template <bool F64>
 __global__ void __launch_bounds__(256) k_features(int L, Case c, uint16_t* __restrict__ x0, float* __restrict__ f32) {
+  using R = typename std::conditional<F64, double, float>::type;
   const long long V = (long long)L * L * L;
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  const int x = (int)(v % L), y = (int)((v / L) % L), z = (int)(v / ((long long)L * L));
-  double r[3] = {x - c.pos[0], y - c.pos[1], z - c.pos[2]};
-  for (int k = 0; k < 3; k++) r[k] = r[k] > 0.5 * L ? r[k] - L : (r[k] < -0.5 * L ? r[k] + L : r[k]);
-  const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-  double f[16];
-  double sd = (rn - c.a0) / 8.0;
-  f[0] = sd < -1.0 ? -1.0 : (sd > 2.0 ? 2.0 : sd);
-  for (int k = 0; k < 3; k++) f[1 + k] = rn > 0.0 ? r[k] / rn : 0.0;
-  const double q0 = 2.0 * M_PI / c.pitch;
-  const double cz = cos(q0 * z), sz = sin(q0 * z);
-  f[4] = cz * cz - 1.0 / 3.0;
-  f[5] = cz * sz;
-  f[6] = 0.0;
-  f[7] = sz * sz - 1.0 / 3.0;
-  f[8] = 0.0;
-  f[9] = c.a0 / 16.0;
-  f[10] = 32.0 / c.pitch;
-  f[11] = c.anchoring == 2 ? -1.0 : 1.0;
-  for (int k = 12; k < 16; k++) f[k] = 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; k++) x0[v * 16 + k] = f2bf((float)f[k]);
-  if (f32)
+  // V < 2^31 (the grid is limited to L <= 1024)
+  const unsigned u = (unsigned)v, LL = (unsigned)L * (unsigned)L;
+  const int z = (int)(u / LL), y = (int)((u - (unsigned)z * LL) / (unsigned)L), x = (int)(u - (unsigned)z * LL - (unsigned)y * L);
+  R f[16];
+  features_at<R>(L, c, x, y, z, f);
+  // the voxel's 16 BF16 channels as two 16-byte stores
+  unsigned pk[8];
+  pack16<R>(f, pk);
+  *(u4*)(x0 + v * 16) = u4{pk[0], pk[1], pk[2], pk[3]};
+  *(u4*)(x0 + v * 16 + 8) = u4{pk[4], pk[5], pk[6], pk[7]};
+  if constexpr (F64)
     for (int k = 0; k < 12; k++) f32[k * V + v] = (float)f[k];
 }
 
@@ -78,37 +108,101 @@ __global__ void __launch_bounds__(256) k_features(int L, Case c, uint16_t* __res
 // silu'(zprev) stored as bf16 (data gradient through an activation);
 // MODE 3: acc stored as FP32 (plain data gradient); MODE 4: as MODE 0
 // without keeping z (inference).
-template <int CIN, int COUT, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(COUT == 32 ? 4 : 1)))
+// FEAT (first layer): the input is not read but computed, the 16 features
+// of every halo voxel from the case cs (the FP32 values k_features<false>
+// stores); xf, if not null, receives them for the tile's own voxels.
+template <int CIN, int COUT, int MODE, bool FEAT = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     k_conv(int L, const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias,
-           const float* __restrict__ zprev, float* __restrict__ zout, uint16_t* __restrict__ aout) {
-  // K of one matrix-core instruction: 32 input channels at once
-  // (v_mfma_f32_16x16x32_bf16) where the input has a multiple of 32, else
-  // 16.  Each lane's A and B fragments hold the same KI/4 consecutive
-  // channels, so the products pair up whatever order the instruction
-  // assigns to them within a K block.
+           const float* __restrict__ zprev, float* __restrict__ zout, uint16_t* __restrict__ aout, Case cs,
+           uint16_t* __restrict__ xf) {
+  // Every K step is one v_mfma_f32_16x16x32_bf16: 32 input channels of one
+  // tap, or (16-channel inputs) the 16 channels of two taps, lane groups
+  // kq = 0, 1 taking tap 2s and kq = 2, 3 tap 2s + 1 (tap 27 of the last
+  // pair has zero fragments).  Each lane's A and B fragments hold the same
+  // eight consecutive (tap, channel) pairs, so the products pair up
+  // whatever order the instruction assigns to them within a K block.
   static_assert(CIN == 16 || CIN == 32, "16 or 32 input channels");
-  constexpr int KI = CIN;
+  constexpr bool PAIR = CIN == 16;
+  constexpr int NK = PAIR ? 14 : 27;
   // LDS layout of the halo: voxel (hx, hy, hz) at hx CIN + hy RS + hz PZ
-  // elements, the voxels of an x-row packed, rows 10.5 voxels apart.  A
-  // 16-byte LDS read serves 16 lanes per cycle, lane groups {0-3, 12-15,
-  // 20-23, 24-27}, {4-7, 8-11, 16-19, 28-31} and the same in 32-63
-  // (measured on gfx950 with the bank-conflict counter); each group reads
-  // all 16 voxels of a fragment, half at channel chunk kq and half at
-  // kq + 1, and with these strides the 16 addresses fall in distinct banks.
-  // For 16 channels (8-byte reads) lanes 0-31 fall in distinct banks.  The
-  // packed rows also keep four blocks' halos within one CU's LDS.
-  constexpr int RS = HX * CIN + CIN / 2, PZ = HY * RS, SB = KI == 32 ? 8 : 4;
-  using Chunk = typename std::conditional<SB == 8, u4, uint2>::type;
+  // elements, the voxels of an x-row packed.  A 16-byte LDS read serves 16
+  // lanes per cycle, lane groups {0-3, 12-15, 20-23, 24-27}, {4-7, 8-11,
+  // 16-19, 28-31} and the same in 32-63 (measured on gfx950 with the
+  // bank-conflict counter); each group reads all 16 voxels of a fragment
+  // (of one tap), half at the lane's first channel chunk and half at the
+  // next, and with rows 10.5 voxels apart (32 channels) or 512 bytes apart
+  // (16 channels) the 16 addresses fall in distinct banks.  The packed rows
+  // keep four blocks' halos within one CU's LDS.
+  constexpr int RS = PAIR ? 256 : HX * CIN + CIN / 2, PZ = HY * RS, SB = 8;
+  using Chunk = u4;
   __shared__ __align__(16) uint16_t sx[HZ * PZ];
   const int tid = threadIdx.x;
   const int ntx = L / TX, nty = L / TY;
   const int b = blockIdx.x;
   const int x0 = (b % ntx) * TX, y0 = ((b / ntx) % nty) * TY, z0 = (b / (ntx * nty)) * TZ;
+  const int wv = tid >> 6, lane = tid & 63;
+  const int ri = lane & 15, kq = lane >> 4;
+  // the lane's tap within a pair and first input channel
+  const int hi = PAIR ? kq >> 1 : 0, ch = PAIR ? 8 * (kq & 1) : 8 * kq;
+  // Operand roles: A = weights (M = output channels), B = activations
+  // (N = voxels), so that a lane's accumulators are output channels of one
+  // voxel: D[i][j] sits in lane j + 16 (i / 4), element i % 4.  Row i of M
+  // block mb is output channel oc(mb, i).  With 32 outputs and only BF16
+  // stored (inference) oc = 8 (i / 4) + 4 mb + i % 4, so lane (j, kq)
+  // holds channels 8 kq .. 8 kq + 7 of voxel j (one 16-byte store); when
+  // FP32 values are stored or read oc = 16 mb + i, so that the four lanes
+  // of a voxel cover 16 consecutive channels (64 bytes) per M block.
+  constexpr int NM = COUT / 16, PF = 4;
+  constexpr bool OCT = COUT == 32 && MODE == 4;
+  auto oc = [](int mb, int i) { return OCT ? 8 * (i >> 2) + 4 * mb + (i & 3) : 16 * mb + i; };
+  f4 acc[NM][4];   // [M block][voxel block]
+#pragma unroll
+  for (int mb = 0; mb < NM; mb++)
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) acc[mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  // LDS offset of tap t from the centre voxel
+  auto tap_off = [](int t) { return (t % 3 - 1) * CIN + ((t / 3) % 3 - 1) * RS + (t / 9 - 1) * PZ; };
+  // weight fragments of steps k+1 .. k+PF-1 are in flight while step k runs
+  // on the matrix cores; the first PF are loaded before the halo
+  u4 wq[PF][NM];
+  auto load_w = [&](int k, u4 (&wf)[NM]) {
+    const bool pad = PAIR && k == NK - 1 && hi;   // tap 27: zero
+    const int t = pad ? 26 : (PAIR ? 2 * k + hi : k);
+#pragma unroll
+    for (int mb = 0; mb < NM; mb++) {
+      const u4 v = *(const u4*)(w + ((long long)(t * COUT + oc(mb, ri)) * CIN + ch));
+      wf[mb] = pad ? u4{0u, 0u, 0u, 0u} : v;
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < PF; k++) load_w(k, wq[k]);
   // halo staging: every load is issued before the first store to LDS, so
   // their latencies overlap
   constexpr int CH = CIN / SB, NIT = (HV * CH + 255) / 256;
-  {
+  if constexpr (FEAT) {
+    static_assert(CIN == 16, "16 feature channels");
+#pragma unroll
+    for (int it = 0; it < (HV + 255) / 256; it++) {
+      const int v = tid + it * 256;
+      if (v < HV) {
+        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+        const int gx = wrap1(x0 - 1 + hx, L), gy = wrap1(y0 - 1 + hy, L), gz = wrap1(z0 - 1 + hz, L);
+        float f[16];
+        unsigned pk[8];
+        features_at<float>(L, cs, gx, gy, gz, f);
+        pack16<float>(f, pk);
+        uint16_t* d = sx + hx * CIN + hy * RS + hz * PZ;
+        *(u4*)d = u4{pk[0], pk[1], pk[2], pk[3]};
+        *(u4*)(d + 8) = u4{pk[4], pk[5], pk[6], pk[7]};
+        if (xf && hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && hz >= 1 && hz <= TZ) {
+          uint16_t* g = xf + (gx + (long long)L * (gy + (long long)L * gz)) * 16;
+          *(u4*)g = u4{pk[0], pk[1], pk[2], pk[3]};
+          *(u4*)(g + 8) = u4{pk[4], pk[5], pk[6], pk[7]};
+        }
+      }
+    }
+  } else {
     Chunk tmp[NIT];
     int soff[NIT];
 #pragma unroll
@@ -130,74 +224,63 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(COUT =
     }
   }
   __syncthreads();
-  const int wv = tid >> 6, lane = tid & 63;
-  const int ri = lane & 15, kq = lane >> 4;
-  f4 acc[4][COUT / 16];
+  // voxel block nb of the wave: x = ri & 7, y = 2 nb + (ri >> 3)
+  const uint16_t* sa = sx + ((ri & 7) + 1) * CIN + ((ri >> 3) + 1) * RS + (wv + 1) * PZ + ch;
 #pragma unroll
-  for (int m = 0; m < 4; m++)
+  for (int k = 0; k < NK; k++) {
+    const int off = PAIR ? (hi ? tap_off(k == NK - 1 ? 26 : 2 * k + 1) : tap_off(2 * k)) : tap_off(k);
 #pragma unroll
-    for (int n = 0; n < COUT / 16; n++) acc[m][n] = f4{0.f, 0.f, 0.f, 0.f};
-  // weight fragments of taps t+1 .. t+PF-1 are in flight while tap t runs
-  // on the matrix cores
-  constexpr int KC = CIN / KI, NN = COUT / 16, PF = 4;
-  using Frag = typename std::conditional<KI == 32, u4, s4>::type;
-  Frag bq[PF][KC][NN];
-  auto load_b = [&](int t, Frag (&bf)[KC][NN]) {
+    for (int nb = 0; nb < 4; nb++) {
+      const u4 xf = *(const u4*)(sa + off + 2 * nb * RS);
 #pragma unroll
-    for (int kc = 0; kc < KC; kc++)
-#pragma unroll
-      for (int n = 0; n < NN; n++)
-        bf[kc][n] = *(const Frag*)(w + ((long long)(t * COUT + n * 16 + ri) * CIN + kc * KI + (KI / 4) * kq));
-  };
-#pragma unroll
-  for (int t = 0; t < PF; t++) load_b(t, bq[t]);
-#pragma unroll
-  for (int t = 0; t < 27; t++) {
-    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-#pragma unroll
-    for (int kc = 0; kc < KC; kc++) {
-#pragma unroll
-      for (int m = 0; m < 4; m++) {
-        const int lx = ri & 7, ly = 2 * m + (ri >> 3);
-        const Frag af = *(const Frag*)(sx + (lx + 1 + dx) * CIN + (ly + 1 + dy) * RS + (wv + 1 + dz) * PZ + kc * KI +
-                                       (KI / 4) * kq);
-#pragma unroll
-        for (int n = 0; n < NN; n++) {
-          if constexpr (KI == 32)
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, af),
-                                                                __builtin_bit_cast(bf8, bq[t % PF][kc][n]),
-                                                                acc[m][n], 0, 0, 0);
-          else
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bq[t % PF][kc][n], acc[m][n], 0, 0, 0);
-        }
-      }
+      for (int mb = 0; mb < NM; mb++)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, wq[k % PF][mb]),
+                                                              __builtin_bit_cast(bf8, xf), acc[mb][nb], 0, 0, 0);
     }
-    if (t + PF < 27) load_b(t + PF, bq[t % PF]);
+    if (k + PF < NK) load_w(k + PF, wq[k % PF]);
+  }
+  // epilogue: lane (ri, kq) owns, for each M block mb, the four channels
+  // oc(mb, 4 kq) .. + 3 of voxel (ri & 7, 2 nb + (ri >> 3)) of the wave's
+  // layer.  Every value it reads (bias, z of the previous pass) is loaded
+  // before its first store, so that no load waits behind the stores.
+  const long long gv0 = (x0 + (ri & 7)) + (long long)L * ((y0 + (ri >> 3)) + (long long)L * (z0 + wv));
+  f4 bj[NM], zq[MODE == 2 ? 4 : 1][NM];
+#pragma unroll
+  for (int mb = 0; mb < NM; mb++)
+    bj[mb] = (MODE == 0 || MODE == 1 || MODE == 4) ? *(const f4*)(bias + oc(mb, 4 * kq)) : f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (MODE == 2) {
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+      for (int mb = 0; mb < NM; mb++) zq[nb][mb] = *(const f4*)(zprev + (gv0 + 2LL * nb * L) * COUT + oc(mb, 4 * kq));
   }
 #pragma unroll
-  for (int m = 0; m < 4; m++)
+  for (int nb = 0; nb < 4; nb++) {
+    const long long base = (gv0 + 2LL * nb * L) * COUT;
+    unsigned pk[NM][2];
 #pragma unroll
-    for (int n = 0; n < COUT / 16; n++)
+    for (int mb = 0; mb < NM; mb++) {
+      f4 v = acc[mb][nb];
+      if constexpr (MODE == 0 || MODE == 1 || MODE == 4) v += bj[mb];
+      if constexpr (MODE == 0 || MODE == 1 || MODE == 3) *(f4*)(zout + base + oc(mb, 4 * kq)) = v;
+      if constexpr (MODE == 0 || MODE == 2 || MODE == 4) {
+        float a[4];
 #pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const int i = 4 * kq + e, j = n * 16 + ri;
-        const int lx = i & 7, ly = 2 * m + (i >> 3);
-        const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + wv));
-        const float val = acc[m][n][e];
-        if (MODE == 0 || MODE == 4) {
-          const float z = val + bias[j];
-          if (MODE == 0) zout[gv * COUT + j] = z;
-          aout[gv * COUT + j] = f2bf(z * sigmoidf_(z));
-        } else if (MODE == 1) {
-          zout[gv * COUT + j] = val + bias[j];
-        } else if (MODE == 2) {
-          const float zp = zprev[gv * COUT + j];
-          const float s = sigmoidf_(zp);
-          aout[gv * COUT + j] = f2bf(val * (s * (1.0f + zp * (1.0f - s))));
-        } else {
-          zout[gv * COUT + j] = val;
+        for (int e = 0; e < 4; e++) {
+          if constexpr (MODE == 2) {
+            const float zp = zq[nb][mb][e], sg = sigmoidf_(zp);
+            a[e] = v[e] * (sg * (1.0f + zp * (1.0f - sg)));
+          } else {
+            a[e] = v[e] * sigmoidf_(v[e]);
+          }
         }
+        pk[mb][0] = (unsigned)f2bf(a[0]) | ((unsigned)f2bf(a[1]) << 16);
+        pk[mb][1] = (unsigned)f2bf(a[2]) | ((unsigned)f2bf(a[3]) << 16);
+        if constexpr (!OCT) *(uint2*)(aout + base + oc(mb, 4 * kq)) = uint2{pk[mb][0], pk[mb][1]};
       }
+    }
+    if constexpr (OCT) *(u4*)(aout + base + 8 * kq) = u4{pk[0][0], pk[0][1], pk[1][0], pk[1][1]};
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -423,8 +506,11 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------
 // loss and its gradient; warm-start output
 // ---------------------------------------------------------------------
-__device__ inline void helix_unit(double q0, int z, double h[5]) {
-  const double c = cos(q0 * z), s = sin(q0 * z);
+// unit helix Q at layer z for the given pitch (phase 2 pi z / pitch,
+// reduced exactly in units of pi)
+__device__ inline void helix_unit(double pitch, int z, double h[5]) {
+  double s, c;
+  sincospi(2.0 * z / pitch, &s, &c);
   h[0] = c * c - 1.0 / 3.0; h[1] = c * s; h[2] = 0.0; h[3] = s * s - 1.0 / 3.0; h[4] = 0.0;
 }
 
@@ -438,9 +524,9 @@ __global__ void __launch_bounds__(256)
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double l2 = 0.0;
   if (v < V) {
-    const int z = (int)(v / ((long long)L * L));
+    const int z = (int)((unsigned)v / ((unsigned)L * (unsigned)L));
     double h[5];
-    helix_unit(2.0 * M_PI / c.pitch, z, h);
+    helix_unit(c.pitch, z, h);
     float d[5];
     for (int k = 0; k < 5; k++) d[k] = (float)(c.q_amp * h[k]) + (float)c.q_eq * out[v * 16 + k] - Qt[k * V + v];
     const bool f = fluid[v] != 0;
@@ -450,7 +536,12 @@ __global__ void __launch_bounds__(256)
     }
     const float sc = f ? (float)(c.q_eq * inv_nf) : 0.f;
     const float g[5] = {4.f * d[0] + 2.f * d[3], 4.f * d[1], 4.f * d[2], 4.f * d[3] + 2.f * d[0], 4.f * d[4]};
-    for (int k = 0; k < 16; k++) dz[v * 16 + k] = k < 5 ? f2bf(sc * g[k]) : (uint16_t)0;
+    // channels 0-4 of the voxel's 16 (the rest zero) as two 16-byte stores
+    const unsigned p0 = (unsigned)f2bf(sc * g[0]) | ((unsigned)f2bf(sc * g[1]) << 16);
+    const unsigned p1 = (unsigned)f2bf(sc * g[2]) | ((unsigned)f2bf(sc * g[3]) << 16);
+    const unsigned p2 = (unsigned)f2bf(sc * g[4]);
+    *(u4*)(dz + v * 16) = u4{p0, p1, p2, 0u};
+    *(u4*)(dz + v * 16 + 8) = u4{0u, 0u, 0u, 0u};
   }
   s[threadIdx.x] = l2;
   __syncthreads();
@@ -469,7 +560,7 @@ __global__ void __launch_bounds__(256)
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   double h[5];
-  helix_unit(2.0 * M_PI / c.pitch, (int)(v / ((long long)L * L)), h);
+  helix_unit(c.pitch, (int)((unsigned)v / ((unsigned)L * (unsigned)L)), h);
   for (int k = 0; k < 5; k++) Q[k * nsites + off + v] = (R)(c.q_amp * h[k] + c.q_eq * (double)out[v * 16 + k]);
 }
 
@@ -530,7 +621,10 @@ __global__ void k_unpack_f32(long long V, int C, int CP, const float* __restrict
 // ---------------------------------------------------------------------
 hipError_t launch_features(int L, const Case& c, uint16_t* x0, float* f32, hipStream_t s) {
   const long long V = (long long)L * L * L;
-  k_features<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(L, c, x0, f32);
+  if (f32)
+    k_features<true><<<(unsigned)((V + 255) / 256), 256, 0, s>>>(L, c, x0, f32);
+  else
+    k_features<false><<<(unsigned)((V + 255) / 256), 256, 0, s>>>(L, c, x0, f32);
   return hipGetLastError();
 }
 
@@ -539,7 +633,7 @@ hipError_t launch_conv(int cinp, int coutp, int mode, int L, const uint16_t* x, 
   const int nblk = (L / TX) * (L / TY) * (L / TZ);
 #define LCNN_CONV(CI, CO, M)                                                            \
   if (cinp == CI && coutp == CO && mode == M) {                                         \
-    k_conv<CI, CO, M><<<nblk, 256, 0, s>>>(L, x, w, bias, zprev, zout, aout);           \
+    k_conv<CI, CO, M><<<nblk, 256, 0, s>>>(L, x, w, bias, zprev, zout, aout, Case{}, nullptr); \
     return hipGetLastError();                                                           \
   }
   LCNN_CONV(16, 32, 0)
@@ -554,6 +648,18 @@ hipError_t launch_conv(int cinp, int coutp, int mode, int L, const uint16_t* x, 
   LCNN_CONV(32, 16, 3)
 #undef LCNN_CONV
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv_feat(int mode, int L, const Case& c, const uint16_t* w, const float* bias, float* zout,
+                            uint16_t* aout, uint16_t* xf, hipStream_t s) {
+  const int nblk = (L / TX) * (L / TY) * (L / TZ);
+  if (mode == 0)
+    k_conv<16, 32, 0, true><<<nblk, 256, 0, s>>>(L, nullptr, w, bias, nullptr, zout, aout, c, xf);
+  else if (mode == 4)
+    k_conv<16, 32, 4, true><<<nblk, 256, 0, s>>>(L, nullptr, w, bias, nullptr, zout, aout, c, xf);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_wgrad(int cinp, int coutp, int L, int nblk, int tpb, const uint16_t* dz, const uint16_t* x,

@@ -21,6 +21,11 @@ hipError_t launch_features(int L, const Case& c, uint16_t* x0, float* f32, hipSt
 // silu'(zprev), bf16 out; 3: FP32 out
 hipError_t launch_conv(int cinp, int coutp, int mode, int L, const uint16_t* x, const uint16_t* w, const float* bias,
                        const float* zprev, float* zout, uint16_t* aout, hipStream_t s);
+// The first layer (16 -> 32, mode 0 or 4) with its input features computed
+// in the halo staging instead of read; xf (if not null) receives them
+// (BF16 [V][16], as launch_features without f32 writes).
+hipError_t launch_conv_feat(int mode, int L, const Case& c, const uint16_t* w, const float* bias, float* zout,
+                            uint16_t* aout, uint16_t* xf, hipStream_t s);
 // Weight and bias gradients of a layer: per-block partials (nblk blocks of
 // tpb tiles; 27 coutp cinp + coutp floats each), then their fixed-order sum
 // into dW [cout][cin][27] and db [cout].

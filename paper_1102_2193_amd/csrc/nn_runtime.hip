@@ -94,9 +94,12 @@ int refresh_bf16(lc_nn* n, int l) {
 
 // Forward pass; `keep` stores the pre-activations for a backward pass.
 int forward(lc_nn* n, const lcnn::Case& k, bool keep) {
-  NNCHK(n, lcnn::launch_features(n->L, k, n->x0, nullptr, n->stream));
-  const uint16_t* in = n->x0;
-  for (int l = 0; l < NL - 1; l++) {
+  // layer 0 computes its input features itself (kept in x0 for the weight
+  // gradient when training)
+  NNCHK(n, lcnn::launch_conv_feat(keep ? 0 : 4, n->L, k, n->wf[0], n->b[0], n->z[0], n->a[0], keep ? n->x0 : nullptr,
+                                  n->stream));
+  const uint16_t* in = n->a[0];
+  for (int l = 1; l < NL - 1; l++) {
     NNCHK(n, lcnn::launch_conv(CINP[l], COUTP[l], keep ? 0 : 4, n->L, in, n->wf[l], n->b[l], nullptr, n->z[l],
                                n->a[l], n->stream));
     in = n->a[l];
@@ -167,7 +170,7 @@ extern "C" {
 int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out) {
   if (!out) return nfail(nullptr, LC_EINVAL, "out is NULL");
   *out = nullptr;
-  if (L < 8 || L % 8) return nfail(nullptr, LC_EINVAL, "L must be a positive multiple of 8");
+  if (L < 8 || L % 8 || L > 1024) return nfail(nullptr, LC_EINVAL, "L must be a multiple of 8 in [8, 1024]");
   lc_nn* n = new lc_nn();
   n->L = L;
   n->V = (long long)L * L * L;

@@ -107,3 +107,6 @@ def test_nn_create_rejects_bad_grid(lib):
     h = ctypes.c_void_p()
     assert L.lc_nn_create(12, 0, None, ctypes.byref(h)) == 1
     assert b"multiple of 8" in L.lc_nn_last_error(None)
+    # the elementwise kernels index voxels in 32 bits
+    assert L.lc_nn_create(1032, 0, None, ctypes.byref(h)) == 1
+    assert b"[8, 1024]" in L.lc_nn_last_error(None)
