@@ -283,6 +283,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
   }
 }
 
+// one Adam step of parameter w with gradient g (beta1 0.9, beta2 0.999,
+// eps 1e-8; c1, c2 the bias corrections of the step)
+__device__ inline float adam_step(float w, float g, float& m, float& v, float lr, float c1, float c2) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  m = b1 * m + (1.f - b1) * g;
+  v = b2 * v + (1.f - b2) * g * g;
+  return w - lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
 // ---------------------------------------------------------------------
 // weight gradient: dW[t][o][c] = sum_p dz[p][o] x[p + d_t][c]
 // ---------------------------------------------------------------------
@@ -469,10 +478,18 @@ __global__ void __launch_bounds__(kWgThreads)
 // bias partials that follow them into db[o].  A workgroup
 // takes 64 consecutive partial entries (coalesced rows); wave w sums blocks
 // w, w+4, ... and the four wave sums are added in wave order, so the result
-// does not depend on timing.
+// does not depend on timing.  ADAM: instead of storing the gradient, the
+// thread that summed it takes the layer's Adam step on that weight (W, its
+// moments and both BF16 copies, as k_adam) or bias.
+struct AdamArgs {
+  float *W, *b, *mW, *vW, *mb, *vb;
+  float lr, c1, c2;
+  uint16_t *wf, *wb;
+};
+template <bool ADAM>
 __global__ void __launch_bounds__(256)
     k_wgrad_reduce(int nblk, int COUTP, int CINP, int cout, int cin, const float* __restrict__ part,
-                   float* __restrict__ dW, float* __restrict__ db) {
+                   float* __restrict__ dW, float* __restrict__ db, AdamArgs ad) {
   __shared__ float s[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nw = 27 * COUTP * CINP, np = nw + COUTP;   // weight entries, then the biases
@@ -496,9 +513,24 @@ __global__ void __launch_bounds__(256)
     const float t4 = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
     if (i < nw) {
       const int c = i % CINP, o = (i / CINP) % COUTP, t = i / (CINP * COUTP);
-      if (o < cout && c < cin) dW[(o * cin + c) * 27 + t] = t4;
+      if (o < cout && c < cin) {
+        const int e = (o * cin + c) * 27 + t;
+        if constexpr (ADAM) {
+          const float wn = adam_step(ad.W[e], t4, ad.mW[e], ad.vW[e], ad.lr, ad.c1, ad.c2);
+          ad.W[e] = wn;
+          const uint16_t h = f2bf(wn);
+          ad.wf[(t * COUTP + o) * CINP + c] = h;
+          ad.wb[((26 - t) * CINP + c) * COUTP + o] = h;
+        } else {
+          dW[e] = t4;
+        }
+      }
     } else if (i - nw < cout) {
-      db[i - nw] = t4;
+      const int o = i - nw;
+      if constexpr (ADAM)
+        ad.b[o] = adam_step(ad.b[o], t4, ad.mb[o], ad.vb[o], ad.lr, ad.c1, ad.c2);
+      else
+        db[o] = t4;
     }
   }
 }
@@ -576,16 +608,10 @@ __global__ void __launch_bounds__(256)
            uint16_t* __restrict__ wb) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int nW = cout * cin * 27;
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   if (e < nW) {
     float w = W[e];
     if (update) {
-      const float g = dW[e];
-      const float m = b1 * mW[e] + (1.f - b1) * g;
-      const float v = b2 * vW[e] + (1.f - b2) * g * g;
-      mW[e] = m;
-      vW[e] = v;
-      w -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+      w = adam_step(w, dW[e], mW[e], vW[e], lr, c1, c2);
       W[e] = w;
     }
     const int t = e % 27, c = (e / 27) % cin, o = e / (27 * cin);
@@ -594,12 +620,7 @@ __global__ void __launch_bounds__(256)
     wb[((26 - t) * CINP + c) * COUTP + o] = h;
   } else if (e < nW + cout && update) {
     const int o = e - nW;
-    const float g = db[o];
-    const float m = b1 * mb[o] + (1.f - b1) * g;
-    const float v = b2 * vb[o] + (1.f - b2) * g * g;
-    mb[o] = m;
-    vb[o] = v;
-    b[o] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+    b[o] = adam_step(b[o], db[o], mb[o], vb[o], lr, c1, c2);
   }
 }
 
@@ -679,7 +700,16 @@ hipError_t launch_wgrad(int cinp, int coutp, int L, int nblk, int tpb, const uin
 hipError_t launch_wgrad_reduce(int nblk, int coutp, int cinp, int cout, int cin, const float* part, float* dW,
                                float* db, hipStream_t s) {
   const int np = 27 * coutp * cinp + coutp;
-  k_wgrad_reduce<<<(np + 63) / 64, 256, 0, s>>>(nblk, coutp, cinp, cout, cin, part, dW, db);
+  k_wgrad_reduce<false><<<(np + 63) / 64, 256, 0, s>>>(nblk, coutp, cinp, cout, cin, part, dW, db, AdamArgs{});
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad_adam(int nblk, int coutp, int cinp, int cout, int cin, const float* part, float* W, float* b,
+                             float* mW, float* vW, float* mb, float* vb, float lr, float c1, float c2, uint16_t* wf,
+                             uint16_t* wb, hipStream_t s) {
+  const int np = 27 * coutp * cinp + coutp;
+  const AdamArgs ad{W, b, mW, vW, mb, vb, lr, c1, c2, wf, wb};
+  k_wgrad_reduce<true><<<(np + 63) / 64, 256, 0, s>>>(nblk, coutp, cinp, cout, cin, part, nullptr, nullptr, ad);
   return hipGetLastError();
 }
 

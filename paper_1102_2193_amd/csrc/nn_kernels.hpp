@@ -33,6 +33,11 @@ hipError_t launch_wgrad(int cinp, int coutp, int L, int nblk, int tpb, const uin
                         float* part, hipStream_t s);
 hipError_t launch_wgrad_reduce(int nblk, int coutp, int cinp, int cout, int cin, const float* part, float* dW,
                                float* db, hipStream_t s);
+// The same sums, each followed by the layer's Adam step on that weight or
+// bias (as launch_adam with update 1) instead of being stored.
+hipError_t launch_wgrad_adam(int nblk, int coutp, int cinp, int cout, int cin, const float* part, float* W, float* b,
+                             float* mW, float* vW, float* mb, float* vb, float lr, float c1, float c2, uint16_t* wf,
+                             uint16_t* wb, hipStream_t s);
 hipError_t launch_loss(int L, const Case& c, const float* out, const float* Qt, const uint8_t* fluid, double inv_nf,
                        uint16_t* dz, double* part, hipStream_t s);
 template <typename R>

@@ -116,24 +116,25 @@ int layer_grads(lc_nn* n, int l, const uint16_t* dz, const uint16_t* x) {
   return LC_OK;
 }
 
+// Backward pass and Adam step.  Per layer, from the last: the data
+// gradient for the layer below (with the layer's old BF16 weights), then the
+// weight and bias gradients, summed and applied by one fused kernel.
 int backward_and_update(lc_nn* n, float lr) {
+  n->step++;
+  const float c1 = 1.f - powf(0.9f, (float)n->step), c2 = 1.f - powf(0.999f, (float)n->step);
   const uint16_t* dz = n->g4;
   for (int l = NL - 1; l >= 0; l--) {
     const uint16_t* x = l == 0 ? n->x0 : n->a[l - 1];
-    int rc = layer_grads(n, l, dz, x);
-    if (rc) return rc;
-    if (l > 0) {
+    if (l > 0)
       // d loss / d z_{l-1} = (W^T * dz) times silu'(z_{l-1})
       NNCHK(n, lcnn::launch_conv(COUTP[l], CINP[l], 2, n->L, dz, n->wb[l], nullptr, n->z[l - 1], nullptr,
                                  n->g[l - 1], n->stream));
-      dz = n->g[l - 1];
-    }
+    NNCHK(n, lcnn::launch_wgrad(CINP[l], COUTP[l], n->L, n->wblk, n->tpb, dz, x, n->wpart, n->stream));
+    NNCHK(n, lcnn::launch_wgrad_adam(n->wblk, COUTP[l], CINP[l], COUT[l], CIN[l], n->wpart, n->W[l], n->b[l],
+                                     n->mW[l], n->vW[l], n->mb[l], n->vb[l], lr, c1, c2, n->wf[l], n->wb[l],
+                                     n->stream));
+    if (l > 0) dz = n->g[l - 1];
   }
-  n->step++;
-  const float c1 = 1.f - powf(0.9f, (float)n->step), c2 = 1.f - powf(0.999f, (float)n->step);
-  for (int l = 0; l < NL; l++)
-    NNCHK(n, lcnn::launch_adam(COUT[l], CIN[l], COUTP[l], CINP[l], n->W[l], n->b[l], n->dW[l], n->db[l], n->mW[l],
-                               n->vW[l], n->mb[l], n->vb[l], lr, c1, c2, 1, n->wf[l], n->wb[l], n->stream));
   return LC_OK;
 }
 
