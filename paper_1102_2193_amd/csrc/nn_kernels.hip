@@ -14,6 +14,7 @@
 
 #include <type_traits>
 
+#include "lc_arch.hpp"
 #include "nn_kernels.hpp"
 
 namespace lcnn {
@@ -305,12 +306,9 @@ __device__ inline float adam_step(float w, float g, float& m, float& v, float lr
 // 16-byte LDS read serves the lane groups {0-3, 12-15, 20-23, 24-27},
 // {4-7, 8-11, 16-19, 28-31} (and the same in 32-63) one per cycle: with
 // row strides of 34 and 62 16-byte chunks (2 mod 4) the eight lanes of
-// each row half that a group holds fall in distinct banks.  Staging loads
-// four voxels (eight channels each) per item and writes one 64-bit row
-// segment per channel; item oc of an octet writes its channels rotated by
-// 8 oc / octets (the load's dwords rotated in registers), so that the
-// lanes of one 64-bit store, which hold all octets, write banks 64 or 128
-// bytes apart instead of the same ones.
+// each row half that a group holds fall in distinct banks.  The staging
+// loads each input voxel once (a halo row's ten voxels per item) and
+// writes 16-byte row segments.
 // Block b accumulates over tiles [b*tpb, (b+1)*tpb) and writes its partial
 // sums part[b][27][COUT][CIN] followed by the bias-gradient partials
 // part[b][27 COUT CIN + o] = sum of dz[p][o] over its voxels (row sums of
@@ -338,85 +336,63 @@ __global__ void __launch_bounds__(kWgThreads)
       for (int n = 0; n < CIN / 16; n++) acc[a][m][n] = f4{0.f, 0.f, 0.f, 0.f};
   static_assert(COUT * 16 <= kWgThreads && TV == 16 * 16, "16 threads of 16 voxels per dz row");
   float bacc = 0.f;   // bias gradient: this thread's 16 voxels of row tid / 16, over the tiles
-  // staging items: (voxel quad, channel octet) of dz; (copy, halo row, quad,
-  // channel octet) of the input
+  // staging items: (halo row, channel octet) of the input, whose ten voxels
+  // are loaded once and written as the three shifted copies, on threads
+  // [0, NXI); (tile x-row, channel octet) of dz on threads [NXI, NXI + NDI).
+  // An item writes one 16-byte segment (eight voxels of one channel) per
+  // channel and copy.
   constexpr int DO = COUT / 8, XO = CIN / 8;
-  constexpr int NDZ = (TV / 4) * DO, NXS = 3 * NROW * 2 * XO;
-  constexpr int NID = (NDZ + kWgThreads - 1) / kWgThreads, NIX = (NXS + kWgThreads - 1) / kWgThreads;
-  // element k (0..7) of four voxels' octets as one 64-bit row segment
-  auto seg = [](const u4 (&v)[4], int k) {
+  constexpr int NXI = NROW * XO, NDI = (TV / TX) * DO;
+  static_assert(NXI + NDI <= kWgThreads && TX == 8, "one staging item per thread, 8-voxel rows");
+  // element k (0..7) of the octets of voxels v[0..7] as one 16-byte segment
+  auto seg8 = [](const u4* v, int k) {
     const int d = k >> 1, sh = 16 * (k & 1);
-    const unsigned e0 = (v[0][d] >> sh) & 0xffffu, e1 = (v[1][d] >> sh) & 0xffffu;
-    const unsigned e2 = (v[2][d] >> sh) & 0xffffu, e3 = (v[3][d] >> sh) & 0xffffu;
-    return uint2{e0 | (e1 << 16), e2 | (e3 << 16)};
-  };
-  // the four voxels' octets with dword d taken from dword (d + r) & 3:
-  // element k is then channel (k + 2 r) & 7 of the octet
-  auto rot = [](const u4 (&v)[4], int r, u4 (&o)[4]) {
+    unsigned o[4];
 #pragma unroll
-    for (int j = 0; j < 4; j++)
-#pragma unroll
-      for (int d = 0; d < 4; d++) {
-        const int q = (d + r) & 3;
-        o[j][d] = q == 0 ? v[j][0] : q == 1 ? v[j][1] : q == 2 ? v[j][2] : v[j][3];
-      }
+    for (int q = 0; q < 4; q++)
+      o[q] = ((v[2 * q][d] >> sh) & 0xffffu) | (((v[2 * q + 1][d] >> sh) & 0xffffu) << 16);
+    return u4{o[0], o[1], o[2], o[3]};
   };
-  static_assert((DO == 2 || DO == 4) && (XO == 2 || XO == 4), "16 or 32 channels");
-  for (int tile = blockIdx.x * tpb; tile < (blockIdx.x + 1) * tpb && tile < ntile; tile++) {
+  // the global loads of a tile's items: all issued before the first LDS
+  // store; the next tile's are issued once this tile's are stored, so they
+  // overlap this tile's matrix-core work
+  u4 tv[HX];
+  auto load_items = [&](int tile) {
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-    // every global load of the tile is issued before the first LDS store
-    u4 td[NID][4], tx[NIX][4];
+    if (tid < NXI) {
+      const int oc = tid % XO, row = tid / XO, hy = row % HY, hz = row / HY;
+      const long long gyz = (long long)L * (wrap1(y0 - 1 + hy, L) + (long long)L * wrap1(z0 - 1 + hz, L));
 #pragma unroll
-    for (int it = 0; it < NID; it++) {
-      const int e = tid + it * kWgThreads;
-      if (e < NDZ) {
-        const int oc = e % DO, p = 4 * (e / DO);   // four voxels along x in one row
-        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        const long long gv = (x0 + lx) + (long long)L * ((y0 + ly) + (long long)L * (z0 + lz));
+      for (int i = 0; i < HX; i++) tv[i] = *(const u4*)(x + (wrap1(x0 - 1 + i, L) + gyz) * CIN + 8 * oc);
+    } else if (tid < NXI + NDI) {
+      const int e = tid - NXI, oc = e % DO, p8 = e / DO, ly = p8 % TY, lz = p8 / TY;
+      const long long gv = x0 + (long long)L * ((y0 + ly) + (long long)L * (z0 + lz));
 #pragma unroll
-        for (int j = 0; j < 4; j++) td[it][j] = *(const u4*)(dz + (gv + j) * COUT + 8 * oc);
-      }
+      for (int j = 0; j < TX; j++) tv[j] = *(const u4*)(dz + (gv + j) * COUT + 8 * oc);
     }
+  };
+  const int tile_end = min((blockIdx.x + 1) * tpb, ntile);
+  if (blockIdx.x * tpb < tile_end) load_items(blockIdx.x * tpb);
+  // the barriers below order LDS accesses only (lc::lds_sync), so the next
+  // tile's loads stay in flight across them
+  for (int tile = blockIdx.x * tpb; tile < tile_end; tile++) {
+    lc::lds_sync();   // the previous tile's LDS reads are done
+    // the four lanes of a voxel write rows that meet in the same banks;
+    // rotating each item's channel order removes those conflicts but costs
+    // more in register rotations than it saves
+    if (tid < NXI) {
+      const int oc = tid % XO, row = tid / XO;
 #pragma unroll
-    for (int it = 0; it < NIX; it++) {
-      const int e = tid + it * kWgThreads;
-      if (e < NXS) {
-        const int oc = e % XO, r = e / XO, quad = r % 2, row = (r / 2) % NROW, cp = r / (2 * NROW);
-        const int hy = row % HY, hz = row / HY;
-        const long long gyz = (long long)L * (wrap1(y0 - 1 + hy, L) + (long long)L * wrap1(z0 - 1 + hz, L));
+      for (int cp = 0; cp < 3; cp++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int gx = wrap1(x0 - 1 + 4 * quad + cp + j, L);   // halo x = element + cp
-          tx[it][j] = *(const u4*)(x + (gx + gyz) * CIN + 8 * oc);
-        }
-      }
+        for (int k = 0; k < 8; k++) *(u4*)(sxs + (cp * CIN + 8 * oc + k) * CSTR + row * 8) = seg8(tv + cp, k);
+    } else if (tid < NXI + NDI) {
+      const int e = tid - NXI, oc = e % DO, p8 = e / DO;
+#pragma unroll
+      for (int k = 0; k < 8; k++) *(u4*)(sd + (8 * oc + k) * PS + 8 * p8) = seg8(tv, k);
     }
-    __syncthreads();   // the previous tile's LDS reads are done
-#pragma unroll
-    for (int it = 0; it < NID; it++) {
-      const int e = tid + it * kWgThreads;
-      if (e < NDZ) {
-        const int oc = e % DO, p = 4 * (e / DO), r = (4 / DO) * oc;
-        u4 v[4];
-        rot(td[it], r, v);
-#pragma unroll
-        for (int k = 0; k < 8; k++) *(uint2*)(sd + (8 * oc + ((k + 2 * r) & 7)) * PS + p) = seg(v, k);
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < NIX; it++) {
-      const int e = tid + it * kWgThreads;
-      if (e < NXS) {
-        const int oc = e % XO, r = e / XO, quad = r % 2, row = (r / 2) % NROW, cp = r / (2 * NROW);
-        const int rr = (4 / XO) * oc;
-        u4 v[4];
-        rot(tx[it], rr, v);
-#pragma unroll
-        for (int k = 0; k < 8; k++)
-          *(uint2*)(sxs + (cp * CIN + 8 * oc + ((k + 2 * rr) & 7)) * CSTR + row * 8 + 4 * quad) = seg(v, k);
-      }
-    }
-    __syncthreads();
+    if (tile + 1 < tile_end) load_items(tile + 1);
+    lc::lds_sync();
     if (tid < COUT * 16) {
       const u4* r = (const u4*)(sd + (tid >> 4) * PS + 16 * (tid & 15));
       float t = 0.f;
