@@ -472,16 +472,16 @@ __global__ void __launch_bounds__(256)
   const int i = blockIdx.x * 64 + lane;
   float acc = 0.f;
   if (i < np)
-    for (int k0 = w; k0 < nblk; k0 += 32) {
-      // eight loads in flight, added in the order k = w, w + 4, ...
-      float t[8];
+    for (int k0 = w; k0 < nblk; k0 += 64) {
+      // sixteen loads in flight, added in the order k = w, w + 4, ...
+      float t[16];
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
+      for (int j = 0; j < 16; j++) {
         const int k = k0 + 4 * j;
         t[j] = k < nblk ? part[(long long)k * np + i] : 0.f;
       }
 #pragma unroll
-      for (int j = 0; j < 8; j++) acc += t[j];
+      for (int j = 0; j < 16; j++) acc += t[j];
     }
   s[w][lane] = acc;
   __syncthreads();
