@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "lc_arch.hpp"
+#include "lc_reduce.hpp"
 #include "nn_kernels.hpp"
 
 namespace lcnn {
@@ -371,11 +372,11 @@ __global__ void __launch_bounds__(kWgThreads)
       for (int j = 0; j < TX; j++) tv[j] = *(const u4*)(dz + (gv + j) * COUT + 8 * oc);
     }
   };
-  const int tile_end = min((blockIdx.x + 1) * tpb, ntile);
-  if (blockIdx.x * tpb < tile_end) load_items(blockIdx.x * tpb);
+  const int tile_beg = (int)blockIdx.x * tpb, tile_end = min(tile_beg + tpb, ntile);
+  if (tile_beg < tile_end) load_items(tile_beg);
   // the barriers below order LDS accesses only (lc::lds_sync), so the next
   // tile's loads stay in flight across them
-  for (int tile = blockIdx.x * tpb; tile < tile_end; tile++) {
+  for (int tile = tile_beg; tile < tile_end; tile++) {
     lc::lds_sync();   // the previous tile's LDS reads are done
     // the four lanes of a voxel write rows that meet in the same banks;
     // rotating each item's channel order removes those conflicts but costs
@@ -527,7 +528,7 @@ __device__ inline void helix_unit(double pitch, int z, double h[5]) {
 __global__ void __launch_bounds__(256)
     k_loss(int L, Case c, const float* __restrict__ out, const float* __restrict__ Qt, const uint8_t* __restrict__ fluid,
            double inv_nf, uint16_t* __restrict__ dz, double* __restrict__ part) {
-  __shared__ double s[256];
+  __shared__ double sred[4];
   const long long V = (long long)L * L * L;
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double l2 = 0.0;
@@ -535,8 +536,10 @@ __global__ void __launch_bounds__(256)
     const int z = (int)((unsigned)v / ((unsigned)L * (unsigned)L));
     double h[5];
     helix_unit(c.pitch, z, h);
+    const f4 o4 = *(const f4*)(out + v * 16);   // channels 0-3 in one load
+    const float o[5] = {o4[0], o4[1], o4[2], o4[3], out[v * 16 + 4]};
     float d[5];
-    for (int k = 0; k < 5; k++) d[k] = (float)(c.q_amp * h[k]) + (float)c.q_eq * out[v * 16 + k] - Qt[k * V + v];
+    for (int k = 0; k < 5; k++) d[k] = (float)(c.q_amp * h[k]) + (float)c.q_eq * o[k] - Qt[k * V + v];
     const bool f = fluid[v] != 0;
     if (f) {
       const double xx = d[0], xy = d[1], xz = d[2], yy = d[3], yz = d[4];
@@ -551,13 +554,8 @@ __global__ void __launch_bounds__(256)
     *(u4*)(dz + v * 16) = u4{p0, p1, p2, 0u};
     *(u4*)(dz + v * 16 + 8) = u4{0u, 0u, 0u, 0u};
   }
-  s[threadIdx.x] = l2;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+  double lv[1] = {l2};
+  lc::block_sum<256, 1>(lv, sred, part + blockIdx.x);
 }
 
 // Q_warm = q_amp * helix + q_eq * dQ into a field [5][nsites] at offset off
