@@ -113,6 +113,32 @@ def test_chained_forward_and_warm_start(net):
     np.testing.assert_allclose(Q, 0.495 * qh + 0.5 * dq, atol=1e-6)
 
 
+def test_predict_matches_the_layer_chain(net):
+    """The inference forward (first layer computing its features in the
+    halo staging, 16-byte output rows) against the same network run layer
+    by layer through the single-layer calls (features read from the FP64
+    feature kernel, activations packed to BF16 from FP32 SiLU on the host):
+    they differ only where an FP32 versus FP64 feature or SiLU value falls
+    on the other side of a BF16 rounding."""
+    from paper_1102_2193_amd import nn
+    say("case: predict against the layer chain")
+    rng = np.random.default_rng(12)
+    for l in range(4):
+        W, b = rand_layer(rng, l)
+        net.set_layer(l, W * 0.5, b * 0.5)
+    c = nn.make_case((6.2, 9.0, 7.7), 4.0, 12.0, "planar", 0.495, 0.5)
+    dq = net.predict(c)
+    x = net.features(c)
+    for l in range(4):
+        z = net.layer_forward(l, x)
+        if l < 3:
+            zd = z.astype(np.float64)
+            x = (zd / (1.0 + np.exp(-zd))).astype(np.float32)
+    e = nrel(dq, z)
+    say("   predict vs layer chain rel err %.3e" % e)
+    assert e < 2e-3   # measured 3.1e-4
+
+
 def test_training_step_follows_gradient(net):
     from oracle import cnn
     from paper_1102_2193_amd import inputs, nn
