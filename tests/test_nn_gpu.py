@@ -5,7 +5,9 @@ accumulates in FP64; the kernels accumulate in FP32 on the matrix cores, so
 layer outputs and gradients agree to FP32 accumulation error (norm-relative
 1e-5), at 16^3 and at the training size 64^3.  A chained forward pass can
 differ by one bfloat16 rounding of an intermediate activation, so it is
-compared at 2e-2, and so are the losses of chained training steps; the loss
+compared at 2e-2 (the inference forward against the same network run layer
+by layer on the GPU at 2e-3), and so are the losses of chained training
+steps; the loss
 kernel alone is compared on the GPU's own network output (1e-6), and two
 Adam steps against the oracle's to 2% of the learning rate on the weights
 whose gradients stand far above Adam's epsilon.
