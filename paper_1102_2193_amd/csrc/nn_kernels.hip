@@ -1,14 +1,14 @@
 // nn_kernels.hip -- gfx950 kernels of the warm-start network (include/lc_nn.h).
 //
 // Activations are BF16, channels-last [voxel][C] with C padded to 16 or 32.
-// A 3x3x3 periodic convolution is an implicit GEMM: M = voxels of an
-// 8x8x4 tile, N = output channels, K = 27 taps x input channels.  Each
-// wave owns one z-layer of the tile (64 voxels = four 16-row M tiles) and
+// A 3x3x3 periodic convolution is an implicit GEMM over the voxels of an
+// 8x8x4 tile, the output channels and K = 27 taps x input channels.  Each
+// wave owns one z-layer of the tile (64 voxels = four blocks of 16) and
 // multiplies BF16 fragments on the matrix cores (v_mfma_f32_16x16x32_bf16,
-// FP32 accumulation; a 16-channel input takes two taps per instruction).  Fragment layout for a wave of 64 lanes: A[i][k] -> lane
-// i + 16*(k/KB), element k%KB; B[k][j] -> lane j + 16*(k/KB), element
-// k%KB (KB = K/4 consecutive k per lane); D[i][j] -> lane j + 16*(i/4),
-// element i%4.
+// FP32 accumulation; a 16-channel input takes two taps per instruction).
+// Fragment layout for a wave of 64 lanes: A[i][k] -> lane i + 16*(k/KB),
+// element k%KB; B[k][j] -> lane j + 16*(k/KB), element k%KB (KB = K/4
+// consecutive k per lane); D[i][j] -> lane j + 16*(i/4), element i%4.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
