@@ -233,11 +233,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     const int off = PAIR ? (hi ? tap_off(k == NK - 1 ? 26 : 2 * k + 1) : tap_off(2 * k)) : tap_off(k);
 #pragma unroll
     for (int nb = 0; nb < 4; nb++) {
-      const u4 xf = *(const u4*)(sa + off + 2 * nb * RS);
+      const u4 xv = *(const u4*)(sa + off + 2 * nb * RS);
 #pragma unroll
       for (int mb = 0; mb < NM; mb++)
         acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, wq[k % PF][mb]),
-                                                              __builtin_bit_cast(bf8, xf), acc[mb][nb], 0, 0, 0);
+                                                              __builtin_bit_cast(bf8, xv), acc[mb][nb], 0, 0, 0);
     }
     if (k + PF < NK) load_w(k + PF, wq[k % PF]);
   }
@@ -343,8 +343,13 @@ __global__ void __launch_bounds__(kWgThreads)
   // An item writes one 16-byte segment (eight voxels of one channel) per
   // channel and copy.
   constexpr int DO = COUT / 8, XO = CIN / 8;
-  constexpr int NXI = NROW * XO, NDI = (TV / TX) * DO;
-  static_assert(NXI + NDI <= kWgThreads && TX == 8, "one staging item per thread, 8-voxel rows");
+  // Item numbering: 16 consecutive threads take 16 consecutive rows of one
+  // octet, so that the 16 lanes of a 16-byte store write 16 consecutive
+  // chunks of one channel row (the halo's 60 rows padded to 64 items).
+  constexpr int NXI = 64 * XO, NDI = (TV / TX) * DO;
+  static_assert(NXI + NDI <= kWgThreads && TX == 8 && NROW <= 64, "one staging item per thread, 8-voxel rows");
+  auto xitem = [](int e, int& oc, int& row) { oc = (e / 16) % XO, row = e % 16 + 16 * (e / (16 * XO)); };
+  auto ditem = [](int e, int& oc, int& p8) { oc = (e / 16) % DO, p8 = e % 16 + 16 * (e / (16 * DO)); };
   // element k (0..7) of the octets of voxels v[0..7] as one 16-byte segment
   auto seg8 = [](const u4* v, int k) {
     const int d = k >> 1, sh = 16 * (k & 1);
@@ -360,16 +365,20 @@ __global__ void __launch_bounds__(kWgThreads)
   u4 tv[HX];
   auto load_items = [&](int tile) {
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-    if (tid < NXI) {
-      const int oc = tid % XO, row = tid / XO, hy = row % HY, hz = row / HY;
+    int oc, row;
+    xitem(tid, oc, row);
+    if (tid < NXI && row < NROW) {
+      const int hy = row % HY, hz = row / HY;
       const long long gyz = (long long)L * (wrap1(y0 - 1 + hy, L) + (long long)L * wrap1(z0 - 1 + hz, L));
 #pragma unroll
       for (int i = 0; i < HX; i++) tv[i] = *(const u4*)(x + (wrap1(x0 - 1 + i, L) + gyz) * CIN + 8 * oc);
-    } else if (tid < NXI + NDI) {
-      const int e = tid - NXI, oc = e % DO, p8 = e / DO, ly = p8 % TY, lz = p8 / TY;
+    } else if (tid >= NXI && tid < NXI + NDI) {
+      int dc, p8;
+      ditem(tid - NXI, dc, p8);
+      const int ly = p8 % TY, lz = p8 / TY;
       const long long gv = x0 + (long long)L * ((y0 + ly) + (long long)L * (z0 + lz));
 #pragma unroll
-      for (int j = 0; j < TX; j++) tv[j] = *(const u4*)(dz + (gv + j) * COUT + 8 * oc);
+      for (int j = 0; j < TX; j++) tv[j] = *(const u4*)(dz + (gv + j) * COUT + 8 * dc);
     }
   };
   const int tile_beg = (int)blockIdx.x * tpb, tile_end = min(tile_beg + tpb, ntile);
@@ -378,19 +387,18 @@ __global__ void __launch_bounds__(kWgThreads)
   // tile's loads stay in flight across them
   for (int tile = tile_beg; tile < tile_end; tile++) {
     lc::lds_sync();   // the previous tile's LDS reads are done
-    // the four lanes of a voxel write rows that meet in the same banks;
-    // rotating each item's channel order removes those conflicts but costs
-    // more in register rotations than it saves
-    if (tid < NXI) {
-      const int oc = tid % XO, row = tid / XO;
+    int oc, row;
+    xitem(tid, oc, row);
+    if (tid < NXI && row < NROW) {
 #pragma unroll
       for (int cp = 0; cp < 3; cp++)
 #pragma unroll
         for (int k = 0; k < 8; k++) *(u4*)(sxs + (cp * CIN + 8 * oc + k) * CSTR + row * 8) = seg8(tv + cp, k);
-    } else if (tid < NXI + NDI) {
-      const int e = tid - NXI, oc = e % DO, p8 = e / DO;
+    } else if (tid >= NXI && tid < NXI + NDI) {
+      int dc, p8;
+      ditem(tid - NXI, dc, p8);
 #pragma unroll
-      for (int k = 0; k < 8; k++) *(u4*)(sd + (8 * oc + k) * PS + 8 * p8) = seg8(tv, k);
+      for (int k = 0; k < 8; k++) *(u4*)(sd + (8 * dc + k) * PS + 8 * p8) = seg8(tv, k);
     }
     if (tile + 1 < tile_end) load_items(tile + 1);
     lc::lds_sync();
