@@ -187,3 +187,76 @@ def test_batch48_against_oracle_per_box():
             assert eF <= bound, (shape, b, eF, bound)
         say("   tile %s: worst rel err of Q and f over the 48 boxes %.3e" % (shape, worst))
         ctx.close()
+
+
+def _tiled_equal(big, small, rx, ry):
+    """big (nc, nz, ry ny, rx nx) equals small (nc, nz, ny, nx) repeated
+    rx times in x and ry times in y, bit for bit (plane chunk by chunk)."""
+    nc, nz, sy, sx = small.shape
+    b = big.reshape(nc, nz, ry, sy, rx, sx)
+    c = small.reshape(nc, nz, 1, sy, 1, sx)
+    return all(bool(np.array_equal(b[:, z0:z0 + 16], np.broadcast_to(c[:, z0:z0 + 16], b[:, z0:z0 + 16].shape)))
+               for z0 in range(0, nz, 16))
+
+
+def test_largest_marching_box_against_a_repeated_cell():
+    """The largest FP32 box the marching kernel takes: 384 x 384 x 383 sites,
+    whose 19 population components span 4,292,149,248 bytes, just under the
+    4 GiB that the kernel's 32-bit component offsets reach; one plane more
+    and the library refuses the marching shapes and defaults to the 3D tile.
+    The initial Q repeats with period 8 in x and y and there is no colloid,
+    so every site of the box must evolve as the same site of a 32 x 16 x 383
+    box with the same repeated start, on the same marching shape: Q, f and u
+    bit for bit (each site's arithmetic does not depend on how the planes
+    are split into work items), and that box against one oracle run of the
+    8 x 8 x 383 cell (the paper's parameters with pitch 32, tau = 0.8,
+    20 steps; Q and f to 1e-5, u to the bound below)."""
+    from oracle import lco
+    from paper_1102_2193_amd import lc
+    say("case: 384x384x383 fp32 (marching kernel at its 4 GiB offset limit), 20 steps vs 32x16x383 and an 8x8x383 oracle cell")
+    C, NZ, n = 8, 383, 20
+    prm = dict(PAPER, tau=0.8, q0=2 * math.pi / 32)
+    Qc = inputs.noisy_nematic_q(C, C, NZ, 0.5, seed=57, noise=0.02, director=(1, 0.2, 0.4))
+    ref = lco.Sim(C, C, NZ, **prm)
+    ref.set_Q(Qc)
+    ref.step(n)
+    cell = dict(Q=ref.get_Q(), f=ref.get_f(), u=ref.get_u())
+    del ref
+    ctx = lc.Context([dict(nx=32, ny=16, nz=NZ, precision="fp32", **prm)])
+    ctx.set_tile([t for t in range(ctx.num_tiles()) if tuple(ctx.tile_shape(t)) == (32, 16, 8)][0])
+    ctx.set_Q(0, np.tile(Qc, (1, 1, 2, 4)))
+    ctx.step(n)
+    small = dict(Q=ctx.get_Q(0), f=ctx.get_f(0), u=ctx.get_u(0))
+    ctx.close()
+    # u: each step's force density is a difference of FP32 stresses of size
+    # up to A0 S^2 = 0.25, rounded to 2^-24 relative, so after n steps u is
+    # off by at most about n 2^-24 0.25 in absolute terms
+    fluid = np.ones((NZ, 16, 32), dtype=bool)
+    umax = np.max(np.abs(cell["u"]))
+    for k, tol in (("Q", 1e-5), ("f", 1e-5), ("u", n * 2.0 ** -24 * 0.25 / umax)):
+        ref_k = np.tile(cell[k], (1, 1, 2, 4))
+        e = max(rel_inf(small[k], ref_k, fluid), rel_l2(small[k], ref_k, fluid))
+        say("   32x16x383 vs oracle: rel err %s %.3e (bound %.3e)" % (k, e, tol))
+        assert e < tol, (k, e)
+    assert umax > 1e-4   # the tilt and the noise drive a flow
+    L = 384
+    assert 19 * 4 * L * L * NZ < 2 ** 32 <= 19 * 4 * L * L * (NZ + 1)
+    ctx = lc.Context([dict(nx=L, ny=L, nz=NZ, precision="fp32", **prm)])
+    shape = ctx.tile_shape(ctx.get_tile())
+    nblk, _ = ctx.launch_info()
+    say("   default tile %s, %d blocks" % (shape, nblk))
+    assert tuple(shape) == (32, 16, 8)   # the marching kernel's default shape
+    ctx.set_Q(0, np.tile(Qc, (1, 1, L // C, L // C)))
+    ctx.step(n)
+    for k, get in (("Q", ctx.get_Q), ("f", ctx.get_f), ("u", ctx.get_u)):
+        same = _tiled_equal(get(0), small[k], L // 32, L // 16)
+        say("   384x384x383 %s equal to the repeated 32x16x383 box: %s" % (k, same))
+        assert same, k
+    ctx.close()
+    # one plane more: 19 x 4 x sites reaches 4 GiB
+    ctx = lc.Context([dict(nx=L, ny=L, nz=NZ + 1, precision="fp32", **prm)])
+    assert tuple(ctx.tile_shape(ctx.get_tile())) == (16, 8, 2)
+    march = [t for t in range(ctx.num_tiles()) if tuple(ctx.tile_shape(t)) == (32, 16, 8)][0]
+    with pytest.raises(lc.LCError, match="too large for the marching kernel"):
+        ctx.set_tile(march)
+    ctx.close()
