@@ -222,6 +222,30 @@ def test_every_shape_and_item_length_12cubed(builds, shape):
             assert lds <= LDS_BYTES, "FP32 %dx%d needs %d bytes of LDS" % (shape + (lds,))
 
 
+SMALL_COLLOID = dict(pos=(7.4, 0.3, 7.8), a0=2.0, anchoring="planar", W=0.05, S0=0.5)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d" % s)
+def test_smallest_boxes(builds, shape):
+    """The smallest boxes the library takes (edges of 8 sites), narrower than
+    every tile: 8^3 with the largest colloid that fits one (a = 2, planar,
+    chiral branch, centred next to the periodic corner, so that its
+    stencils wrap in all three directions), and a ragged 8 x 9 x 11 box
+    without colloid; FP64 and FP32, items of 1 and 2 planes."""
+    exe = builds[(shape, "asan")]
+    cases = [(L, col, prec, planes) for L, col in (((8, 8, 8), SMALL_COLLOID), ((8, 9, 11), None))
+             for prec in ("f64", "f32") for planes in (1, 2)]
+    states = [oracle_case(L, CHIRAL, col) for L, col, _, _ in cases]
+    with cf.ThreadPoolExecutor(4) as pool:
+        futs = [pool.submit(run_host, exe, st, CHIRAL, col, shape, prec, planes, 2)
+                for st, (L, col, prec, planes) in zip(states, cases)]
+        results = [f.result() for f in futs]
+    for st, res, (L, col, prec, planes) in zip(states, results, cases):
+        label = "%dx%d %s box %s planes=%d" % (shape + (prec, L, planes))
+        e = check_step(res, reference_after_step(st, col), col, prec, label)
+        print(label, " ".join("%s %.2e" % kv for kv in e.items()))
+
+
 @pytest.mark.parametrize("shape", [(16, 8), (64, 4), (32, 16)], ids=lambda s: "%dx%d" % s)
 def test_wrapping_box_moving_wall_nematic(builds, shape):
     """40 x 36 x 12 (several column blocks per axis, ragged in x and y) with a
