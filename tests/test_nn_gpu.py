@@ -3,7 +3,8 @@
 The oracle rounds the operands to bfloat16 exactly as the kernels do and
 accumulates in FP64; the kernels accumulate in FP32 on the matrix cores, so
 layer outputs and gradients agree to FP32 accumulation error (norm-relative
-1e-5), at 16^3 and at the training size 64^3.  A chained forward pass can
+1e-5), at 16^3, at the training size 64^3, at the smallest grid 8^3 and at
+56^3 (a last weight-gradient block with fewer tiles).  A chained forward pass can
 differ by one bfloat16 rounding of an intermediate activation, so it is
 compared at 2e-2 (the inference forward against the same network run layer
 by layer on the GPU at 2e-3), and so are the losses of chained training
@@ -203,6 +204,33 @@ def test_layer_forward_backward_64cubed(net64, l):
     e = (ez, nrel(dW, rdW), nrel(db, rdb), nrel(dx, rdx))
     say("   rel err z %.3e dW %.3e db %.3e dx %.3e" % e)
     assert max(e) < 1e-5
+
+
+@pytest.mark.parametrize("n", [8, 56])
+def test_layer_forward_backward_smallest_and_ragged_grids(n):
+    """8^3, the smallest grid the network takes: two convolution blocks,
+    every halo wrapping onto the block's own tile, two weight-gradient
+    blocks.  56^3: 686 weight-gradient tiles over 229 blocks of three, the
+    last block with two.  Every layer forward and backward, as at 64^3."""
+    from oracle import cnn
+    from paper_1102_2193_amd import nn
+    net = nn.Net(n, seed=9)
+    for l in range(4):
+        say("case: layer %d forward and backward at %d^3" % (l, n))
+        rng = np.random.default_rng(60 + l)
+        W, b = rand_layer(rng, l)
+        net.set_layer(l, W, b)
+        x = rng.normal(size=(nn.CIN[l], n, n, n)).astype(np.float32)
+        z = net.layer_forward(l, x)
+        xr, Wr = cnn.bf16_round(x), cnn.bf16_round(W)
+        ez = nrel(z, cnn.conv3d(xr, Wr, b.astype(np.float64)))
+        dz = rng.normal(size=(nn.COUT[l], n, n, n)).astype(np.float32)
+        dW, db, dx = net.layer_backward(l, x, dz)
+        rdx, rdW, rdb = cnn.conv3d_backward(xr, Wr, cnn.bf16_round(dz))
+        e = (ez, nrel(dW, rdW), nrel(db, rdb), nrel(dx, rdx))
+        say("   rel err z %.3e dW %.3e db %.3e dx %.3e" % e)
+        assert max(e) < 1e-5
+    net.close()
 
 
 def _two_step_case(L, seed):
