@@ -9,8 +9,8 @@
   to 1e-5 on Q and f, 1e-3 on the force, and element by element on the
   deviations from rest f - w and on u (bound below).
 * The 128^3 drag workload for 100 steps, the 128^3 cholesteric workload
-  with the a = 16 colloid, and the 48-box batch against one oracle run per
-  box.
+  with the a = 16 colloid, the 256^3 nematic workload, and the 48-box batch
+  against one oracle run per box; the largest box the marching kernel takes.
 
 FP32 bound on f - w and u, element by element relative to the largest
 reference value over fluid sites: each step rounds u = (j + F/2)/rho and
@@ -139,6 +139,40 @@ def test_full_size_cholesteric128_a16():
     r = run_pair((L, L, L), prm, n, "fp32", colloid=col, Q0=Q0, hist=True)
     check(r, 1e-5, 1e-5, tol_force=1e-3)
     check_dev(r, fp32_dev_bound(n))
+
+
+def test_full_size_nematic256():
+    """The 256^3 workload (nematic, a = 16 normal colloid with W = 0.01 at the
+    centre, the benchmark's inputs) on the 64 x 8 marching tile the tuner
+    picks at this size and on the default 32 x 16, 10 steps against one
+    oracle run."""
+    from oracle import lco
+    from paper_1102_2193_amd import lc
+    say("case: 256^3 fp32 nematic workload, a = 16, 10 steps vs oracle, tiles 64x8 and 32x16")
+    L, n = 256, 10
+    c = (L / 2,) * 3
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=2)
+    ref = lco.Sim(L, **inputs.NEMATIC)
+    ref.set_colloid(c, 16.0, anchoring=ANCH["normal"], W=0.01, S0=0.5)
+    ref.set_Q(Q0)
+    hr = []
+    for _ in range(n):
+        ref.step(1)
+        hr.append(ref.force())
+    base = dict(Qr=ref.get_Q(), fr=ref.get_f(), ur=ref.get_u(), Hr=np.array(hr), fluid=~ref.solid())
+    del ref
+    say("   oracle done")
+    for shape in ((64, 8, 8), (32, 16, 8)):
+        ctx = lc.Context([dict(nx=L, precision="fp32", **inputs.NEMATIC)])
+        ctx.set_tile([t for t in range(ctx.num_tiles()) if tuple(ctx.tile_shape(t)) == shape][0])
+        ctx.set_colloid(0, c, 16.0, anchoring="normal", W=0.01, S0=0.5)
+        ctx.set_Q(0, Q0)
+        ctx.step(n)
+        say("  tile %s" % (shape,))
+        r = dict(base, Q=ctx.get_Q(0), f=ctx.get_f(0), u=ctx.get_u(0), H=ctx.force_history(0, n))
+        check(r, 1e-5, 1e-5, tol_force=1e-3)
+        check_dev(r, fp32_dev_bound(n))
+        ctx.close()
 
 
 def test_batch48_against_oracle_per_box():
