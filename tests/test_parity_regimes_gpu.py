@@ -8,7 +8,8 @@
   paper's fixed Q^0), a fixed and a free colloid.  FP64 to round-off; FP32
   to 1e-5 on Q and f, 1e-3 on the force, and element by element on the
   deviations from rest f - w and on u (bound below).
-* The 128^3 drag workload for 100 steps, the 128^3 cholesteric workload
+* The 128^3 drag workload for 100 steps (along x on every tile, along z on
+  the default one), the 128^3 cholesteric workload
   with the a = 16 colloid, the 256^3 nematic workload, and the 48-box batch
   against one oracle run per box; the largest box the marching kernel takes.
 
@@ -127,6 +128,39 @@ def test_full_size_drag128_100_steps_every_tile():
         np.testing.assert_array_equal(np.array(ctx.get_colloid(0).pos), pos_ref)
         ctx.close()
         t += 1
+
+
+def test_full_size_drag128_along_z():
+    """The drag workload's second leg: the same colloid dragged along z, the
+    direction the marching kernel sweeps its planes, so the planes with
+    solid nodes move through the planned work items; the default tile and
+    graph replay, 100 steps against one oracle run."""
+    from oracle import lco
+    from paper_1102_2193_amd import lc
+    say("case: 128^3 fp32 drag workload along z, 100 steps vs oracle")
+    L, n = 128, 100
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=2)
+    col = dict(pos=(64.0, 64.0, 64.0), a0=8.0, anchoring="normal", W=0.01, S0=0.5, vel=(0, 0, 1e-3))
+    ref = lco.Sim(L, **inputs.NEMATIC)
+    ref.set_colloid(col["pos"], col["a0"], anchoring=ANCH["normal"], W=0.01, S0=0.5, vel=col["vel"],
+                    motion=lco.PRESCRIBED)
+    ref.set_Q(Q0)
+    hr = []
+    for _ in range(n):
+        ref.step(1)
+        hr.append(ref.force())
+    ctx = lc.Context([dict(nx=L, precision="fp32", **inputs.NEMATIC)])
+    ctx.set_colloid(0, col["pos"], col["a0"], anchoring="normal", W=0.01, S0=0.5, vel=col["vel"],
+                    motion=lc.PRESCRIBED)
+    ctx.set_Q(0, Q0)
+    ctx.step(n)
+    say("  tile %s" % (ctx.tile_shape(ctx.get_tile()),))
+    r = dict(Q=ctx.get_Q(0), f=ctx.get_f(0), u=ctx.get_u(0), H=ctx.force_history(0, n), Qr=ref.get_Q(),
+             fr=ref.get_f(), ur=ref.get_u(), Hr=np.array(hr), fluid=~ref.solid())
+    check(r, 1e-5, 1e-5, tol_force=1e-3)
+    check_dev(r, fp32_dev_bound(n))
+    np.testing.assert_array_equal(np.array(ctx.get_colloid(0).pos), np.array(ref.get_colloid().pos))
+    ctx.close()
 
 
 def test_full_size_cholesteric128_a16():
