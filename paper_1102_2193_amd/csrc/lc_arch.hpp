@@ -61,9 +61,10 @@ struct FieldBuf {
 };
 
 // Element `off` of LDS component [lo, lo + n) of an array: the reads made
-// through the pointer stay within that component.
+// through the pointer stay within that component (n is checked only by the
+// host version of this layer).
 template <typename T, int N>
-__device__ inline const T* lds_at(const T (&row)[N], int lo, int n, int off) {
+__device__ inline const T* lds_at(const T (&row)[N], int lo, [[maybe_unused]] int n, int off) {
   return row + lo + off;
 }
 

@@ -1135,7 +1135,7 @@ __global__ void __launch_bounds__(256)
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_fill_f(R* f, long long NS, const double* rho0_site_unused, double rho0) {
+__global__ void __launch_bounds__(256) k_fill_f(R* f, long long NS, double rho0) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= NS) return;
 #pragma unroll
@@ -1252,7 +1252,7 @@ hipError_t launch_solid(const BoxDev* boxes, const ColDev* cols, int box, long l
 
 template <typename R>
 hipError_t launch_fill(R* f, long long NS, double rho0, hipStream_t s) {
-  k_fill_f<R><<<(unsigned)((NS + 255) / 256), 256, 0, s>>>(f, NS, nullptr, rho0);
+  k_fill_f<R><<<(unsigned)((NS + 255) / 256), 256, 0, s>>>(f, NS, rho0);
   return hipGetLastError();
 }
 

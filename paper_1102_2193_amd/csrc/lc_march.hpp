@@ -96,7 +96,6 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   const int gx = x0 + lx, gy = y0 + ly;
   const bool incol = gx < nx && gy < ny;
 
-  auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
   auto wrapn = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
 
   // this thread's elements of a halo plane: 2D offsets computed once
@@ -300,7 +299,7 @@ __device__ __forceinline__ void march_tile(const BoxDev& B, const int2 tt, const
   int qs_m1 = 1, qs_0 = 2, qs_p1 = 3, qs_p2 = 4, qs_free = 0;  // slots of planes k-1..k+2, k+3
   int us_m1 = 0, us_0 = 1, us_p1 = 2, us_free = 3;
   int ps_0 = 0;
-  const int lane = tid & 63, wv = tid >> 6;
+  const int wv = tid >> 6;
 
   for (int k = z0; k < zend; k++) {
     const int gi = (k - z0) / kGroup;

@@ -156,8 +156,8 @@ int num_tiles(const lc_ctx* c) { return c->prec == LC_FP32 ? kNumF32 : kNumF64; 
 long long box_sites(const lc_params& p) { return (long long)p.nx * p.ny * p.nz; }
 
 void destroy_graph(lc_ctx* c) {
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   c->gexec = nullptr;
   c->graph = nullptr;
   c->graph_ok = false;
@@ -465,7 +465,7 @@ int resize_colloid_arrays(lc_ctx* c, const std::vector<int>& base, int total) {
   int* pend = nullptr;
   const size_t hrow = (size_t)kHistCap * 12;
   auto bail = [&](hipError_t e) {
-    hipFree(force); hipFree(hist); hipFree(fsum); hipFree(count); hipFree(pend);
+    for (void* p : {(void*)force, (void*)hist, (void*)fsum, (void*)count, (void*)pend}) (void)hipFree(p);
     return fail(c, LC_ENOMEM, std::string("per-colloid arrays: ") + hipGetErrorString(e));
   };
   hipError_t e = hipMalloc(&force, sizeof(double) * 12 * cap);
@@ -496,7 +496,11 @@ int resize_colloid_arrays(lc_ctx* c, const std::vector<int>& base, int total) {
     }
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  hipFree(c->dforce); hipFree(c->dhist); hipFree(c->dfsum); hipFree(c->dcount); hipFree(c->dpending);
+  (void)hipFree(c->dforce);
+  (void)hipFree(c->dhist);
+  (void)hipFree(c->dfsum);
+  (void)hipFree(c->dcount);
+  (void)hipFree(c->dpending);
   c->dforce = force; c->dhist = hist; c->dfsum = fsum; c->dcount = count; c->dpending = pend;
   c->col_cap = cap;
   return LC_OK;
@@ -625,9 +629,9 @@ int layout(lc_ctx* c) {
       if (s < nt) order[i] = tiles[s];
     }
   }
-  if (c->dtiles) hipFree(c->dtiles);
-  if (c->doffs) hipFree(c->doffs);
-  if (c->dpart) hipFree(c->dpart);
+  if (c->dtiles) (void)hipFree(c->dtiles);
+  if (c->doffs) (void)hipFree(c->doffs);
+  if (c->dpart) (void)hipFree(c->dpart);
   c->dtiles = nullptr;
   c->doffs = nullptr;
   c->dpart = nullptr;
@@ -639,8 +643,8 @@ int layout(lc_ctx* c) {
   HIPCHK(c, hipMalloc(&c->dpart, sizeof(double) * 12 * c->nslot));
   HIPCHK(c, hipMemsetAsync(c->dpart, 0, sizeof(double) * 12 * c->nslot, c->stream));
   if ((size_t)pblk * 24 > c->dbpart_cap) {
-    if (c->dbpart) hipFree(c->dbpart);
-    if (c->dpostmap) hipFree(c->dpostmap);
+    if (c->dbpart) (void)hipFree(c->dbpart);
+    if (c->dpostmap) (void)hipFree(c->dpostmap);
     c->dbpart = nullptr;
     c->dpostmap = nullptr;
     c->dbpart_cap = std::max<size_t>(24, (size_t)pblk * 24);
@@ -657,7 +661,7 @@ int layout(lc_ctx* c) {
   // the colloid table (a zeroed entry when there is none: the marching
   // kernel reads entry 0 of a box without colloids but uses nothing of it)
   if ((size_t)std::max(1, total) > c->dcol_cap) {
-    if (c->dcol) hipFree(c->dcol);
+    if (c->dcol) (void)hipFree(c->dcol);
     c->dcol = nullptr;
     c->dcol_cap = (size_t)std::max(1, total);
     HIPCHK(c, hipMalloc(&c->dcol, sizeof(ColDev) * c->dcol_cap));
@@ -742,7 +746,7 @@ int build_graph(lc_ctx* c) {
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->stream, &g);
   if (e != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return fail(c, LC_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   }
   HIPCHK(c, e2);
@@ -980,10 +984,13 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
       c->scratch_err = std::string("device / static scratch address: ") + hipGetErrorString(e);
     }
   }
-  hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream);
-  for (int k = 0; k < 2; k++) {
-    hipMemsetAsync(c->Q[k], 0, nq, c->stream);
-    hipMemsetAsync(c->u[k], 0, nu, c->stream);
+  {
+    hipError_t e = hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; k++) {
+      e = hipMemsetAsync(c->Q[k], 0, nq, c->stream);
+      if (e == hipSuccess) e = hipMemsetAsync(c->u[k], 0, nu, c->stream);
+    }
+    if (e != hipSuccess) return bail(LC_EDEVICE, std::string("init: ") + hipGetErrorString(e));
   }
   // f = w_i rho0 everywhere (stored shifted by w_i)
   for (int k = 0; k < 2; k++) {
@@ -1026,19 +1033,19 @@ int lc_create_batch(int nbox, const lc_params* p, void* hip_stream, lc_ctx** out
 
 void lc_destroy(lc_ctx* c) {
   if (!c) return;
-  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   destroy_graph(c);
   if (c->own_buf)
     for (int k = 0; k < 2; k++) {
-      if (c->f[k]) hipFree(c->f[k]);
-      if (c->Q[k]) hipFree(c->Q[k]);
-      if (c->u[k]) hipFree(c->u[k]);
+      if (c->f[k]) (void)hipFree(c->f[k]);
+      if (c->Q[k]) (void)hipFree(c->Q[k]);
+      if (c->u[k]) (void)hipFree(c->u[k]);
     }
   void* bufs[] = {c->dbox,  c->dtiles, c->doffs, c->dpart,  c->dbpart, c->dpending, c->dfsum,
                   c->dforce, c->dhist,  c->dcount, c->dflag,  c->ddiag,  c->dcol, c->dpostmap};
   for (void* b : bufs)
-    if (b) hipFree(b);
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    if (b) (void)hipFree(b);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -1070,9 +1077,9 @@ int lc_bind_buffers(lc_ctx* c, void* f0, void* f1, void* Q0, void* Q1, void* u0,
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->own_buf)
     for (int k = 0; k < 2; k++) {
-      hipFree(c->f[k]);
-      hipFree(c->Q[k]);
-      hipFree(c->u[k]);
+      (void)hipFree(c->f[k]);
+      (void)hipFree(c->Q[k]);
+      (void)hipFree(c->u[k]);
     }
   for (int k = 0; k < 2; k++) {
     c->f[k] = nf[k];
@@ -1471,7 +1478,7 @@ int lc_get_solid(lc_ctx* c, int box, unsigned char* id) {
   hipError_t e = lc::launch_solid(c->dbox, c->dcol, box, n, d, c->cur, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(id, d, n, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  hipFree(d);
+  (void)hipFree(d);
   HIPCHK(c, e);
   return LC_OK;
 }
@@ -1484,24 +1491,24 @@ int lc_get_diag(lc_ctx* c, int box, lc_diag* out) {
   const long long n = box_sites(c->prm[box]);
   const long long nb = (n + 255) / 256;
   if ((size_t)(6 * nb) > c->ddiag_cap) {
-    if (c->ddiag) hipFree(c->ddiag);
+    if (c->ddiag) (void)hipFree(c->ddiag);
     c->ddiag = nullptr;
     c->ddiag_cap = 6 * nb;
     HIPCHK(c, hipMalloc(&c->ddiag, sizeof(double) * c->ddiag_cap));
   }
-  hipError_t e;
+  hipError_t e = hipSuccess;
   if (c->prec == LC_FP32) {
     lc::StepPtrs<float> a = ptrs<float>(c, c->cur);
     if (c->any_colloid)
-      lc::launch_ghost<float>(c->dbox, c->dcol, c->ncol, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->cur,
-                              c->stream);
-    e = lc::launch_diag<float>(c->dbox, box, n, a, c->ddiag, c->stream);
+      e = lc::launch_ghost<float>(c->dbox, c->dcol, c->ncol, c->ghost_total, (float*)c->Q[c->cur], c->nsites, c->cur,
+                                  c->stream);
+    if (e == hipSuccess) e = lc::launch_diag<float>(c->dbox, box, n, a, c->ddiag, c->stream);
   } else {
     lc::StepPtrs<double> a = ptrs<double>(c, c->cur);
     if (c->any_colloid)
-      lc::launch_ghost<double>(c->dbox, c->dcol, c->ncol, c->ghost_total, (double*)c->Q[c->cur], c->nsites, c->cur,
-                               c->stream);
-    e = lc::launch_diag<double>(c->dbox, box, n, a, c->ddiag, c->stream);
+      e = lc::launch_ghost<double>(c->dbox, c->dcol, c->ncol, c->ghost_total, (double*)c->Q[c->cur], c->nsites,
+                                   c->cur, c->stream);
+    if (e == hipSuccess) e = lc::launch_diag<double>(c->dbox, box, n, a, c->ddiag, c->stream);
   }
   HIPCHK(c, e);
   std::vector<double> h((size_t)(6 * nb));
@@ -1565,23 +1572,24 @@ int lc_defects(lc_ctx* c, int box, double threshold, unsigned char* mask, long* 
   unsigned long long* dc = nullptr;
   HIPCHK(c, hipMalloc(&dm, n));
   if (hipMalloc(&dc, sizeof(unsigned long long)) != hipSuccess) {
-    hipFree(dm);
+    (void)hipFree(dm);
     return fail(c, LC_ENOMEM, "hipMalloc failed");
   }
-  hipMemsetAsync(dc, 0, sizeof(unsigned long long), c->stream);
-  hipError_t e = c->prec == LC_FP32
-                     ? lc::launch_defects<float>(c->dbox, c->dcol, box, n, (const float*)c->Q[c->cur], c->nsites,
-                                                 threshold, dm, dc, c->cur, c->stream)
-                     : lc::launch_defects<double>(c->dbox, c->dcol, box, n, (const double*)c->Q[c->cur], c->nsites,
-                                                  threshold, dm, dc, c->cur, c->stream);
+  hipError_t e = hipMemsetAsync(dc, 0, sizeof(unsigned long long), c->stream);
+  if (e == hipSuccess)
+    e = c->prec == LC_FP32
+            ? lc::launch_defects<float>(c->dbox, c->dcol, box, n, (const float*)c->Q[c->cur], c->nsites, threshold,
+                                        dm, dc, c->cur, c->stream)
+            : lc::launch_defects<double>(c->dbox, c->dcol, box, n, (const double*)c->Q[c->cur], c->nsites, threshold,
+                                         dm, dc, c->cur, c->stream);
   unsigned long long cnt = 0;
   if (e == hipSuccess) {
     if (mask) e = hipMemcpyAsync(mask, dm, n, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&cnt, dc, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   }
-  hipFree(dm);
-  hipFree(dc);
+  (void)hipFree(dm);
+  (void)hipFree(dc);
   HIPCHK(c, e);
   if (count_out) *count_out = (long)cnt;
   return LC_OK;
@@ -1661,7 +1669,7 @@ int lc_time_kernel(lc_ctx* c, int nsteps, double out[3]) {
   }
   float tot = 0.f;
   HIPCHK(c, hipEventElapsedTime(&tot, ev[2 * nt], ev[2 * nt + 1]));
-  for (auto& e : ev) hipEventDestroy(e);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   out[0] = ks / nt;
   out[1] = tot / nsteps;
   out[2] = tot;

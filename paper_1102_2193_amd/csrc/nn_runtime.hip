@@ -192,7 +192,7 @@ int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out) 
   bool ok = true;
   auto dmalloc = [&](void** p, size_t sz) {
     if (ok && hipMalloc(p, sz) != hipSuccess) ok = false;
-    if (ok) hipMemsetAsync(*p, 0, sz, n->stream);
+    if (ok && hipMemsetAsync(*p, 0, sz, n->stream) != hipSuccess) ok = false;
   };
   for (int l = 0; l < NL; l++) {
     const size_t nw = (size_t)COUT[l] * CIN[l] * 27;
@@ -245,17 +245,17 @@ int lc_nn_create(int L, unsigned long long seed, void* hip_stream, lc_nn** out) 
 
 void lc_nn_destroy(lc_nn* n) {
   if (!n) return;
-  if (n->stream) hipStreamSynchronize(n->stream);
+  if (n->stream) (void)hipStreamSynchronize(n->stream);
   for (int l = 0; l < NL; l++) {
     void* p[] = {n->W[l], n->b[l], n->mW[l], n->vW[l], n->mb[l], n->vb[l], n->dW[l], n->db[l], n->wf[l], n->wb[l]};
     for (void* q : p)
-      if (q) hipFree(q);
+      if (q) (void)hipFree(q);
   }
   void* q[] = {n->x0, n->z[0], n->z[1], n->z[2], n->a[0], n->a[1], n->a[2], n->g[0], n->g[1], n->g[2], n->out,
                n->g4, n->wpart, n->lpart, n->Qt, n->fluid, n->tmpf, n->tmph, n->tmph2};
   for (void* p : q)
-    if (p) hipFree(p);
-  if (n->own_stream && n->stream) hipStreamDestroy(n->stream);
+    if (p) (void)hipFree(p);
+  if (n->own_stream && n->stream) (void)hipStreamDestroy(n->stream);
   delete n;
 }
 
@@ -469,9 +469,9 @@ int lc_nn_time(lc_nn* n, const lc_nn_case* c, const double* Q_target, const unsi
   float t1 = 0.f, t2 = 0.f;
   NNCHK(n, hipEventElapsedTime(&t1, e0, e1));
   NNCHK(n, hipEventElapsedTime(&t2, e1, e2));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipEventDestroy(e2);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
   out[0] = t1 / reps;
   out[1] = t2 / reps;
   return LC_OK;
