@@ -1389,6 +1389,9 @@ int lc_step(lc_ctx* c, int nsteps) {
       c->nstep += kGraphSteps;
       left -= kGraphSteps;
     }
+    // the replayed graph's last step is finished by the next step or, for
+    // the getters, by flush (the flag is set on the host, not by the capture)
+    c->maybe_pending = true;
   }
   while (left > 0)
     if ((rc = eager()) != LC_OK) return rc;

@@ -324,6 +324,40 @@ def test_graph_replay_equals_eager():
         np.testing.assert_array_equal(a, b)
 
 
+def test_graph_replays_with_eager_work_between():
+    """Four replays of the 16-step graph, each followed on the same stream by
+    host reads and the eager diagnostics kernels (anchoring pass and sums);
+    after every replay the state, the force, the force history and the
+    diagnostics equal, bit for bit, those of eager stepping with the same
+    work between.  (The getters finish the last step of a run; a run ending
+    on a graph replay after an earlier read once left it unfinished, so the
+    force was a step old and the history a step short.)"""
+    from paper_1102_2193_amd import lc
+    say("case: graph replays with eager work between, 24^3 fp32, 4 x 16 steps")
+    L = 24
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=19)
+    runs = []
+    for g in (False, True):
+        ctx = lc.Context([dict(nx=L, precision="fp32", **NEM)])
+        ctx.use_graph(g)
+        ctx.set_colloid(0, (11.6, 12.3, 12.1), 4.0, anchoring="planar", W=0.02, vel=(1.5e-2, -5e-3, 0),
+                        motion=lc.PRESCRIBED)
+        ctx.set_Q(0, Q0)
+        snaps = []
+        for r in range(4):
+            ctx.step(16)
+            d = ctx.diag(0)
+            snaps.append([ctx.get_Q(0), ctx.get_f(0), ctx.get_u(0), ctx.force(0), ctx.force_history(0, 16 * (r + 1)),
+                          np.array([d["free_energy"], d["mass"], d["umax"], *d["momentum"]]),
+                          np.array(ctx.get_colloid(0).pos)])
+        runs.append(snaps)
+        ctx.close()
+    for r, (a, b) in enumerate(zip(*runs)):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+        say("   replay %d equal to eager" % (r + 1))
+
+
 def test_diag_and_defects_match_oracle():
     say("case: diag/defects 24^3 fp64 cholesteric")
     L = 24
