@@ -73,6 +73,34 @@ def test_fp32_moving_colloid_continues_bit_for_bit():
     b.close()
 
 
+def test_state_saved_right_after_graph_replays():
+    """A state saved when the last steps ran as graph replays (16, a read of
+    the force, 16 more): the restored context continues exactly as the
+    original, whose last replayed step is still to be finished."""
+    from paper_1102_2193_amd import lc
+    say("case: checkpoint 24^3 fp32 after two graph replays with a read between, continue 16")
+    L = 24
+    box = [dict(nx=L, precision="fp32", **NEM)]
+    a = lc.Context(box)
+    a.set_colloid(0, (11.7, 12.2, 12.4), 4.0, anchoring="planar", W=0.02, vel=(0.02, -0.01, 0.005),
+                  motion=lc.PRESCRIBED)
+    a.set_Q(0, inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=31, noise=0.01))
+    a.step(16)
+    f16 = a.force(0)
+    a.step(16)
+    state = a.get_state()
+    np.testing.assert_array_equal(a.force_history(0, 32)[15], f16)
+    a.step(16)
+    ref = snapshot(a, 1, 48)
+    b = lc.Context(box)
+    b.set_state(state)
+    assert b.nstep == 32
+    b.step(16)
+    assert_same(snapshot(b, 1, 48), ref)
+    a.close()
+    b.close()
+
+
 def test_fp64_batch_continues_bit_for_bit(tmp_path):
     from paper_1102_2193_amd import lc
     say("case: checkpoint fp64 batch (16^3 with a fixed colloid, 20x16x24 without), file round trip")
