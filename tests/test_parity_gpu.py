@@ -358,6 +358,38 @@ def test_graph_replays_with_eager_work_between():
         say("   replay %d equal to eager" % (r + 1))
 
 
+def test_graph_rebuilt_after_the_host_changes_the_setup():
+    """Graph replays, then the host moves the colloid to another place (a new
+    work layout), changes the tile shape and writes a new Q; the replays that
+    follow equal eager stepping through the same changes, bit for bit."""
+    from paper_1102_2193_amd import lc
+    say("case: graph replays around set_colloid / set_tile / set_Q, 32^3 fp32")
+    L = 32
+    Q0 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=23)
+    Q1 = inputs.noisy_nematic_q(L, L, L, inputs.Q_INIT, seed=24, director=(1, 0, 0))
+    runs = []
+    for g in (False, True):
+        ctx = lc.Context([dict(nx=L, precision="fp32", **NEM)])
+        ctx.use_graph(g)
+        march = [t for t in range(ctx.num_tiles()) if tuple(ctx.tile_shape(t)) == (64, 8, 8)][0]
+        ctx.set_colloid(0, (10.4, 12.2, 15.9), 4.0, anchoring="normal", W=0.01, vel=(0.01, 0, 0),
+                        motion=lc.PRESCRIBED)
+        ctx.set_Q(0, Q0)
+        ctx.step(32)
+        ctx.set_colloid(0, (22.3, 20.6, 8.1), 5.0, anchoring="planar", W=0.02, vel=(0, 0.01, -0.01),
+                        motion=lc.PRESCRIBED)
+        ctx.step(16)
+        ctx.set_tile(march)
+        ctx.step(16)
+        ctx.set_Q(0, Q1)
+        ctx.step(32)
+        runs.append([ctx.get_Q(0), ctx.get_f(0), ctx.get_u(0), ctx.force(0), ctx.force_history(0, 48),
+                     np.array(ctx.get_colloid(0).pos)])
+        ctx.close()
+    for x, y in zip(*runs):
+        np.testing.assert_array_equal(x, y)
+
+
 def test_diag_and_defects_match_oracle():
     say("case: diag/defects 24^3 fp64 cholesteric")
     L = 24
